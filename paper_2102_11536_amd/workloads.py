@@ -1,0 +1,140 @@
+"""Seeded synthetic workloads: geometry control points and initial data.
+
+This module is shared by the HIP path and the CPU oracle and holds none of the
+method's arithmetic (no basis evaluation, quadrature, operators, solves or time
+stepping); it only builds input arrays.  Recipes:
+
+* Control points are a map evaluated at the Greville abscissae (knot averages)
+  of the open uniform knot vector.  For the identity map this reproduces the
+  identity exactly (linear precision of B-splines); for the deformed cube
+  x_c = xi_c + a sin(pi xi_{c+1}) sin(pi xi_{c+2}) (cyclic c) it gives a spline
+  approximation of that map with det J > 0.
+* Gaussian random field (GRF) initial displacement on the free coefficient
+  grid: separable squared-exponential covariance with correlation length ell
+  at the free Greville abscissae, sampled as (L_z x L_y x L_x) g with
+  L = V sqrt(Lambda) from eigh of the 1-D covariance and g ~ N(0, 1) from
+  numpy's PCG64 seeded generator, tapered by prod sin(pi x_a) and scaled to
+  RMS 1.
+* The 2-D standing wave u0 = sin(pi x) sin(pi y) is sampled at the Greville
+  abscissae of the free coefficients.
+"""
+import numpy as np
+
+
+def greville(n, p):
+    """Greville abscissae of the open uniform knot vector with n elements and
+    degree p (length n + p)."""
+    kn = np.concatenate([np.zeros(p + 1), np.arange(1, n) / n, np.ones(p + 1)])
+    m = n + p
+    if p == 0:
+        return 0.5 * (kn[:m] + kn[1:m + 1])
+    return np.array([kn[i + 1:i + p + 1].mean() for i in range(m)])
+
+
+def _grid(axes):
+    """Tensor grid of 1-D coordinate arrays (axis order x, y[, z]) as [N, d]
+    in co-lex order (x fastest)."""
+    mesh = np.meshgrid(*axes[::-1], indexing="ij")  # z, y, x
+    return np.stack([mesh[::-1][a].ravel() for a in range(len(axes))], axis=1)
+
+
+def _ns(n, dim):
+    return (int(n),) * dim if np.isscalar(n) else tuple(int(v) for v in n)
+
+
+def identity_ctrl(n, p, dim):
+    ns = _ns(n, dim)
+    return _grid([greville(v, p) for v in ns])
+
+
+def deformed_cube_ctrl(n, p, amp=0.1, dim=3):
+    ns = _ns(n, dim)
+    g = identity_ctrl(ns, p, dim)
+    out = g.copy()
+    s = np.sin(np.pi * g)
+    for c in range(dim):
+        prod = np.ones(len(g))
+        for o in range(1, dim):
+            prod = prod * s[:, (c + o) % dim]
+        out[:, c] = g[:, c] + amp * prod
+    return out
+
+
+def smooth_random_ctrl(n, p, seed, amp=0.06, dim=3):
+    """Seeded smooth map: identity plus, per coordinate, two products of sines
+    with random integer frequencies (1 or 2) and random amplitudes."""
+    ns = _ns(n, dim)
+    rng = np.random.default_rng(seed)
+    g = identity_ctrl(ns, p, dim)
+    out = g.copy()
+    for c in range(dim):
+        for _ in range(2):
+            fr = rng.integers(1, 3, size=dim)
+            a = amp * rng.uniform(-1.0, 1.0)
+            prod = np.ones(len(g))
+            for o in range(dim):
+                if o != c:
+                    prod = prod * np.sin(np.pi * fr[o] * g[:, o])
+            out[:, c] += a * prod
+    return out
+
+
+def grf(n, p, seed, ell=0.1, dim=3):
+    """Seeded GRF on the free coefficient grid, shape [N_free] co-lex."""
+    ns = _ns(n, dim)
+    rng = np.random.default_rng(seed)
+    axes = [greville(v, p)[1:-1] for v in ns]
+    Ls = []
+    for x in axes:
+        C = np.exp(-0.5 * ((x[:, None] - x[None, :]) / ell) ** 2)
+        lam, V = np.linalg.eigh(C)
+        Ls.append(V * np.sqrt(np.clip(lam, 0.0, None))[None, :])
+    g = rng.standard_normal(tuple(len(x) for x in axes[::-1]))  # [z, y, x]
+    for a in range(dim):
+        ax = dim - 1 - a
+        g = np.moveaxis(np.tensordot(Ls[a], g, axes=([1], [ax])), 0, ax)
+    taper = np.ones(1)
+    for x in axes:
+        taper = np.kron(np.sin(np.pi * x), taper)
+    u = g.ravel() * taper
+    return u / np.sqrt(np.mean(u * u))
+
+
+def standing_wave_u0(n, p):
+    """sin(pi x) sin(pi y) at the free Greville abscissae (2-D)."""
+    ns = _ns(n, 2)
+    axes = [greville(v, p)[1:-1] for v in ns]
+    pts = _grid(axes)
+    return np.sin(np.pi * pts[:, 0]) * np.sin(np.pi * pts[:, 1])
+
+
+# Workload presets (sizes and seeds).  tau is set from the stability limit by
+# the caller (0.5 of the critical step).
+PRESETS = {
+    "wave2d_p2_n32_k1": dict(dim=2, n=32, p=2, k=1, rho=0.5, steps=200,
+                             geometry="identity", init="standing_wave"),
+    "cube_p3_n64_k2": dict(dim=3, n=64, p=3, k=2, rho=0.5, steps=100, rtol=1e-10,
+                           geometry="deformed", init="grf", seed=0),
+    "cube_p4_n128_k3": dict(dim=3, n=128, p=4, k=3, rho=0.5, steps=100,
+                            geometry="deformed", init="grf", seed=1),
+    "cube_p3_n128_k2": dict(dim=3, n=128, p=3, k=2, rho=0.5, steps=100, rtol=1e-10,
+                            geometry="deformed", init="grf", seed=2000),
+}
+
+
+def make_geometry(dim, n, p, geometry, seed=None):
+    if geometry == "identity":
+        return identity_ctrl(n, p, dim)
+    if geometry == "deformed":
+        return deformed_cube_ctrl(n, p, dim=dim)
+    if geometry == "random":
+        return smooth_random_ctrl(n, p, seed, dim=dim)
+    raise ValueError(geometry)
+
+
+def make_initial(dim, n, p, init, seed=0):
+    if init == "standing_wave":
+        return standing_wave_u0(n, p)
+    if init == "grf":
+        return grf(n, p, seed, dim=dim)
+    raise ValueError(init)
