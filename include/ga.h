@@ -1,0 +1,161 @@
+/*
+ * ga.h -- C ABI of the MI355X hot path of the explicit order-2k
+ * generalized-alpha method for isogeometric structural dynamics with
+ * Kronecker-preconditioned conjugate-gradient mass solves.
+ *
+ * Problem (Sec. 2, eqs. pde and mp): M U'' + K U = 0 with homogeneous
+ * Dirichlet data, unit density and wave speed (C = 0, F = 0), on one
+ * single-patch spline domain (Sec. 5.2) of degree p with maximal smoothness.
+ *
+ * Conventions shared by every call:
+ *  - Vectors are FP64, device-resident, and hold the free (Dirichlet-
+ *    eliminated) coefficients in co-lexicographic order, x fastest
+ *    (Sec. 5.2): index ix + mf_x*(iy + mf_y*iz), mf_a = n_a + p - 2.
+ *    Several right-hand sides ("nrhs") are stored back to back.
+ *  - The caller owns every vector it passes; the library never frees or
+ *    retains them.  The library owns all handle internals (tables,
+ *    geometric factors, preconditioner data, work buffers).
+ *  - All work is ordered on the HIP stream passed as `stream` (a
+ *    hipStream_t; NULL = the default stream).  Calls return once the work
+ *    is enqueued unless they hand scalars back to the host (ga_mass_solve,
+ *    ga_step, ga_init_state, ga_lambda_max, ga_patch_setup).
+ *  - Every call returns GA_OK or a negative status; it never throws.
+ *    ga_last_error() gives a message for the last failure of the calling
+ *    thread.
+ */
+#ifndef GA_H
+#define GA_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ga_patch ga_patch;
+typedef struct ga_integrator ga_integrator;
+
+enum {
+  GA_OK = 0,
+  GA_EINVAL = -1,     /* bad argument: sizes, degree, null pointer, k, rho */
+  GA_ENOMEM = -2,     /* device allocation failed                         */
+  GA_EDEVICE = -3,    /* a HIP call failed                                */
+  GA_EGEOMETRY = -4,  /* det DF <= 0 at a quadrature point (Assumption 3) */
+  GA_ENOCONV = -5,    /* PCG hit maxit; the last iterate is still written */
+  GA_EUNSTABLE = -6   /* a state norm became non-finite during stepping   */
+};
+
+enum { GA_FP64 = 0 };                /* arithmetic of operator applies      */
+enum { GA_GUESS_ZERO = 0, GA_GUESS_PREV = 1 }; /* CG initial guess in ga_step */
+
+/*
+ * ga_setup_patch -- build one patch (Sec. 5.1-5.2, eq. mass_matrix and the
+ * preconditioner definition of Sec. 5.4).
+ *   dim        2 or 3.
+ *   n_el[dim]  elements per direction (>= 1), uniform open knot vectors.
+ *   p          spline degree, 1..4; p+1 Gauss points per element/direction.
+ *   ctrl_host  host array [N_dof][dim] of control points C_i of the map
+ *              F = sum_i C_i B_i, co-lex over the full grid of
+ *              N_dof = prod (n_a + p) coefficients.  Read during the call only.
+ * Builds, on the device: the quadrature factors w|det J| and
+ * w|det J| J^{-1} J^{-T}, D = diag(M), the scaling s = (Dhat/D)^{1/2} and the
+ * dense inverses of the univariate parametric mass matrices on the free
+ * coefficients.  Returns GA_EGEOMETRY (and no handle) if det J <= 0 anywhere.
+ */
+int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host,
+                   void* stream, ga_patch** out);
+int ga_destroy_patch(ga_patch* patch);
+
+/* Sizes: free coefficients, quadrature points, free coefficients per axis. */
+int ga_patch_info(const ga_patch* patch, long long* n_free, long long* n_quad,
+                  int* mf /* [3]; mf[2] = 1 for dim 2 */);
+
+/* d_dev[N_free] <- diag(M) (the D of Sec. 5.4). */
+int ga_diag_M(ga_patch* patch, double* d_dev, void* stream);
+
+/*
+ * ga_apply_MK -- y = alpha * Op x for nrhs vectors, Op = M (which = 'M', eq.
+ * mass_matrix) or K (which = 'K', stiffness of eq. mp with omega = 1),
+ * restricted to the free coefficients, applied matrix-free by sum
+ * factorisation over the Gauss points.  x and y must not overlap.
+ */
+int ga_apply_MK(ga_patch* patch, char which, int nrhs, double alpha,
+                const double* x_dev, double* y_dev, void* stream);
+
+/*
+ * ga_apply_Pinv -- z = P^{-1} r for nrhs vectors, with
+ * P = D^{1/2} Dhat^{-1/2} Mhat Dhat^{-1/2} D^{1/2} (Sec. 5.4), applied as
+ * z = s * (Mz^{-1} x My^{-1} x Mx^{-1})(s * r): a dense contraction along
+ * each tensor axis.  r and z may be the same buffer.
+ */
+int ga_apply_Pinv(ga_patch* patch, int nrhs, const double* r_dev, double* z_dev,
+                  void* stream);
+
+/*
+ * ga_mass_solve -- PCG for M x_j = b_j, j < nrhs (Sec. 5.6; solver settings of
+ * Sec. 6).  x_dev holds the initial guesses on entry (zero them for the
+ * paper's null guess) and the solutions on return.  Each right-hand side
+ * stops when sqrt(r^T P^{-1} r) <= rtol * sqrt(b^T P^{-1} b); converged
+ * right-hand sides are frozen while the others continue.
+ *   iters_out[nrhs], relres_out[nrhs]  host arrays or NULL.
+ * Returns GA_ENOCONV if any right-hand side did not converge in maxit.
+ */
+int ga_mass_solve(ga_patch* patch, int nrhs, const double* b_dev, double* x_dev,
+                  double rtol, int maxit, int* iters_out, double* relres_out,
+                  void* stream);
+
+/*
+ * ga_lambda_max -- estimate of the largest eigenvalue of M^{-1} K by power
+ * iteration (iters steps, each one K apply and one PCG mass solve).  Used to
+ * choose tau below the stability limit tau^2 lambda_max <= Theta_s.
+ */
+int ga_lambda_max(ga_patch* patch, int iters, double* lambda_out, void* stream);
+
+/* Theta_s(rho): stability limit on tau^2 lambda of the scheme (all k). */
+double ga_stability_limit(double rho);
+
+/*
+ * ga_integrator_create -- the order-2k scheme of Sec. 4 (k = 1, 2, 3, 4) with
+ * rho_b = rho_s = rho in [0, 1), step tau > 0, PCG tolerance rtol and maxit.
+ * State vectors are L^a, a = -2 .. 3k-3 (U, V, A, then time derivatives of A).
+ */
+int ga_integrator_create(ga_patch* patch, int k, double rho, double tau, double rtol,
+                         int maxit, int guess_mode, ga_integrator** out);
+int ga_integrator_destroy(ga_integrator* integ);
+
+/*
+ * ga_init_state -- initial data: L^{-2} = U0, L^{-1} = V0 and
+ * L^a = M^{-1}(-K L^{a-2}) for a = 0..3k-3 (the initial solves of Sec. 3,
+ * continued to general k).  state_dev[3k] are caller-owned vectors.
+ */
+int ga_init_state(ga_integrator* integ, const double* U0_dev, const double* V0_dev,
+                  double* const* state_dev, void* stream);
+
+/*
+ * ga_step -- advance state_dev[3k] by nsteps steps.  Each step forms the
+ * Taylor predictors, the k stage right-hand sides -K Y_j (eq. ho1), solves
+ * the k mass systems together by PCG, and applies the updates of eq. ho2.
+ *   iters_out  host array [nsteps][k] of PCG iterations, or NULL.
+ * Returns GA_ENOCONV if a stage solve did not converge, GA_EUNSTABLE if the
+ * displacement norm became non-finite.
+ */
+int ga_step(ga_integrator* integ, double* const* state_dev, int nsteps,
+            int* iters_out, void* stream);
+
+/*
+ * Launch timing (instrumentation, not part of the method): with profiling on,
+ * every operator launch (kind 0 = mass apply, 1 = stiffness apply) and every
+ * preconditioner application (kind 2) is bracketed by HIP events on the
+ * stream it runs on.  ga_profile(enable) clears the totals;
+ * ga_profile_query waits for the recorded events and returns the summed
+ * duration in ms and the number of launches of one kind.  Host-global state,
+ * not thread safe.
+ */
+int ga_profile(int enable);
+int ga_profile_query(int kind, double* total_ms, long long* launches);
+
+/* Message for the last non-GA_OK status returned on this thread. */
+const char* ga_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GA_H */

@@ -1,0 +1,624 @@
+// C ABI of the library: patch setup, operator applies, preconditioner, PCG
+// mass solves and the order-2k generalized-alpha time step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace ga {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+}  // namespace ga
+
+using namespace ga;
+
+#define GA_TRY_HIP(call)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      set_error(std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_));      \
+      return GA_EDEVICE;                                                                   \
+    }                                                                                      \
+  } while (0)
+
+namespace {
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int dalloc(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+    return GA_ENOMEM;
+  }
+  return GA_OK;
+}
+
+template <class T>
+int upload(T** dst, const std::vector<T>& v) {
+  int rc = dalloc((void**)dst, v.size() * sizeof(T));
+  if (rc) return rc;
+  GA_TRY_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GA_OK;
+}
+
+int check_launch(int rc, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (rc != 0 || e != hipSuccess) {
+    set_error(std::string("kernel launch failed: ") + what + " (" + hipGetErrorString(e) + ")");
+    return GA_EDEVICE;
+  }
+  return GA_OK;
+}
+
+// ---- optional HIP-event timing of the operator and preconditioner launches ----
+struct ProfState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
+  double total_ms[3] = {0, 0, 0};
+  long long count[3] = {0, 0, 0};
+};
+ProfState g_prof;
+
+hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_drain(int kind) {
+  for (auto& pr : g_prof.pending[kind]) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) == hipSuccess &&
+        hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      g_prof.total_ms[kind] += ms;
+      g_prof.count[kind] += 1;
+    }
+    g_prof.pool.push_back(pr.first);
+    g_prof.pool.push_back(pr.second);
+  }
+  g_prof.pending[kind].clear();
+}
+
+struct ProfScope {
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int k, hipStream_t s) : kind(k), st(s) {
+    if (!g_prof.on) return;
+    if (g_prof.pending[kind].size() > 4096) prof_drain(kind);
+    a = prof_event();
+    b = prof_event();
+    if (a && b) hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!g_prof.on || !a || !b) return;
+    hipEventRecord(b, st);
+    g_prof.pending[kind].push_back({a, b});
+  }
+};
+
+// grow the patch work area to hold `nvec` vectors of n_free doubles
+int ensure_work(ga_patch* pt, int nvec) {
+  size_t need = (size_t)nvec * (size_t)pt->n_free * sizeof(double);
+  if (need <= pt->work_bytes) return GA_OK;
+  if (pt->work) hipFree(pt->work);
+  pt->work = nullptr;
+  pt->work_bytes = 0;
+  int rc = dalloc((void**)&pt->work, need);
+  if (rc) return rc;
+  pt->work_bytes = need;
+  return GA_OK;
+}
+
+constexpr int MAX_NR = 3;  // right-hand sides per kernel pass
+
+int op_apply(ga_patch* pt, int mode, int nr, double alpha, const double* x, double* y,
+             hipStream_t st) {
+  // y += alpha * Op x, in chunks of MAX_NR right-hand sides
+  for (int r0 = 0; r0 < nr; r0 += MAX_NR) {
+    int c = nr - r0 < MAX_NR ? nr - r0 : MAX_NR;
+    const double* xc = x ? x + (size_t)r0 * pt->n_free : nullptr;
+    double* yc = y + (size_t)r0 * pt->n_free;
+    ProfScope prof(mode == 1 ? 1 : 0, st);
+    int rc = pt->dim == 3 ? launch_op3d(mode, c, pt, xc, yc, alpha, st)
+                          : launch_op2d(mode, c, pt, xc, yc, alpha, st);
+    if (check_launch(rc, "operator")) return GA_EDEVICE;
+  }
+  return GA_OK;
+}
+
+// z = P^{-1} r using two scratch vectors t0, t1 (each nr * n_free)
+int pinv_apply(ga_patch* pt, int nr, const double* r, double* z, double* t0, double* t1,
+               hipStream_t st) {
+  const size_t n = pt->n_free;
+  const int m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
+  ProfScope prof(2, st);
+  launch_scale_mul(t0, r, pt->s, nr, n, st);
+  // x axis: rows of length m0:  t1[row][i] = sum_j t0[row][j] Ax[j][i]  (Ax symmetric)
+  launch_gemm((int)((size_t)nr * m1 * m2), m0, m0, t0, m0, 0, pt->Minv[0], m0, 0, t1, m0, 0, 1, st);
+  // y axis: per (r, z) plane: t0[i][x] = sum_j Ay[i][j] t1[j][x]
+  launch_gemm(m1, m0, m1, pt->Minv[1], m1, 0, t1, m0, (long long)m0 * m1, t0, m0,
+              (long long)m0 * m1, nr * m2, st);
+  const double* last = t0;
+  if (pt->dim == 3) {
+    // z axis: per r: t1[i][yx] = sum_j Az[i][j] t0[j][yx]
+    launch_gemm(m2, m0 * m1, m2, pt->Minv[2], m2, 0, t0, (long long)m0 * m1, (long long)n, t1,
+                (long long)m0 * m1, (long long)n, nr, st);
+    last = t1;
+  }
+  launch_scale_mul(z, last, pt->s, nr, n, st);
+  return check_launch(0, "preconditioner");
+}
+
+// Stability limit: the lambda = -1 crossing of the characteristic polynomial
+// of the last diagonal block (printed in Sec. 3), i.e. Theta (8 beta - 4 gamma)
+// = 16 alpha - 8, with the block-k parameters.
+void block_k_params(double rho, double& a, double& b, double& g) {
+  const double rb = rho, rs = rho;
+  a = (2 + (1 - rb) * rs) / ((1 + rb) * (1 + rs));
+  b = (-5 - 3 * rb - 4 * rs + 2 * rb * rs + 2 * rb * rb * rs - rs * rs + rb * rs * rs) /
+      ((1 + rb) * (1 + rb) * (-2 - 3 * rs + rb * rs - rs * rs + rb * rs * rs));
+  g = 0.5 + a;  // gamma = 1/2 - alpha_f + alpha with alpha_f = 0
+}
+
+// blocks j < k: the printed formulas evaluated at rho_b = rho_s = -rho
+void block_j_params(double rho, double& a, double& b, double& g) {
+  const double rb = -rho, rs = -rho;
+  a = (2 - (1 + rb) * rs) / ((-1 + rb) * (-1 + rs));
+  b = (1 + rb) * (-1 + rb * rs) * (-1 + rb * rs) /
+      ((-1 + rb) * (-1 + rb) * (-1 + rs) * (-2 + rs + rb * rs));
+  g = 0.5 - 1.0 + a;  // alpha_f = 1
+}
+
+struct SolveBufs {
+  double *r, *z, *p, *q, *t0, *t1;
+};
+
+// PCG for nr right-hand sides; x holds the guess (zero_guess: ignored and set to 0)
+int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, int maxit,
+               bool zero_guess, int* iters_out, double* relres_out, hipStream_t st) {
+  const size_t n = pt->n_free;
+  int rc = ensure_work(pt, 6 * nr);
+  if (rc) return rc;
+  SolveBufs w;
+  double* base = pt->work;
+  w.r = base;
+  w.z = base + (size_t)nr * n;
+  w.p = base + (size_t)2 * nr * n;
+  w.q = base + (size_t)3 * nr * n;
+  w.t0 = base + (size_t)4 * nr * n;
+  w.t1 = base + (size_t)5 * nr * n;
+  double* partA = pt->red;
+  double* partB = pt->red + (size_t)16 * RED_BLOCKS;
+  const size_t tot = (size_t)nr * n;
+  if (zero_guess) {
+    launch_fill(x, 0.0, tot, st);
+    launch_copy(w.r, b, tot, st);
+  } else {
+    launch_copy(w.r, b, tot, st);
+    if ((rc = op_apply(pt, 0, nr, -1.0, x, w.r, st))) return rc;
+  }
+  if ((rc = pinv_apply(pt, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+  launch_dot_partial(nr, w.r, w.z, n, partA, st);
+  const double* pbn = nullptr;
+  if (!zero_guess) {
+    if ((rc = pinv_apply(pt, nr, b, w.q, w.t0, w.t1, st))) return rc;
+    launch_dot_partial(nr, b, w.q, n, partB, st);
+    pbn = partB;
+  }
+  launch_cg_start(nr, partA, pbn, pt->scal, rtol * rtol, st);
+  launch_copy(w.p, w.z, tot, st);
+  if (check_launch(0, "pcg start")) return GA_EDEVICE;
+  int it = 0;
+  for (;; ++it) {
+    GA_TRY_HIP(hipMemcpyAsync(pt->host_scal, pt->scal, sizeof(double) * NSCAL * nr,
+                              hipMemcpyDeviceToHost, st));
+    GA_TRY_HIP(hipStreamSynchronize(st));
+    bool any = false;
+    for (int r = 0; r < nr; ++r) any |= pt->host_scal[r * NSCAL + S_ACTIVE] != 0.0;
+    if (!any || it >= maxit) break;
+    launch_fill(w.q, 0.0, tot, st);
+    if ((rc = op_apply(pt, 0, nr, 1.0, w.p, w.q, st))) return rc;
+    launch_dot_partial(nr, w.p, w.q, n, partA, st);
+    launch_cg_alpha(nr, partA, pt->scal, st);
+    launch_cg_xr(nr, x, w.r, w.p, w.q, pt->scal, n, st);
+    if ((rc = pinv_apply(pt, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+    launch_dot_partial(nr, w.r, w.z, n, partA, st);
+    launch_cg_beta(nr, partA, pt->scal, st);
+    launch_cg_p(nr, w.p, w.z, pt->scal, n, st);
+    if (check_launch(0, "pcg iteration")) return GA_EDEVICE;
+  }
+  bool ok = true;
+  for (int r = 0; r < nr; ++r) {
+    const double* s = pt->host_scal + r * NSCAL;
+    if (iters_out) iters_out[r] = (int)s[S_ITERS];
+    if (relres_out) relres_out[r] = s[S_BN2] > 0 ? std::sqrt(std::fabs(s[S_RZ] / s[S_BN2])) : 0.0;
+    if (s[S_ACTIVE] != 0.0) ok = false;
+    if (!std::isfinite(s[S_RZ])) ok = false;
+  }
+  if (!ok) {
+    set_error("PCG did not converge within maxit");
+    return GA_ENOCONV;
+  }
+  return GA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ga_last_error(void) { return g_err.c_str(); }
+
+int ga_profile(int enable) {
+  for (int k = 0; k < 3; ++k) prof_drain(k);
+  for (int k = 0; k < 3; ++k) { g_prof.total_ms[k] = 0.0; g_prof.count[k] = 0; }
+  g_prof.on = enable != 0;
+  return GA_OK;
+}
+
+int ga_profile_query(int kind, double* total_ms, long long* launches) {
+  if (kind < 0 || kind > 2 || !total_ms || !launches) { set_error("bad argument"); return GA_EINVAL; }
+  prof_drain(kind);
+  *total_ms = g_prof.total_ms[kind];
+  *launches = g_prof.count[kind];
+  return GA_OK;
+}
+
+double ga_stability_limit(double rho) {
+  double a, b, g;
+  block_k_params(rho, a, b, g);
+  return (16.0 * a - 8.0) / (8.0 * b - 4.0 * g);
+}
+
+int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, void* stream,
+                   ga_patch** out) {
+  if (!out || !n_el || !ctrl_host) { set_error("null argument"); return GA_EINVAL; }
+  *out = nullptr;
+  if (dim != 2 && dim != 3) { set_error("dim must be 2 or 3"); return GA_EINVAL; }
+  if (p < 1 || p > 4) { set_error("p must be in 1..4"); return GA_EINVAL; }
+  for (int a = 0; a < dim; ++a)
+    if (n_el[a] < 1 || n_el[a] > 4096) { set_error("n_el out of range"); return GA_EINVAL; }
+  for (int a = 0; a < dim; ++a)
+    if (n_el[a] + p - 2 < 1) { set_error("no free coefficients"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  ga_patch* pt = new ga_patch();
+  pt->dim = dim;
+  pt->p = p;
+  const int TE = dim == 3 ? TE3 : TE2;
+  long long ndof = 1;
+  pt->n_free = 1;
+  pt->n_tiles = 1;
+  for (int a = 0; a < dim; ++a) {
+    pt->n[a] = n_el[a];
+    pt->m[a] = n_el[a] + p;
+    pt->mf[a] = n_el[a] + p - 2;
+    pt->nt[a] = (n_el[a] + TE - 1) / TE;
+    ndof *= pt->m[a];
+    pt->n_free *= pt->mf[a];
+    pt->n_tiles *= pt->nt[a];
+  }
+  long long qpt = 1;
+  for (int a = 0; a < dim; ++a) qpt *= (long long)TE * (p + 1);
+  pt->qp_per_tile = qpt;
+  pt->n_quad = 1;
+  for (int a = 0; a < dim; ++a) pt->n_quad *= (long long)n_el[a] * (p + 1);
+  int rc = GA_OK;
+  auto fail = [&](int code) { ga_destroy_patch(pt); return code; };
+  // univariate tables, padded to whole tiles with zeros
+  std::vector<double*> wdev(3, nullptr);
+  for (int a = 0; a < dim; ++a) {
+    pt->ax[a] = build_axis(n_el[a], p);
+    const Axis1D& ax = pt->ax[a];
+    const size_t per_el = (size_t)ax.q * (p + 1);
+    const size_t npad = (size_t)pt->nt[a] * TE;
+    std::vector<double> B(npad * per_el, 0.0), D(npad * per_el, 0.0), B2(npad * per_el, 0.0);
+    std::vector<double> w(npad * ax.q, 0.0);
+    for (size_t i = 0; i < ax.B.size(); ++i) {
+      B[i] = ax.B[i];
+      D[i] = ax.D[i];
+      B2[i] = ax.B[i] * ax.B[i];
+    }
+    for (size_t i = 0; i < ax.w.size(); ++i) w[i] = ax.w[i];
+    if ((rc = upload(&pt->tabB[a], B)) || (rc = upload(&pt->tabD[a], D)) ||
+        (rc = upload(&pt->tabB2[a], B2)) || (rc = upload(&pt->Minv[a], ax.Minv)) ||
+        (rc = upload(&wdev[a], w))) {
+      for (double* d : wdev) if (d) hipFree(d);
+      return fail(rc);
+    }
+  }
+  auto free_w = [&]() { for (double*& d : wdev) if (d) { hipFree(d); d = nullptr; } };
+  // control points, SoA [dim][ndof]
+  std::vector<double> ctrl((size_t)dim * ndof);
+  for (long long i = 0; i < ndof; ++i)
+    for (int c = 0; c < dim; ++c) ctrl[(size_t)c * ndof + i] = ctrl_host[(size_t)i * dim + c];
+  double* dctrl = nullptr;
+  int* dbad = nullptr;
+  if ((rc = upload(&dctrl, ctrl))) { free_w(); return fail(rc); }
+  if ((rc = dalloc((void**)&dbad, sizeof(int)))) { hipFree(dctrl); free_w(); return fail(rc); }
+  const size_t nqp_pad = (size_t)pt->n_tiles * qpt;
+  const int ncomp = dim == 3 ? 6 : 3;
+  if ((rc = dalloc((void**)&pt->W, nqp_pad * sizeof(double))) ||
+      (rc = dalloc((void**)&pt->G, nqp_pad * ncomp * sizeof(double))) ||
+      (rc = dalloc((void**)&pt->diagM, pt->n_free * sizeof(double))) ||
+      (rc = dalloc((void**)&pt->s, pt->n_free * sizeof(double))) ||
+      (rc = dalloc((void**)&pt->red, sizeof(double) * 32 * RED_BLOCKS)) ||
+      (rc = dalloc((void**)&pt->scal, sizeof(double) * NSCAL * 64)) ||
+      (rc = dalloc((void**)&pt->flags, sizeof(int) * 16))) {
+    hipFree(dctrl); hipFree(dbad); free_w();
+    return fail(rc);
+  }
+  if (hipHostMalloc((void**)&pt->host_scal, sizeof(double) * NSCAL * 64) != hipSuccess) {
+    hipFree(dctrl); hipFree(dbad); free_w();
+    set_error("hipHostMalloc failed");
+    return fail(GA_ENOMEM);
+  }
+  int hbad = 0;
+  hipMemsetAsync(dbad, 0, sizeof(int), st);
+  const double* wp[3] = {wdev[0], wdev[1], wdev[2]};
+  int lrc = dim == 3 ? launch_geo3d(pt, dctrl, wp, dbad, st) : launch_geo2d(pt, dctrl, wp, dbad, st);
+  if (check_launch(lrc, "geometry")) { hipFree(dctrl); hipFree(dbad); free_w(); return fail(GA_EDEVICE); }
+  hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    set_error("geometry setup failed on the device");
+    hipFree(dctrl); hipFree(dbad); free_w();
+    return fail(GA_EDEVICE);
+  }
+  hipFree(dctrl);
+  hipFree(dbad);
+  free_w();
+  if (hbad) {
+    set_error("det DF <= 0 at a quadrature point (the map must be orientation preserving)");
+    return fail(GA_EGEOMETRY);
+  }
+  // D = diag(M), s = (Dhat / D)^{1/2}
+  launch_fill(pt->diagM, 0.0, pt->n_free, st);
+  if ((rc = op_apply(pt, 2, 1, 1.0, nullptr, pt->diagM, st))) return fail(rc);
+  std::vector<double*> dh(3, nullptr);
+  for (int a = 0; a < dim; ++a)
+    if ((rc = upload(&dh[a], pt->ax[a].dhat))) {
+      for (double* d : dh) if (d) hipFree(d);
+      return fail(rc);
+    }
+  launch_scaling(pt->s, pt->diagM, dh[0], dh[1], dim == 3 ? dh[2] : nullptr, pt->mf[0], pt->mf[1],
+                 dim == 3 ? pt->mf[2] : 1, st);
+  hipError_t e = hipStreamSynchronize(st);
+  for (double* d : dh) if (d) hipFree(d);
+  if (e != hipSuccess) { set_error("setup failed on the device"); return fail(GA_EDEVICE); }
+  *out = pt;
+  return GA_OK;
+}
+
+int ga_destroy_patch(ga_patch* pt) {
+  if (!pt) return GA_OK;
+  for (int a = 0; a < 3; ++a) {
+    if (pt->tabB[a]) hipFree(pt->tabB[a]);
+    if (pt->tabD[a]) hipFree(pt->tabD[a]);
+    if (pt->tabB2[a]) hipFree(pt->tabB2[a]);
+    if (pt->Minv[a]) hipFree(pt->Minv[a]);
+  }
+  if (pt->W) hipFree(pt->W);
+  if (pt->G) hipFree(pt->G);
+  if (pt->diagM) hipFree(pt->diagM);
+  if (pt->s) hipFree(pt->s);
+  if (pt->work) hipFree(pt->work);
+  if (pt->red) hipFree(pt->red);
+  if (pt->scal) hipFree(pt->scal);
+  if (pt->flags) hipFree(pt->flags);
+  if (pt->host_scal) hipHostFree(pt->host_scal);
+  delete pt;
+  return GA_OK;
+}
+
+int ga_patch_info(const ga_patch* pt, long long* n_free, long long* n_quad, int* mf) {
+  if (!pt) { set_error("null patch"); return GA_EINVAL; }
+  if (n_free) *n_free = pt->n_free;
+  if (n_quad) *n_quad = pt->n_quad;
+  if (mf) for (int a = 0; a < 3; ++a) mf[a] = a < pt->dim ? pt->mf[a] : 1;
+  return GA_OK;
+}
+
+int ga_diag_M(ga_patch* pt, double* d, void* stream) {
+  if (!pt || !d) { set_error("null argument"); return GA_EINVAL; }
+  GA_TRY_HIP(hipMemcpyAsync(d, pt->diagM, pt->n_free * sizeof(double), hipMemcpyDeviceToDevice,
+                            S(stream)));
+  return GA_OK;
+}
+
+int ga_apply_MK(ga_patch* pt, char which, int nrhs, double alpha, const double* x, double* y,
+                void* stream) {
+  if (!pt || !x || !y) { set_error("null argument"); return GA_EINVAL; }
+  if (nrhs < 1) { set_error("nrhs must be >= 1"); return GA_EINVAL; }
+  if (which != 'M' && which != 'K') { set_error("which must be 'M' or 'K'"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  launch_fill(y, 0.0, (size_t)nrhs * pt->n_free, st);
+  return op_apply(pt, which == 'M' ? 0 : 1, nrhs, alpha, x, y, st);
+}
+
+int ga_apply_Pinv(ga_patch* pt, int nrhs, const double* r, double* z, void* stream) {
+  if (!pt || !r || !z) { set_error("null argument"); return GA_EINVAL; }
+  if (nrhs < 1) { set_error("nrhs must be >= 1"); return GA_EINVAL; }
+  int rc = ensure_work(pt, 6 * nrhs);
+  if (rc) return rc;
+  double* t0 = pt->work + (size_t)4 * nrhs * pt->n_free;
+  double* t1 = pt->work + (size_t)5 * nrhs * pt->n_free;
+  return pinv_apply(pt, nrhs, r, z, t0, t1, S(stream));
+}
+
+int ga_mass_solve(ga_patch* pt, int nrhs, const double* b, double* x, double rtol, int maxit,
+                  int* iters_out, double* relres_out, void* stream) {
+  if (!pt || !b || !x) { set_error("null argument"); return GA_EINVAL; }
+  if (nrhs < 1 || nrhs > 16) { set_error("nrhs must be in 1..16"); return GA_EINVAL; }
+  if (!(rtol > 0.0) || maxit < 0) { set_error("rtol must be > 0 and maxit >= 0"); return GA_EINVAL; }
+  return solve_impl(pt, nrhs, b, x, rtol, maxit, false, iters_out, relres_out, S(stream));
+}
+
+int ga_lambda_max(ga_patch* pt, int iters, double* out, void* stream) {
+  if (!pt || !out || iters < 1) { set_error("bad argument"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  const size_t n = pt->n_free;
+  double *v = nullptr, *kv = nullptr, *u = nullptr, *mv = nullptr, *res = nullptr;
+  int rc;
+  if ((rc = dalloc((void**)&v, n * 8)) || (rc = dalloc((void**)&kv, n * 8)) ||
+      (rc = dalloc((void**)&u, n * 8)) || (rc = dalloc((void**)&mv, n * 8)) ||
+      (rc = dalloc((void**)&res, 64))) {
+    hipFree(v); hipFree(kv); hipFree(u); hipFree(mv); hipFree(res);
+    return rc;
+  }
+  std::vector<double> h(n);
+  unsigned long long s = 0x9E3779B97F4A7C15ull;
+  for (size_t i = 0; i < n; ++i) {
+    s = s * 6364136223846793005ull + 1442695040888963407ull;
+    h[i] = (double)((s >> 11) & ((1ull << 52) - 1)) / (double)(1ull << 52) - 0.5;
+  }
+  hipMemcpy(v, h.data(), n * 8, hipMemcpyHostToDevice);
+  double lam = 0.0;
+  double hres[2];
+  for (int it = 0; it < iters && rc == GA_OK; ++it) {
+    launch_fill(kv, 0.0, n, st);
+    if ((rc = op_apply(pt, 1, 1, 1.0, v, kv, st))) break;
+    launch_fill(mv, 0.0, n, st);
+    if ((rc = op_apply(pt, 0, 1, 1.0, v, mv, st))) break;
+    launch_dot_partial(1, v, kv, n, pt->red, st);
+    launch_sum_partials(1, pt->red, res, st);
+    launch_dot_partial(1, v, mv, n, pt->red, st);
+    launch_sum_partials(1, pt->red, res + 1, st);
+    hipMemcpyAsync(hres, res, 16, hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    lam = hres[0] / hres[1];
+    rc = solve_impl(pt, 1, kv, u, 1e-8, 500, true, nullptr, nullptr, st);
+    if (rc == GA_ENOCONV) rc = GA_OK;
+    if (rc) break;
+    // normalise: v = u / sqrt(u.u)
+    launch_dot_partial(1, u, u, n, pt->red, st);
+    launch_sum_partials(1, pt->red, res, st);
+    hipMemcpyAsync(hres, res, 8, hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    double nrm = std::sqrt(hres[0]);
+    if (!(nrm > 0)) break;
+    launch_axpby(v, 1.0 / nrm, u, 0.0, v, n, st);
+  }
+  hipFree(v); hipFree(kv); hipFree(u); hipFree(mv); hipFree(res);
+  if (rc) return rc;
+  *out = lam;
+  return GA_OK;
+}
+
+int ga_integrator_create(ga_patch* pt, int k, double rho, double tau, double rtol, int maxit,
+                         int guess_mode, ga_integrator** out) {
+  if (!pt || !out) { set_error("null argument"); return GA_EINVAL; }
+  *out = nullptr;
+  if (k < 1 || k > 4) { set_error("k must be in 1..4"); return GA_EINVAL; }
+  if (!(rho >= 0.0 && rho < 1.0)) { set_error("rho must be in [0, 1)"); return GA_EINVAL; }
+  if (!(tau > 0.0) || !(rtol > 0.0) || maxit < 1) { set_error("bad tau/rtol/maxit"); return GA_EINVAL; }
+  if (guess_mode != GA_GUESS_ZERO && guess_mode != GA_GUESS_PREV) { set_error("bad guess mode"); return GA_EINVAL; }
+  ga_integrator* it = new ga_integrator();
+  it->patch = pt;
+  it->k = k;
+  it->rho = rho;
+  it->tau = tau;
+  it->rtol = rtol;
+  it->maxit = maxit;
+  it->guess = guess_mode;
+  for (int j = 0; j < k; ++j) {
+    if (j < k - 1) block_j_params(rho, it->alpha[j], it->beta[j], it->gamma[j]);
+    else block_k_params(rho, it->alpha[j], it->beta[j], it->gamma[j]);
+  }
+  int rc;
+  if ((rc = dalloc((void**)&it->Y, (size_t)k * pt->n_free * 8)) ||
+      (rc = dalloc((void**)&it->Bv, (size_t)k * pt->n_free * 8)) ||
+      (rc = dalloc((void**)&it->X, (size_t)k * pt->n_free * 8))) {
+    ga_integrator_destroy(it);
+    return rc;
+  }
+  *out = it;
+  return GA_OK;
+}
+
+int ga_integrator_destroy(ga_integrator* it) {
+  if (!it) return GA_OK;
+  if (it->Y) hipFree(it->Y);
+  if (it->Bv) hipFree(it->Bv);
+  if (it->X) hipFree(it->X);
+  delete it;
+  return GA_OK;
+}
+
+int ga_init_state(ga_integrator* it, const double* U0, const double* V0, double* const* state,
+                  void* stream) {
+  if (!it || !U0 || !V0 || !state) { set_error("null argument"); return GA_EINVAL; }
+  for (int s = 0; s < 3 * it->k; ++s)
+    if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+  ga_patch* pt = it->patch;
+  hipStream_t st = S(stream);
+  const size_t n = pt->n_free;
+  launch_copy(state[0], U0, n, st);
+  launch_copy(state[1], V0, n, st);
+  for (int a = 0; a <= 3 * it->k - 3; ++a) {
+    launch_fill(it->Y, 0.0, n, st);
+    int rc = op_apply(pt, 1, 1, -1.0, state[a], it->Y, st);  // -K L^{a-2}
+    if (rc) return rc;
+    rc = solve_impl(pt, 1, it->Y, state[a + 2], it->rtol, it->maxit, true, nullptr, nullptr, st);
+    if (rc) return rc;
+  }
+  it->have_prev = false;
+  return GA_OK;
+}
+
+int ga_step(ga_integrator* it, double* const* state, int nsteps, int* iters_out, void* stream) {
+  if (!it || !state || nsteps < 0) { set_error("bad argument"); return GA_EINVAL; }
+  const int k = it->k, ns = 3 * k;
+  for (int s = 0; s < ns; ++s)
+    if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+  ga_patch* pt = it->patch;
+  hipStream_t st = S(stream);
+  const size_t n = pt->n_free;
+  StatePtrs sp;
+  for (int s = 0; s < 12; ++s) sp.L[s] = s < ns ? state[s] : nullptr;
+  Coefs cf;
+  for (int j = 0; j < 4; ++j) {
+    cf.alpha[j] = j < k ? it->alpha[j] : 1.0;
+    cf.beta[j] = j < k ? it->beta[j] : 0.0;
+    cf.gamma[j] = j < k ? it->gamma[j] : 0.0;
+  }
+  int iters[16];
+  for (int step = 0; step < nsteps; ++step) {
+    launch_predict(k, it->tau, sp, it->Y, n, st);
+    // stage right-hand sides b_j = -K Y_j (eq. ho1 with C = F = 0)
+    launch_fill(it->Bv, 0.0, (size_t)k * n, st);
+    int rc = op_apply(pt, 1, k, -1.0, it->Y, it->Bv, st);
+    if (rc) return rc;
+    bool zero = !(it->guess == GA_GUESS_PREV && it->have_prev);
+    rc = solve_impl(pt, k, it->Bv, it->X, it->rtol, it->maxit, zero, iters, nullptr, st);
+    if (rc) return rc;
+    if (iters_out)
+      for (int j = 0; j < k; ++j) iters_out[(size_t)step * k + j] = iters[j];
+    launch_update(k, it->tau, cf, sp, it->X, n, st);
+    if (check_launch(0, "update")) return GA_EDEVICE;
+    it->have_prev = true;
+  }
+  // finite check of the displacement
+  double* part = pt->red;
+  launch_dot_partial(1, state[0], state[0], n, part, st);
+  launch_sum_partials(1, part, pt->scal + NSCAL * 63, st);
+  double nrm2 = 0.0;
+  GA_TRY_HIP(hipMemcpyAsync(&nrm2, pt->scal + NSCAL * 63, 8, hipMemcpyDeviceToHost, st));
+  GA_TRY_HIP(hipStreamSynchronize(st));
+  if (!std::isfinite(nrm2)) { set_error("displacement became non-finite"); return GA_EUNSTABLE; }
+  return GA_OK;
+}
+
+}  // extern "C"

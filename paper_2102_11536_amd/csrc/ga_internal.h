@@ -1,0 +1,68 @@
+// Internal declarations of the ga library (not part of the C ABI).
+#pragma once
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/ga.h"
+
+namespace ga {
+
+// Univariate data of one tensor axis.
+struct Axis1D {
+  int n = 0, p = 0, q = 0, m = 0, mf = 0;
+  std::vector<double> B, D;   // [n][q][p+1]: values / derivatives of basis e+r at Gauss point j of element e
+  std::vector<double> w;      // [n][q]: Gauss weights (element length included)
+  std::vector<double> dhat;   // [mf]: diagonal of the univariate parametric mass (free part)
+  std::vector<double> Minv;   // [mf][mf]: its dense inverse, row-major
+};
+
+Axis1D build_axis(int n, int p);
+void gauss_legendre01(int nq, std::vector<double>& t, std::vector<double>& w);
+void basis_on_element(int n, int p, int e, double x, double* val, double* der);
+
+// Element tile of the sum-factorised operator kernels: TE elements per
+// direction, quadrature factors stored tile by tile.
+constexpr int TE3 = 4;   // 3-D tile: 4 x 4 x 4 elements
+constexpr int TE2 = 8;   // 2-D tile: 8 x 8 elements
+
+void set_error(const std::string& msg);
+
+}  // namespace ga
+
+struct ga_patch {
+  int dim = 0, p = 0;
+  int n[3] = {1, 1, 1}, m[3] = {1, 1, 1}, mf[3] = {1, 1, 1};
+  int nt[3] = {1, 1, 1};          // element tiles per direction
+  long long n_free = 0, n_quad = 0, n_tiles = 0, qp_per_tile = 0;
+  ga::Axis1D ax[3];
+  // device data
+  double* tabB[3] = {nullptr, nullptr, nullptr};   // [n_pad][q][p+1]
+  double* tabD[3] = {nullptr, nullptr, nullptr};
+  double* tabB2[3] = {nullptr, nullptr, nullptr};  // squared values (diag(M))
+  double* W = nullptr;        // [tiles][qp]   w |det J|
+  double* G = nullptr;        // [tiles][qz][ncomp][qy][qx]  w |det J| J^-1 J^-T
+  double* diagM = nullptr;    // [n_free]
+  double* s = nullptr;        // [n_free] (Dhat/D)^(1/2)
+  double* Minv[3] = {nullptr, nullptr, nullptr};   // [mf][mf]
+  // work buffers for solves (grown on demand)
+  double* work = nullptr;
+  size_t work_bytes = 0;
+  double* red = nullptr;      // reduction partials
+  double* scal = nullptr;     // device scalars
+  int* flags = nullptr;       // device flags
+  double* host_scal = nullptr;  // pinned host mirror of scalars
+};
+
+struct ga_integrator {
+  ga_patch* patch = nullptr;
+  int k = 1;
+  double rho = 0.5, tau = 0.0, rtol = 1e-10;
+  int maxit = 200, guess = GA_GUESS_ZERO;
+  double alpha[8], beta[8], gamma[8];
+  double* Y = nullptr;        // [k][n_free] stage arguments Y_j
+  double* Bv = nullptr;       // [k][n_free] stage right-hand sides -K Y_j
+  double* X = nullptr;        // [k][n_free] stage solutions
+  bool have_prev = false;
+};

@@ -1,0 +1,49 @@
+// Launchers shared between the kernel files and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ga_internal.h"
+
+namespace ga {
+
+constexpr int RED_BLOCKS = 256;   // partial sums per reduction
+constexpr int NSCAL = 8;          // device scalars per right-hand side
+enum { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_BETA = 3, S_BN2 = 4, S_ACTIVE = 5, S_ITERS = 6, S_TOL2 = 7 };
+
+struct StatePtrs { double* L[12]; };
+struct Coefs { double alpha[4], beta[4], gamma[4]; };
+
+int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
+                hipStream_t st);
+int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
+                 hipStream_t st);
+int launch_op2d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
+                hipStream_t st);
+int launch_geo2d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
+                 hipStream_t st);
+
+void launch_fill(double* p, double v, size_t n, hipStream_t st);
+void launch_copy(double* dst, const double* src, size_t n, hipStream_t st);
+void launch_scale_mul(double* out, const double* in, const double* s, int nr, size_t n, hipStream_t st);
+void launch_gemm(int M, int N, int K, const double* X, long long ldx, long long sX,
+                 const double* Y, long long ldy, long long sY, double* C, long long ldc,
+                 long long sC, int batch, hipStream_t st);
+void launch_scaling(double* s, const double* diagM, const double* dh0, const double* dh1,
+                    const double* dh2, int mf0, int mf1, int mf2, hipStream_t st);
+void launch_dot_partial(int nr, const double* a, const double* b, size_t n, double* part,
+                        hipStream_t st);
+void launch_cg_start(int nr, const double* part_rz, const double* part_bn, double* scal,
+                     double tol2, hipStream_t st);
+void launch_cg_alpha(int nr, const double* part, double* scal, hipStream_t st);
+void launch_cg_beta(int nr, const double* part, double* scal, hipStream_t st);
+void launch_cg_xr(int nr, double* x, double* r, const double* p, const double* q,
+                  const double* scal, size_t n, hipStream_t st);
+void launch_cg_p(int nr, double* p, const double* z, const double* scal, size_t n, hipStream_t st);
+void launch_predict(int k, double tau, StatePtrs sp, double* Y, size_t n, hipStream_t st);
+void launch_update(int k, double tau, Coefs c, StatePtrs sp, const double* X, size_t n,
+                   hipStream_t st);
+void launch_axpby(double* out, double a, const double* x, double b, const double* y, size_t n,
+                  hipStream_t st);
+void launch_sum_partials(int nr, const double* part, double* out, hipStream_t st);
+
+}  // namespace ga

@@ -1,0 +1,206 @@
+"""Thin ctypes binding of the C ABI in include/ga.h (same names, argument
+marshalling only).  Vectors are torch tensors on the GPU (FP64, contiguous);
+the library does all the compute.  Loading fails loudly if libga.so has not
+been built: there is no fallback path."""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libga.so")
+
+GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EGEOMETRY, GA_ENOCONV, GA_EUNSTABLE = 0, -1, -2, -3, -4, -5, -6
+GA_GUESS_ZERO, GA_GUESS_PREV = 0, 1
+
+EXPORTS = ["ga_setup_patch", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
+           "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
+           "ga_integrator_create", "ga_integrator_destroy", "ga_init_state", "ga_step",
+           "ga_profile", "ga_profile_query", "ga_last_error"]
+
+
+class GAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ga error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(the HIP library is the only compute path)")
+    lib = ctypes.CDLL(path)
+    vp, i, d, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    lib.ga_setup_patch.argtypes = [i, ctypes.POINTER(i), i, ctypes.POINTER(d), vp, ctypes.POINTER(vp)]
+    lib.ga_destroy_patch.argtypes = [vp]
+    lib.ga_patch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
+                                  ctypes.POINTER(i)]
+    lib.ga_diag_M.argtypes = [vp, dp, vp]
+    lib.ga_apply_MK.argtypes = [vp, ctypes.c_char, i, d, dp, dp, vp]
+    lib.ga_apply_Pinv.argtypes = [vp, i, dp, dp, vp]
+    lib.ga_mass_solve.argtypes = [vp, i, dp, dp, d, i, ctypes.POINTER(i), ctypes.POINTER(d), vp]
+    lib.ga_lambda_max.argtypes = [vp, i, ctypes.POINTER(d), vp]
+    lib.ga_stability_limit.argtypes = [d]
+    lib.ga_stability_limit.restype = d
+    lib.ga_integrator_create.argtypes = [vp, i, d, d, d, i, i, ctypes.POINTER(vp)]
+    lib.ga_integrator_destroy.argtypes = [vp]
+    lib.ga_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
+    lib.ga_step.argtypes = [vp, ctypes.POINTER(vp), i, ctypes.POINTER(i), vp]
+    lib.ga_profile.argtypes = [i]
+    lib.ga_profile_query.argtypes = [i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
+    lib.ga_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("ga_stability_limit", "ga_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != GA_OK:
+        raise GAError(rc, _lib.ga_last_error().decode())
+    return rc
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, n=None):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("vectors must be contiguous float64 CUDA tensors")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"vector has {t.numel()} entries, needs {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Patch:
+    """One spline patch (ga_setup_patch)."""
+
+    def __init__(self, dim, n_el, p, ctrl):
+        lib = load_library()
+        n_el = [int(v) for v in (n_el if np.ndim(n_el) else [n_el] * dim)]
+        ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
+        arr = (ctypes.c_int * len(n_el))(*n_el)
+        h = ctypes.c_void_p()
+        _check(lib.ga_setup_patch(dim, arr, p, ctrl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  _stream(), ctypes.byref(h)))
+        self.h = h
+        nf, nq = ctypes.c_longlong(), ctypes.c_longlong()
+        mf = (ctypes.c_int * 3)()
+        _check(lib.ga_patch_info(h, ctypes.byref(nf), ctypes.byref(nq), mf))
+        self.dim, self.p, self.n_el = dim, p, n_el
+        self.n_free, self.n_quad, self.mf = nf.value, nq.value, tuple(mf)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ga_destroy_patch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ga_setup_patch(dim, n_el, p, ctrl):
+    return Patch(dim, n_el, p, ctrl)
+
+
+def ga_diag_M(patch, d):
+    _check(_lib.ga_diag_M(patch.h, _ptr(d, patch.n_free), _stream()))
+
+
+def ga_apply_MK(patch, which, x, y, nrhs=1, alpha=1.0):
+    n = nrhs * patch.n_free
+    _check(_lib.ga_apply_MK(patch.h, which.encode(), nrhs, float(alpha), _ptr(x, n), _ptr(y, n), _stream()))
+
+
+def ga_apply_Pinv(patch, r, z, nrhs=1):
+    n = nrhs * patch.n_free
+    _check(_lib.ga_apply_Pinv(patch.h, nrhs, _ptr(r, n), _ptr(z, n), _stream()))
+
+
+def ga_mass_solve(patch, b, x, nrhs=1, rtol=1e-12, maxit=500, raise_on_noconv=True):
+    """Returns (iterations[nrhs], relres[nrhs], status)."""
+    n = nrhs * patch.n_free
+    its = (ctypes.c_int * nrhs)()
+    rel = (ctypes.c_double * nrhs)()
+    rc = _lib.ga_mass_solve(patch.h, nrhs, _ptr(b, n), _ptr(x, n), float(rtol), int(maxit), its, rel, _stream())
+    if rc != GA_ENOCONV or raise_on_noconv:
+        _check(rc)
+    return list(its), list(rel), rc
+
+
+def ga_lambda_max(patch, iters=30):
+    out = ctypes.c_double()
+    _check(_lib.ga_lambda_max(patch.h, int(iters), ctypes.byref(out), _stream()))
+    return out.value
+
+
+def ga_stability_limit(rho):
+    return load_library().ga_stability_limit(float(rho))
+
+
+class Integrator:
+    def __init__(self, patch, k, rho, tau, rtol=1e-10, maxit=200, guess=GA_GUESS_ZERO):
+        h = ctypes.c_void_p()
+        _check(_lib.ga_integrator_create(patch.h, k, float(rho), float(tau), float(rtol), int(maxit),
+                                         int(guess), ctypes.byref(h)))
+        self.h, self.patch, self.k = h, patch, k
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ga_integrator_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ga_integrator_create(patch, k, rho, tau, rtol=1e-10, maxit=200, guess=GA_GUESS_ZERO):
+    return Integrator(patch, k, rho, tau, rtol, maxit, guess)
+
+
+def _state_array(integ, state):
+    ns = 3 * integ.k
+    if len(state) != ns:
+        raise ValueError(f"need {ns} state vectors")
+    return (ctypes.c_void_p * ns)(*[_ptr(s, integ.patch.n_free).value for s in state])
+
+
+def ga_init_state(integ, U0, V0, state):
+    n = integ.patch.n_free
+    _check(_lib.ga_init_state(integ.h, _ptr(U0, n), _ptr(V0, n), _state_array(integ, state), _stream()))
+
+
+def ga_step(integ, state, nsteps=1, record_iters=True):
+    """Advance; returns an int array [nsteps, k] of PCG iterations (or None)."""
+    its = (ctypes.c_int * (nsteps * integ.k))() if record_iters else None
+    _check(_lib.ga_step(integ.h, _state_array(integ, state), int(nsteps), its, _stream()))
+    return np.array(its, dtype=np.int64).reshape(nsteps, integ.k) if record_iters else None
+
+
+PROF_MASS, PROF_STIFF, PROF_PINV = 0, 1, 2
+
+
+def ga_profile(enable):
+    _check(load_library().ga_profile(1 if enable else 0))
+
+
+def ga_profile_query(kind):
+    """(total_ms, launches) of one launch kind since the last ga_profile()."""
+    ms, cnt = ctypes.c_double(), ctypes.c_longlong()
+    _check(_lib.ga_profile_query(int(kind), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

@@ -1,0 +1,273 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import galpha, operators
+from paper_2102_11536_amd import ga, workloads
+from tests.helpers import OracleProblem, rel
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ga.load_library()
+
+
+OP_CASES = [  # dim, n (ragged tiles included), p
+    (2, 5, 1), (2, 9, 2), (2, (11, 7), 3), (2, 3, 4),
+    (3, 2, 1), (3, 5, 2), (3, (6, 5, 3), 3), (3, 4, 3), (3, 3, 4), (3, (9, 4, 5), 2),
+]
+
+
+@pytest.mark.parametrize("dim,n,p", OP_CASES)
+def test_operators_match_assembled(dim, n, p):
+    _say("operators", dim, n, p)
+    pr = OracleProblem(dim, n, p)
+    pt = ga.ga_setup_patch(dim, n, p, pr.ctrl)
+    assert pt.n_free == pr.M.shape[0]
+    rng = np.random.default_rng(7)
+    for nrhs in (1, 2, 3, 4):
+        X = rng.standard_normal((nrhs, pt.n_free))
+        x = _t(X.ravel())
+        y = torch.empty_like(x)
+        for which, A in (("M", pr.M), ("K", pr.K)):
+            ga.ga_apply_MK(pt, which, x, y, nrhs=nrhs, alpha=1.0)
+            got = _np(y).reshape(nrhs, -1)
+            for r in range(nrhs):
+                ref = A @ X[r]
+                assert rel(got[r], ref) < 1e-13, (which, nrhs, r, rel(got[r], ref))
+    d = torch.empty(pt.n_free, dtype=torch.float64, device=DEV)
+    ga.ga_diag_M(pt, d)
+    assert rel(_np(d), pr.M.diagonal()) < 1e-14
+    # alpha scaling
+    ga.ga_apply_MK(pt, "K", x[: pt.n_free], y[: pt.n_free], nrhs=1, alpha=-2.5)
+    assert rel(_np(y[: pt.n_free]), -2.5 * (pr.K @ X[0])) < 1e-13
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 9, 2), (3, 5, 3), (3, (6, 5, 3), 2), (3, 3, 4)])
+def test_preconditioner_matches_oracle(dim, n, p):
+    _say("pinv", dim, n, p)
+    pr = OracleProblem(dim, n, p)
+    pt = ga.ga_setup_patch(dim, n, p, pr.ctrl)
+    R = np.random.default_rng(3).standard_normal((2, pt.n_free))
+    r = _t(R.ravel())
+    z = torch.empty_like(r)
+    ga.ga_apply_Pinv(pt, r, z, nrhs=2)
+    got = _np(z).reshape(2, -1)
+    for i in range(2):
+        assert rel(got[i], pr.P.apply(R[i])) < 1e-12
+    ga.ga_apply_Pinv(pt, r, r, nrhs=2)  # in place
+    assert rel(_np(r).reshape(2, -1)[1], pr.P.apply(R[1])) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 16, 2), (3, 6, 3), (3, 5, 4), (3, (7, 4, 6), 2)])
+def test_mass_solve_matches_cholesky(dim, n, p):
+    _say("solve", dim, n, p)
+    pr = OracleProblem(dim, n, p)
+    pt = ga.ga_setup_patch(dim, n, p, pr.ctrl)
+    B = np.random.default_rng(11).standard_normal((3, pt.n_free))
+    b = _t(B.ravel())
+    x = torch.zeros_like(b)
+    its, relres, rc = ga.ga_mass_solve(pt, b, x, nrhs=3, rtol=1e-12)
+    got = _np(x).reshape(3, -1)
+    for i in range(3):
+        ref = pr.chol.solve(B[i])
+        assert rel(got[i], ref) < 1e-10
+        assert 1 <= its[i] <= 30 and relres[i] <= 1e-12
+    # nonzero initial guess: start from the solution -> zero iterations
+    its2, _, _ = ga.ga_mass_solve(pt, b, x, nrhs=3, rtol=1e-8)
+    assert max(its2) == 0
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 8, 2), (3, 4, 3), (3, 3, 2)])
+def test_identity_map_converges_in_one_iteration(dim, n, p):
+    _say("identity", dim, n, p)
+    ctrl = workloads.identity_ctrl(n, p, dim)
+    pt = ga.ga_setup_patch(dim, n, p, ctrl)
+    b = _t(np.random.default_rng(1).standard_normal(pt.n_free))
+    x = torch.zeros_like(b)
+    its, _, _ = ga.ga_mass_solve(pt, b, x, rtol=1e-12)
+    assert its == [1]
+
+
+def _run_gpu(pt, U0, k, rho, tau, nsteps, rtol=1e-12, guess=ga.GA_GUESS_ZERO, chunk=1):
+    integ = ga.ga_integrator_create(pt, k, rho, tau, rtol=rtol, maxit=200, guess=guess)
+    state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    U = _t(U0)
+    ga.ga_init_state(integ, U, torch.zeros_like(U), state)
+    hist = [[_np(s) for s in state]]
+    its = []
+    for _ in range(nsteps // chunk):
+        its.append(ga.ga_step(integ, state, chunk))
+        hist.append([_np(s) for s in state])
+    return hist, np.concatenate(its)
+
+
+def _compare(hist_gpu, hist_ora, k, chunk, tol, M):
+    # relative L2(Omega) error of each state field: sqrt(e^T M e) / sqrt(x^T M x)
+    def relM(a, b):
+        d = a - b
+        return np.sqrt(d @ (M @ d)) / max(np.sqrt(b @ (M @ b)), 1e-300)
+    worst = 0.0
+    for i, hg in enumerate(hist_gpu):
+        Lo = hist_ora[i * chunk]
+        for s in range(3 * k):
+            e = relM(hg[s], Lo[s - 2])
+            worst = max(worst, e)
+            assert e < tol, (i * chunk, s - 2, e)
+    return worst
+
+
+def test_step_wave2d_p2_n32_k1():
+    # the 2-D standing-wave workload: identity map, p = 2, 32 x 32, k = 1, 200 steps
+    _say("wave2d k=1")
+    pr = OracleProblem(2, 32, 2, geometry="identity")
+    tau = pr.tau()
+    U0 = workloads.standing_wave_u0(32, 2)
+    pt = ga.ga_setup_patch(2, 32, 2, pr.ctrl)
+    hist, its = _run_gpu(pt, U0, 1, 0.5, tau, 200, chunk=20)
+    ora = pr.run(U0, 0 * U0, 1, 0.5, tau, 200)
+    w = _compare(hist, ora, 1, 20, 1e-10, pr.M)
+    _say("worst rel", w, "mean its", its.mean())
+    assert its.max() <= 2  # identity map: P = M
+
+
+@pytest.mark.parametrize("k,p,n,geometry", [(2, 3, 6, "deformed"), (3, 2, 5, "deformed"),
+                                            (2, 4, 4, "random"), (1, 3, 5, "deformed"),
+                                            (4, 2, 4, "deformed")])
+def test_step_3d_matches_oracle(k, p, n, geometry):
+    _say("step3d", k, p, n, geometry)
+    pr = OracleProblem(3, n, p, geometry=geometry, seed=44)
+    tau = pr.tau()
+    U0 = workloads.grf(n, p, seed=3)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    hist, its = _run_gpu(pt, U0, k, 0.5, tau, 24, chunk=4)
+    ora = pr.run(U0, 0 * U0, k, 0.5, tau, 24)
+    w = _compare(hist, ora, k, 4, 1e-10, pr.M)
+    _say("worst rel", w, "its", its.mean())
+
+
+def test_prev_guess_same_answer():
+    pr = OracleProblem(3, 6, 3)
+    tau = pr.tau()
+    U0 = workloads.grf(6, 3, seed=9)
+    pt = ga.ga_setup_patch(3, 6, 3, pr.ctrl)
+    h0, i0 = _run_gpu(pt, U0, 2, 0.5, tau, 12, chunk=12)
+    h1, i1 = _run_gpu(pt, U0, 2, 0.5, tau, 12, guess=ga.GA_GUESS_PREV, chunk=12)
+    for s in range(6):
+        assert rel(h1[-1][s], h0[-1][s]) < 1e-10
+    assert i1.sum() <= i0.sum()
+
+
+def test_cube_p3_n64_sampled_rows():
+    # full-size 64^3, p = 3 deformed cube: operator rows and one k = 2 step,
+    # checked on sampled rows the oracle computes one by one
+    _say("cube p3 n64 sampled")
+    n, p = 64, 3
+    ctrl = workloads.deformed_cube_ctrl(n, p)
+    sp_ = operators.Space(n, p, 3)
+    pt = ga.ga_setup_patch(3, n, p, ctrl)
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([[0, 1, pt.n_free - 1], rng.integers(0, pt.n_free, 20)])
+    X = workloads.grf(n, p, seed=0)
+    x = _t(X)
+    y = torch.empty_like(x)
+    for which in ("M", "K"):
+        ga.ga_apply_MK(pt, which, x, y)
+        got = _np(y)[rows]
+        ref = operators.sampled_rows(sp_, ctrl, rows, X, which)
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+    d = torch.empty_like(x)
+    ga.ga_diag_M(pt, d)
+    np.testing.assert_allclose(_np(d)[rows], operators.sampled_rows(sp_, ctrl, rows, X, "D"), rtol=1e-13)
+    # one step at k = 2: the stage equations M X_j + K Y_j = 0 hold on the sampled rows
+    k, rho = 2, 0.5
+    lam = ga.ga_lambda_max(pt, 20)
+    tau = 0.5 * np.sqrt(ga.ga_stability_limit(rho) / lam)
+    integ = ga.ga_integrator_create(pt, k, rho, tau, rtol=1e-12, maxit=100)
+    state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(6)]
+    ga.ga_init_state(integ, x, torch.zeros_like(x), state)
+    L = {a: _np(state[a + 2]) for a in range(-2, 4)}
+    # initial data: M L^a = -K L^{a-2}
+    for a in range(0, 4):
+        lhs = operators.sampled_rows(sp_, ctrl, rows, L[a], "M")
+        rhs = -operators.sampled_rows(sp_, ctrl, rows, L[a - 2], "K")
+        assert np.max(np.abs(lhs - rhs)) < 1e-9 * np.max(np.abs(rhs)) + 1e-300
+    ga.ga_step(integ, state, 1)  # with V0 = 0 the second stage is trivial at step 1
+    L = {a: _np(state[a + 2]) for a in range(-2, 4)}
+    its = ga.ga_step(integ, state, 1)
+    Ln = {a: _np(state[a + 2]) for a in range(-2, 4)}
+    T = galpha.predictors(L, tau, k)
+    Y = galpha.stage_arguments(L, T, k)
+    prm = galpha.block_params(k, rho)
+    for j in range(k):
+        a = 3 * j
+        Xj = T[a] + prm[j][0] * (Ln[a] - T[a])  # X_j = T + alpha P, P = L_new - T
+        lhs = operators.sampled_rows(sp_, ctrl, rows, Xj, "M")
+        rhs = -operators.sampled_rows(sp_, ctrl, rows, Y[j], "K")
+        err = np.max(np.abs(lhs - rhs)) / max(np.max(np.abs(rhs)), 1e-300)
+        assert np.max(np.abs(rhs)) > 0 and err < 1e-9, (j, err)
+    # the update relations of the other 2k vectors hold exactly
+    for j, (al, be, gm, _) in enumerate(prm):
+        a = 3 * j
+        Pj = Ln[a] - T[a]
+        assert rel(Ln[a - 1], T[a - 1] + gm * tau * Pj) < 1e-12
+        assert rel(Ln[a - 2], T[a - 2] + be * tau ** 2 * Pj) < 1e-12
+    _say("its", its)
+
+
+def test_error_paths():
+    ctrl = workloads.identity_ctrl(3, 2, 2)
+    bad = ctrl.copy()
+    bad[:, 0] = -bad[:, 0]
+    with pytest.raises(ga.GAError) as e:
+        ga.ga_setup_patch(2, 3, 2, bad)
+    assert e.value.code == ga.GA_EGEOMETRY
+    with pytest.raises(ga.GAError) as e:
+        ga.ga_setup_patch(2, 3, 7, ctrl)
+    assert e.value.code == ga.GA_EINVAL
+    pt = ga.ga_setup_patch(3, 4, 3, workloads.deformed_cube_ctrl(4, 3))
+    b = _t(np.random.default_rng(0).standard_normal(pt.n_free))
+    x = torch.zeros_like(b)
+    its, rel_, rc = ga.ga_mass_solve(pt, b, x, rtol=1e-14, maxit=1, raise_on_noconv=False)
+    assert rc == ga.GA_ENOCONV and its == [1]
+    with pytest.raises(ga.GAError):
+        ga.ga_integrator_create(pt, 5, 0.5, 1e-3)
+    with pytest.raises(ga.GAError):
+        ga.ga_integrator_create(pt, 2, 1.0, 1e-3)
+
+
+def test_unstable_step_detected():
+    # tau far above the stability limit: the state grows until it is non-finite
+    pr = OracleProblem(2, 8, 2, geometry="identity")
+    pt = ga.ga_setup_patch(2, 8, 2, pr.ctrl)
+    tau = 3.0 * pr.tau(frac=1.0)
+    integ = ga.ga_integrator_create(pt, 1, 0.5, tau, rtol=1e-10)
+    U = _t(workloads.standing_wave_u0(8, 2) + 1e-3 * np.random.default_rng(0).standard_normal(pt.n_free))
+    state = [torch.zeros_like(U) for _ in range(3)]
+    ga.ga_init_state(integ, U, torch.zeros_like(U), state)
+    with pytest.raises(ga.GAError) as e:
+        for _ in range(50):
+            ga.ga_step(integ, state, 40)
+    assert e.value.code in (ga.GA_EUNSTABLE, ga.GA_ENOCONV)
