@@ -13,29 +13,34 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-ato
          "-Wno-unused-result", "-Wno-unused-command-line-argument"]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, src + ".o")
+def _compile(src, extra=(), build=None):
+    build = build or BUILD
+    obj = os.path.join(build, src + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = ["hipcc", *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build_library(verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
+def build_library(verbose=False, extra=(), out=None, build=None):
+    """Compile every source and link; `extra` adds compiler flags, `out` and
+    `build` redirect the library and object files (defaults: in-tree)."""
+    out = out or LIB
+    build = build or BUILD
+    os.makedirs(build, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, tuple(extra), build), SOURCES))
+    tmp = out + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -2,6 +2,7 @@
 // mass solves and the order-2k generalized-alpha time step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -298,7 +299,6 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, voi
   ga_patch* pt = new ga_patch();
   pt->dim = dim;
   pt->p = p;
-  const int TE = dim == 3 ? TE3 : TE2;
   long long ndof = 1;
   pt->n_free = 1;
   pt->n_tiles = 1;
@@ -306,16 +306,35 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, voi
     pt->n[a] = n_el[a];
     pt->m[a] = n_el[a] + p;
     pt->mf[a] = n_el[a] + p - 2;
-    pt->nt[a] = (n_el[a] + TE - 1) / TE;
     ndof *= pt->m[a];
     pt->n_free *= pt->mf[a];
-    pt->n_tiles *= pt->nt[a];
   }
-  long long qpt = 1;
-  for (int a = 0; a < dim; ++a) qpt *= (long long)TE * (p + 1);
-  pt->qp_per_tile = qpt;
   pt->n_quad = 1;
   for (int a = 0; a < dim; ++a) pt->n_quad *= (long long)n_el[a] * (p + 1);
+  // element padding of the univariate tables: whole tiles of every layout
+  int npad_el[3] = {1, 1, 1};
+  if (dim == 3) {
+    const int tk = te3_stiff(p), tm = te3_mass(p), q = p + 1;
+    for (int a = 0; a < 2; ++a) {
+      pt->ntk[a] = (n_el[a] + tk - 1) / tk;
+      pt->ntm[a] = (n_el[a] + tm - 1) / tm;
+      npad_el[a] = std::max(pt->ntk[a] * tk, pt->ntm[a] * tm);
+    }
+    npad_el[2] = n_el[2];
+    const size_t qz = (size_t)n_el[2] * q;
+    pt->nW = (size_t)pt->ntm[0] * pt->ntm[1] * (tm * q) * (tm * q) * qz;
+    pt->nG = (size_t)pt->ntk[0] * pt->ntk[1] * (tk * q) * (tk * q) * qz * 6;
+  } else {
+    const int q = p + 1;
+    for (int a = 0; a < 2; ++a) {
+      pt->nt[a] = (n_el[a] + TE2 - 1) / TE2;
+      npad_el[a] = pt->nt[a] * TE2;
+      pt->n_tiles *= pt->nt[a];
+    }
+    pt->qp_per_tile = (long long)(TE2 * q) * (TE2 * q);
+    pt->nW = (size_t)pt->n_tiles * pt->qp_per_tile;
+    pt->nG = pt->nW * 3;
+  }
   int rc = GA_OK;
   auto fail = [&](int code) { ga_destroy_patch(pt); return code; };
   // univariate tables, padded to whole tiles with zeros
@@ -324,7 +343,7 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, voi
     pt->ax[a] = build_axis(n_el[a], p);
     const Axis1D& ax = pt->ax[a];
     const size_t per_el = (size_t)ax.q * (p + 1);
-    const size_t npad = (size_t)pt->nt[a] * TE;
+    const size_t npad = (size_t)npad_el[a];
     std::vector<double> B(npad * per_el, 0.0), D(npad * per_el, 0.0), B2(npad * per_el, 0.0);
     std::vector<double> w(npad * ax.q, 0.0);
     for (size_t i = 0; i < ax.B.size(); ++i) {
@@ -349,10 +368,8 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, voi
   int* dbad = nullptr;
   if ((rc = upload(&dctrl, ctrl))) { free_w(); return fail(rc); }
   if ((rc = dalloc((void**)&dbad, sizeof(int)))) { hipFree(dctrl); free_w(); return fail(rc); }
-  const size_t nqp_pad = (size_t)pt->n_tiles * qpt;
-  const int ncomp = dim == 3 ? 6 : 3;
-  if ((rc = dalloc((void**)&pt->W, nqp_pad * sizeof(double))) ||
-      (rc = dalloc((void**)&pt->G, nqp_pad * ncomp * sizeof(double))) ||
+  if ((rc = dalloc((void**)&pt->W, pt->nW * sizeof(double))) ||
+      (rc = dalloc((void**)&pt->G, pt->nG * sizeof(double))) ||
       (rc = dalloc((void**)&pt->diagM, pt->n_free * sizeof(double))) ||
       (rc = dalloc((void**)&pt->s, pt->n_free * sizeof(double))) ||
       (rc = dalloc((void**)&pt->red, sizeof(double) * 32 * RED_BLOCKS)) ||
@@ -368,6 +385,8 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, voi
   }
   int hbad = 0;
   hipMemsetAsync(dbad, 0, sizeof(int), st);
+  hipMemsetAsync(pt->W, 0, pt->nW * sizeof(double), st);  // padding stays zero
+  hipMemsetAsync(pt->G, 0, pt->nG * sizeof(double), st);
   const double* wp[3] = {wdev[0], wdev[1], wdev[2]};
   int lrc = dim == 3 ? launch_geo3d(pt, dctrl, wp, dbad, st) : launch_geo2d(pt, dctrl, wp, dbad, st);
   if (check_launch(lrc, "geometry")) { hipFree(dctrl); hipFree(dbad); free_w(); return fail(GA_EDEVICE); }

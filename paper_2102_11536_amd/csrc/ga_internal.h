@@ -24,7 +24,13 @@ void basis_on_element(int n, int p, int e, double x, double* val, double* der);
 
 // Element tile of the sum-factorised operator kernels: TE elements per
 // direction, quadrature factors stored tile by tile.
-constexpr int TE3 = 4;   // 3-D tile: 4 x 4 x 4 elements
+// 3-D: elements per xy-column edge of the stiffness and the mass kernels
+// (at most 1024 threads = (TE*(p+1))^2 per workgroup)
+constexpr int te3_stiff(int p) { return 4; }
+#ifndef GA_TE3_MASS
+#define GA_TE3_MASS 4
+#endif
+constexpr int te3_mass(int p) { return (p + 1) * GA_TE3_MASS > 32 ? 32 / (p + 1) : GA_TE3_MASS; }
 constexpr int TE2 = 8;   // 2-D tile: 8 x 8 elements
 
 void set_error(const std::string& msg);
@@ -34,15 +40,18 @@ void set_error(const std::string& msg);
 struct ga_patch {
   int dim = 0, p = 0;
   int n[3] = {1, 1, 1}, m[3] = {1, 1, 1}, mf[3] = {1, 1, 1};
-  int nt[3] = {1, 1, 1};          // element tiles per direction
+  int nt[3] = {1, 1, 1};          // element tiles per direction (2-D kernels)
+  int ntk[2] = {1, 1}, ntm[2] = {1, 1};  // 3-D xy columns: stiffness and mass layouts
+  int ze = 0;                     // element layers per workgroup along z (0: automatic)
   long long n_free = 0, n_quad = 0, n_tiles = 0, qp_per_tile = 0;
   ga::Axis1D ax[3];
   // device data
   double* tabB[3] = {nullptr, nullptr, nullptr};   // [n_pad][q][p+1]
   double* tabD[3] = {nullptr, nullptr, nullptr};
   double* tabB2[3] = {nullptr, nullptr, nullptr};  // squared values (diag(M))
-  double* W = nullptr;        // [tiles][qp]   w |det J|
-  double* G = nullptr;        // [tiles][qz][ncomp][qy][qx]  w |det J| J^-1 J^-T
+  double* W = nullptr;        // w |det J|            (3-D: mass-kernel column layout)
+  double* G = nullptr;        // w |det J| J^-1 J^-T  (3-D: stiffness-kernel column layout)
+  size_t nW = 0, nG = 0;      // entries
   double* diagM = nullptr;    // [n_free]
   double* s = nullptr;        // [n_free] (Dhat/D)^(1/2)
   double* Minv[3] = {nullptr, nullptr, nullptr};   // [mf][mf]

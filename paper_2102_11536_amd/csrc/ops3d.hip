@@ -2,19 +2,32 @@
 //
 //   y += alpha * B^T diag(W) B x                        (mass, eq. mass_matrix)
 //   y += alpha * sum_ab D_a^T diag(G_ab) D_b x           (stiffness, K of eq. mp)
-//   y  = (B o B)^T W                                     (diag(M), the D of Sec. 5.4)
+//   y += (B o B)^T W                                     (diag(M), the D of Sec. 5.4)
 //
 // with B = Bz (x) By (x) Bx the tensor basis at the Gauss points and
-// W = w|det J|, G = w|det J| J^{-1} J^{-T} stored per quadrature point.
+// W = w|det J|, G = w|det J| J^{-1} J^{-T} stored per Gauss point.
 //
-// One workgroup owns a tile of TE^3 elements; its (TE*Q)^2 threads each own
-// one (qx, qy) column of Gauss points through the tile's z extent (Q = p+1
-// points per element).  Per tile: the (TE+p)^3 coefficient box is staged in
-// LDS, contracted along x in LDS, along y and z in registers; the factor
-// stream (W or G) is read once, coalesced, in the tile-major layout written
-// by the setup kernel; the transposed contractions run back z (registers),
-// y and x (LDS, plane by plane), and the box is added to the output with
-// FP64 atomics (neighbouring tiles share p coefficient layers).
+// Design (z-marching): one workgroup owns an xy column of TE x TE elements
+// and a range of element layers along z.  Its (TE*Q)^2 threads each own one
+// (qx, qy) line of Gauss points (Q = p+1 per element).  The workgroup marches
+// up its z range one Gauss layer at a time and keeps the p+1 coefficient
+// planes the current element layer touches in registers:
+//   forward   a new coefficient plane (prefetched one element layer ahead)
+//             is staged in LDS, contracted along x (LDS) and along y
+//             (registers) into c[f][p] for the fields f needed at the Gauss
+//             points (value; or x-, y-derivatives and value);
+//   z sweep   per Gauss layer: contraction along z, the 1 or 6 quadrature
+//             factors (a small ring prefetches the next layers; the factor
+//             stream is contiguous along z, read once, fully coalesced) and
+//             the transposed z contraction into accumulators s[f][p];
+//   backward  the plane no later layer touches is finished: transposed y and
+//             x contractions as dense products with zero-padded transposed
+//             basis tables in LDS, then FP64 atomic adds into y (xy
+//             neighbours and the two ends of a z range share planes).
+// The stiffness kernel uses 4x4-element columns (6 factors per point, high
+// register use); the mass kernels use wider columns so the fixed per-plane
+// work is spread over more Gauss points.
+// Factor layout: [xy tile][qz over the whole z extent][component][qy][qx].
 #include <hip/hip_runtime.h>
 
 #include "ga_internal.h"
@@ -22,10 +35,10 @@
 
 namespace ga {
 
-template <int P>
+template <int P, int TE_>
 struct Tile3 {
   static constexpr int Q = P + 1;
-  static constexpr int TE = TE3;
+  static constexpr int TE = TE_;
   static constexpr int QT = TE * Q;      // Gauss points per tile edge
   static constexpr int NB = TE + P;      // coefficients per tile edge
   static constexpr int NT = QT * QT;     // threads per workgroup
@@ -33,7 +46,7 @@ struct Tile3 {
 };
 
 struct Geo3 {
-  int n[3], m[3], mf[3], nt[3];
+  int n[3], m[3], mf[3], nt[2];
 };
 
 // index of a full-grid coefficient (i0,i1,i2) in the free vector, or -1
@@ -43,266 +56,450 @@ __device__ __forceinline__ long long free_index3(const Geo3& g, int i0, int i1, 
   return (long long)f0 + (long long)g.mf[0] * (f1 + (long long)g.mf[1] * f2);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical tiles so xy/z neighbours share its L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned nwg) {
+  const unsigned nx = 8;
+  const unsigned per = nwg / nx, rem = nwg % nx;
+  const unsigned xcd = bid % nx, loc = bid / nx;
+  const unsigned base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+  return base + loc;
+}
+
+#ifndef GA_OP3_WAVES_K
+#define GA_OP3_WAVES_K 2
+#endif
+#ifndef GA_OP3_WAVES_M
+#define GA_OP3_WAVES_M 1
+#endif
+
 // MODE: 0 mass, 1 stiffness, 2 diag(M) (tables hold squared values, x unused)
-template <int P, int MODE, int NR>
-__global__ void __launch_bounds__(Tile3<P>::NT)
+template <int P, int TE, int MODE, int NR>
+__global__ void __launch_bounds__((Tile3<P, TE>::NT), (MODE == 1 ? GA_OP3_WAVES_K : GA_OP3_WAVES_M))
 op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
             const double* __restrict__ fac,
             const double* __restrict__ tB0, const double* __restrict__ tB1,
             const double* __restrict__ tB2, const double* __restrict__ tD0,
             const double* __restrict__ tD1, const double* __restrict__ tD2,
-            Geo3 g, long long n_free, double alpha) {
-  using T = Tile3<P>;
-  constexpr int Q = T::Q, QT = T::QT, NB = T::NB, NT = T::NT, TE = T::TE;
-  constexpr int NPL = NB * NB;                  // coefficients per box plane
+            Geo3 g, int ze, long long n_free, double alpha) {
+  using T = Tile3<P, TE>;
+  constexpr int Q = T::Q, QT = T::QT, NB = T::NB, NT = T::NT;
+  constexpr int NPL = NB * NB;                  // coefficients per plane of the box
+  constexpr int NF = (MODE == 1) ? 3 : 1;       // fields at the Gauss points
   constexpr int NA = (MODE == 1) ? 2 : 1;       // x-contracted fields
-  constexpr int NG = (MODE == 1) ? 3 : 1;       // fields at Gauss points
-  constexpr int FWD = NB * NB * NB + NA * NB * NB * QT;
-  constexpr int BWD = NG * QT * QT + 2 * NB * QT;
-  constexpr int WORK = (FWD > BWD ? FWD : BWD);
+  constexpr int NRF = (MODE == 1) ? 2 : 1;      // y-back-contracted fields
+  constexpr int NC = (MODE == 1) ? 6 : 1;       // factor components per Gauss point
+  constexpr int XPR = (NR * NPL + NT - 1) / NT; // prefetched plane values per thread
+  constexpr int QP = QT + 1;                    // padded LDS row (no bank conflicts)
 
-  __shared__ double sB[3][T::TAB];
-  __shared__ double sD[3][T::TAB];
-  __shared__ double work[NR][WORK];
+  __shared__ double sB[2][T::TAB];
+  __shared__ double sD[2][T::TAB];
+  // x tables by local index: xB[a][q] = value of basis ex(q)+a at tile Gauss point q
+  __shared__ double xB[P + 1][QT];
+  __shared__ double xD[P + 1][QT];
+  // transposed, zero-padded: tBs[a][i * QP + q] = basis i of the box at tile Gauss point q
+  __shared__ double tBs[2][NB * QP];
+  __shared__ double tDs[2][NB * QP];
+  __shared__ double Xs[NR][NPL];
+  __shared__ double As[NR][NA][NB * QT];
+  __shared__ double Ss[NR][NF][NT];
+  __shared__ double Rs[NR][NRF][NB * QP];
 
   const int tid = threadIdx.x;
   const int qx = tid % QT, qy = tid / QT;
-  const long long tile = blockIdx.x;
-  const int tx = (int)(tile % g.nt[0]);
-  const int ty = (int)((tile / g.nt[0]) % g.nt[1]);
-  const int tz = (int)(tile / ((long long)g.nt[0] * g.nt[1]));
-  const int e0[3] = {tx * TE, ty * TE, tz * TE};
+  const unsigned lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntxy = g.nt[0] * g.nt[1];
+  const int txy = (int)(lid % ntxy);
+  const int zc = (int)(lid / ntxy);
+  const int tx = txy % g.nt[0], ty = txy / g.nt[0];
+  const int e0x = tx * TE, e0y = ty * TE;
+  const int ez0 = zc * ze;
+  const int ez1 = min(ez0 + ze, g.n[2]);
+  const int qz_tot = g.n[2] * Q;
 
-  // element tables of this tile
   for (int i = tid; i < T::TAB; i += NT) {
-    sB[0][i] = tB0[(size_t)e0[0] * Q * (P + 1) + i];
-    sB[1][i] = tB1[(size_t)e0[1] * Q * (P + 1) + i];
-    sB[2][i] = tB2[(size_t)e0[2] * Q * (P + 1) + i];
+    sB[0][i] = tB0[(size_t)e0x * Q * (P + 1) + i];
+    sB[1][i] = tB1[(size_t)e0y * Q * (P + 1) + i];
     if (MODE == 1) {
-      sD[0][i] = tD0[(size_t)e0[0] * Q * (P + 1) + i];
-      sD[1][i] = tD1[(size_t)e0[1] * Q * (P + 1) + i];
-      sD[2][i] = tD2[(size_t)e0[2] * Q * (P + 1) + i];
+      sD[0][i] = tD0[(size_t)e0x * Q * (P + 1) + i];
+      sD[1][i] = tD1[(size_t)e0y * Q * (P + 1) + i];
     }
   }
-
-  __syncthreads();
+  for (int i = tid; i < 2 * NB * QT; i += NT) {
+    const int ax = i / (NB * QT), b = i % (NB * QT);
+    const int ib = b / QT, q = b % QT;
+    const int el = q / Q, jq = q % Q, a = ib - el;
+    const double* tb = ax == 0 ? tB0 + (size_t)e0x * Q * (P + 1) : tB1 + (size_t)e0y * Q * (P + 1);
+    const double* td = ax == 0 ? tD0 + (size_t)e0x * Q * (P + 1) : tD1 + (size_t)e0y * Q * (P + 1);
+    const bool in = a >= 0 && a <= P;
+    tBs[ax][ib * QP + q] = in ? tb[(el * Q + jq) * (P + 1) + a] : 0.0;
+    tDs[ax][ib * QP + q] = (in && MODE == 1) ? td[(el * Q + jq) * (P + 1) + a] : 0.0;
+  }
+  for (int i = tid; i < (P + 1) * QT; i += NT) {
+    const int a = i / QT, q = i % QT;
+    xB[a][q] = tB0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a];
+    xD[a][q] = MODE == 1 ? tD0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a] : 0.0;
+  }
   const int eyq = qy / Q, jyq = qy % Q;
+  const double* fcol = fac + (size_t)txy * qz_tot * NC * NT + tid;
 
-  // ---- forward: box -> (qx, qy, iz) values in registers ----
-  double c0[NR][NB], cx[NR][NB], cy[NR][NB];
-  if (MODE != 2) {
-    for (int i = tid; i < NR * NB * NPL; i += NT) {
-      int r = i / (NB * NPL), b = i % (NB * NPL);
-      int ix = b % NB, iy = (b / NB) % NB, iz = b / NPL;
-      long long f = free_index3(g, e0[0] + ix, e0[1] + iy, e0[2] + iz);
-      work[r][b] = (f >= 0) ? x[(size_t)r * n_free + f] : 0.0;
-    }
-    __syncthreads();
-    // x contraction: A[r][a][iz][iy][qx]
-    for (int i = tid; i < NR * NB * NB * QT; i += NT) {
-      int r = i / (NB * NB * QT), b = i % (NB * NB * QT);
-      int q = b % QT, iy = (b / QT) % NB, iz = b / (QT * NB);
-      int ex = q / Q, jx = q % Q;
-      const double* bv = &sB[0][(ex * Q + jx) * (P + 1)];
-      const double* xs = &work[r][iz * NPL + iy * NB + ex];
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int a = 0; a <= P; ++a) s0 += bv[a] * xs[a];
-      if (MODE == 1) {
-        const double* dv = &sD[0][(ex * Q + jx) * (P + 1)];
-#pragma unroll
-        for (int a = 0; a <= P; ++a) s1 += dv[a] * xs[a];
-      }
-      double* A = &work[r][NB * NPL];
-      A[b] = s0;
-      if (MODE == 1) A[NB * NB * QT + b] = s1;
-    }
-    __syncthreads();
-    // y contraction in registers
-    const double* by = &sB[1][(eyq * Q + jyq) * (P + 1)];
-    const double* dy = &sD[1][(eyq * Q + jyq) * (P + 1)];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double* A0 = &work[r][NB * NPL];
-      const double* A1 = A0 + NB * NB * QT;
-#pragma unroll
-      for (int iz = 0; iz < NB; ++iz) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-        for (int b = 0; b <= P; ++b) {
-          double a0 = A0[(iz * NB + eyq + b) * QT + qx];
-          s0 += by[b] * a0;
-          if (MODE == 1) {
-            s1 += by[b] * A1[(iz * NB + eyq + b) * QT + qx];
-            s2 += dy[b] * a0;
-          }
-        }
-        c0[r][iz] = s0;
-        if (MODE == 1) { cx[r][iz] = s1; cy[r][iz] = s2; }
-      }
-    }
-  }
-
-  // ---- z sweep: values at Gauss points, factors, transposed z contraction ----
-  double s0[NR][NB], sx[NR][NB], sy[NR][NB];
+  double c[NR][NF][P + 1];   // forward fields of the coefficient planes ez..ez+P
+  double s[NR][NF][P + 1];   // transposed-z accumulators of the same planes
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int iz = 0; iz < NB; ++iz) { s0[r][iz] = 0.0; sx[r][iz] = 0.0; sy[r][iz] = 0.0; }
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int j = 0; j <= P; ++j) { c[r][f][j] = 0.0; s[r][f][j] = 0.0; }
 
-  const size_t tile_qp = (size_t)QT * QT * QT;
-  const double* ftile = fac + (size_t)tile * tile_qp * (MODE == 1 ? 6 : 1);
+  // prefetch of the next coefficient plane (global -> registers)
+  double xpre[XPR];
+  auto load_plane = [&](int iz) {
 #pragma unroll
-  for (int ez = 0; ez < TE; ++ez) {
+    for (int k = 0; k < XPR; ++k) {
+      const int i = tid + k * NT;
+      double v = 0.0;
+      if (i < NR * NPL) {
+        const int r = i / NPL, b = i % NPL;
+        const long long f = free_index3(g, e0x + b % NB, e0y + b / NB, iz);
+        if (f >= 0) v = x[(size_t)r * n_free + f];
+      }
+      xpre[k] = v;
+    }
+  };
+
+  // contract the prefetched plane along x (LDS) and y (registers) into c[.][.][P]
+  auto forward_plane = [&]() {
+    int lz = 0;
+    asm volatile("" : "+v"(lz));  // keep the basis-table reads below in LDS (no hoisting)
+    __syncthreads();
 #pragma unroll
-    for (int jz = 0; jz < Q; ++jz) {
-      const int qz = ez * Q + jz;
-      const double* bz = &sB[2][(ez * Q + jz) * (P + 1)];
+    for (int k = 0; k < XPR; ++k) {
+      const int i = tid + k * NT;
+      if (i < NR * NPL) Xs[i / NPL][i % NPL] = xpre[k];
+    }
+    __syncthreads();
+    for (int i = tid; i < NR * NB * QT; i += NT) {
+      const int r = i / (NB * QT), b = i % (NB * QT);
+      const int q = b % QT, iy = b / QT;
+      const int ex = q / Q, jx = q % Q;
+      const double* xs = &Xs[r][iy * NB + ex];
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int a = 0; a <= P; ++a) a0 += xB[a][q + lz] * xs[a];
+      As[r][0][b] = a0;
       if (MODE == 1) {
-        const double* dz = &sD[2][(ez * Q + jz) * (P + 1)];
-        const double* gq = ftile + (size_t)qz * 6 * QT * QT + tid;
-        const double gxx = gq[0], gxy = gq[NT], gxz = gq[2 * NT];
-        const double gyy = gq[3 * NT], gyz = gq[4 * NT], gzz = gq[5 * NT];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
+        for (int a = 0; a <= P; ++a) a1 += xD[a][q + lz] * xs[a];
+        As[r][1][b] = a1;
+      }
+    }
+    __syncthreads();
+    const double* by = &sB[1][(eyq * Q + jyq) * (P + 1) + lz];
+    const double* dy = &sD[1][(eyq * Q + jyq) * (P + 1) + lz];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+      for (int b = 0; b <= P; ++b) {
+        const double a0 = As[r][0][(eyq + b) * QT + qx];
+        v0 += by[b] * a0;
+        if (MODE == 1) {
+          v1 += by[b] * As[r][1][(eyq + b) * QT + qx];
+          v2 += dy[b] * a0;
+        }
+      }
+      if (MODE == 1) {
+        c[r][0][P] = v1;  // d/dx (to be contracted with Bz)
+        c[r][1][P] = v2;  // d/dy (Bz)
+        c[r][2][P] = v0;  // value (Dz gives d/dz)
+      } else {
+        c[r][0][P] = v0;
+      }
+    }
+  };
+
+  // finish coefficient plane iz from s[.][.][0]: transposed y and x contractions
+  auto backward_plane = [&](int iz) {
+    int lz = 0;
+    asm volatile("" : "+v"(lz));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) Ss[r][f][tid] = s[r][f][0];
+    __syncthreads();
+    for (int i = tid; i < NR * NRF * NB * QT; i += NT) {
+      const int r = i / (NRF * NB * QT), b = i % (NRF * NB * QT);
+      const int q = b % QT, iy = (b / QT) % NB, cf = b / (NB * QT);
+      const double* ty_ = &tBs[1][iy * QP + lz];
+      const double* tdy = &tDs[1][iy * QP + lz];
+      double acc = 0.0;
+      if (MODE == 1 && cf == 1) {
+#pragma unroll 4
+        for (int k = 0; k < QT; ++k)
+          acc += tdy[k] * Ss[r][1][k * QT + q] + ty_[k] * Ss[r][2][k * QT + q];
+      } else {
+#pragma unroll 4
+        for (int k = 0; k < QT; ++k) acc += ty_[k] * Ss[r][0][k * QT + q];
+      }
+      Rs[r][cf][iy * QP + q] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < NR * NPL; i += NT) {
+      const int r = i / NPL, b = i % NPL;
+      const int ix = b % NB, iy = b / NB;
+      const double* tx_ = &tBs[0][ix * QP + lz];
+      const double* tdx = &tDs[0][ix * QP + lz];
+      double acc = 0.0;
+#pragma unroll 4
+      for (int k = 0; k < QT; ++k) {
+        if (MODE == 1) acc += tdx[k] * Rs[r][0][iy * QP + k] + tx_[k] * Rs[r][1][iy * QP + k];
+        else acc += tx_[k] * Rs[r][0][iy * QP + k];
+      }
+      const long long f = free_index3(g, e0x + ix, e0y + iy, iz);
+      if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
+    }
+  };
+
+  auto shift_c_ = [&]() {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int j = 0; j < P; ++j) c[r][f][j] = c[r][f][j + 1];
+  };
+  // finish plane iz (backward) and contract the prefetched plane (forward) in
+  // one pass of three barriers: the two use disjoint LDS buffers
+  auto step_planes = [&](int iz) {
+    int lz = 0;
+    asm volatile("" : "+v"(lz));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) Ss[r][f][tid] = s[r][f][0];
+#pragma unroll
+    for (int k = 0; k < XPR; ++k) {
+      const int i = tid + k * NT;
+      if (i < NR * NPL) Xs[i / NPL][i % NPL] = xpre[k];
+    }
+    __syncthreads();
+    for (int i = tid; i < NR * NRF * NB * QT; i += NT) {
+      const int r = i / (NRF * NB * QT), b = i % (NRF * NB * QT);
+      const int q = b % QT, iy = (b / QT) % NB, cf = b / (NB * QT);
+      const double* ty_ = &tBs[1][iy * QP + lz];
+      const double* tdy = &tDs[1][iy * QP + lz];
+      double acc = 0.0;
+      if (MODE == 1 && cf == 1) {
+#pragma unroll 4
+        for (int k = 0; k < QT; ++k)
+          acc += tdy[k] * Ss[r][1][k * QT + q] + ty_[k] * Ss[r][2][k * QT + q];
+      } else {
+#pragma unroll 4
+        for (int k = 0; k < QT; ++k) acc += ty_[k] * Ss[r][0][k * QT + q];
+      }
+      Rs[r][cf][iy * QP + q] = acc;
+    }
+    for (int i = tid; i < NR * NB * QT; i += NT) {
+      const int r = i / (NB * QT), b = i % (NB * QT);
+      const int q = b % QT, iy = b / QT;
+      const int ex = q / Q, jx = q % Q;
+      const double* xs = &Xs[r][iy * NB + ex];
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int a = 0; a <= P; ++a) a0 += xB[a][q + lz] * xs[a];
+      As[r][0][b] = a0;
+      if (MODE == 1) {
+#pragma unroll
+        for (int a = 0; a <= P; ++a) a1 += xD[a][q + lz] * xs[a];
+        As[r][1][b] = a1;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < NR * NPL; i += NT) {
+      const int r = i / NPL, b = i % NPL;
+      const int ix = b % NB, iy = b / NB;
+      const double* tx_ = &tBs[0][ix * QP + lz];
+      const double* tdx = &tDs[0][ix * QP + lz];
+      double acc = 0.0;
+#pragma unroll 4
+      for (int k = 0; k < QT; ++k) {
+        if (MODE == 1) acc += tdx[k] * Rs[r][0][iy * QP + k] + tx_[k] * Rs[r][1][iy * QP + k];
+        else acc += tx_[k] * Rs[r][0][iy * QP + k];
+      }
+      const long long f = free_index3(g, e0x + ix, e0y + iy, iz);
+      if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
+    }
+    shift_c_();
+    const double* by = &sB[1][(eyq * Q + jyq) * (P + 1) + lz];
+    const double* dy = &sD[1][(eyq * Q + jyq) * (P + 1) + lz];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+      for (int b = 0; b <= P; ++b) {
+        const double a0 = As[r][0][(eyq + b) * QT + qx];
+        v0 += by[b] * a0;
+        if (MODE == 1) {
+          v1 += by[b] * As[r][1][(eyq + b) * QT + qx];
+          v2 += dy[b] * a0;
+        }
+      }
+      if (MODE == 1) {
+        c[r][0][P] = v1;
+        c[r][1][P] = v2;
+        c[r][2][P] = v0;
+      } else {
+        c[r][0][P] = v0;
+      }
+    }
+  };
+
+  auto shift_c = [&]() {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int j = 0; j < P; ++j) c[r][f][j] = c[r][f][j + 1];
+  };
+  auto shift_s = [&]() {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) s[r][f][j] = s[r][f][j + 1];
+        s[r][f][P] = 0.0;
+      }
+  };
+
+  __syncthreads();
+  if (MODE != 2) {
+    load_plane(ez0);
+#pragma unroll 1
+    for (int j = 0; j <= P; ++j) {
+      if (j > 0) shift_c();
+      forward_plane();
+      load_plane(ez0 + j + 1);   // plane ez0 + P + 1 is the first one of the march
+    }
+  }
+
+  // z sweep over Gauss layers with a ring of D prefetched factor planes
+  constexpr int D = (MODE == 1) ? 2 : 4;
+  const int q0 = ez0 * Q, q1 = ez1 * Q;
+  double gq[D][NC];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc)
+      gq[d][cc] = (q0 + d < q1) ? fcol[((size_t)(q0 + d) * NC + cc) * NT] : 0.0;
+
+  for (int qb = q0; qb < q1; qb += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int q = qb + d;
+      if (q >= q1) break;
+      const int ez = q / Q, jz = q - ez * Q;
+      double cur[NC];
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) cur[cc] = gq[d][cc];
+      if (q + D < q1) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) gq[d][cc] = fcol[((size_t)(q + D) * NC + cc) * NT];
+      }
+      const double* bzt = tB2 + ((size_t)ez * Q + jz) * (P + 1);
+      const double* dzt = tD2 + ((size_t)ez * Q + jz) * (P + 1);
+      double bz[P + 1], dz[P + 1];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) {
+        bz[a] = bzt[a];
+        if (MODE == 1) dz[a] = dzt[a];
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (MODE == 1) {
           double ux = 0.0, uy = 0.0, uz = 0.0;
 #pragma unroll
-          for (int c = 0; c <= P; ++c) {
-            ux += bz[c] * cx[r][ez + c];
-            uy += bz[c] * cy[r][ez + c];
-            uz += dz[c] * c0[r][ez + c];
+          for (int a = 0; a <= P; ++a) {
+            ux += bz[a] * c[r][0][a];
+            uy += bz[a] * c[r][1][a];
+            uz += dz[a] * c[r][2][a];
           }
-          const double fx = gxx * ux + gxy * uy + gxz * uz;
-          const double fy = gxy * ux + gyy * uy + gyz * uz;
-          const double fz = gxz * ux + gyz * uy + gzz * uz;
+          const double fx = cur[0] * ux + cur[1] * uy + cur[2] * uz;
+          const double fy = cur[1] * ux + cur[3] * uy + cur[4] * uz;
+          const double fz = cur[2] * ux + cur[4] * uy + cur[5] * uz;
 #pragma unroll
-          for (int c = 0; c <= P; ++c) {
-            sx[r][ez + c] += bz[c] * fx;
-            sy[r][ez + c] += bz[c] * fy;
-            s0[r][ez + c] += dz[c] * fz;
+          for (int a = 0; a <= P; ++a) {
+            s[r][0][a] += bz[a] * fx;
+            s[r][1][a] += bz[a] * fy;
+            s[r][2][a] += dz[a] * fz;
           }
-        }
-      } else {
-        const double wq = ftile[(size_t)qz * NT + tid];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
+        } else {
           double u = 1.0;
           if (MODE == 0) {
             u = 0.0;
 #pragma unroll
-            for (int c = 0; c <= P; ++c) u += bz[c] * c0[r][ez + c];
+            for (int a = 0; a <= P; ++a) u += bz[a] * c[r][0][a];
           }
-          const double v = wq * u;
+          const double v = cur[0] * u;
 #pragma unroll
-          for (int c = 0; c <= P; ++c) s0[r][ez + c] += bz[c] * v;
+          for (int a = 0; a <= P; ++a) s[r][0][a] += bz[a] * v;
+        }
+      }
+      if (jz == Q - 1) {
+        // plane ez is complete; the next element layer needs plane ez + 1 + P
+        if (MODE != 2 && ez + 1 < ez1) {
+          step_planes(ez);  // backward of plane ez, forward of plane ez + 1 + P
+          shift_s();
+          if (ez + 2 < ez1) load_plane(ez + 2 + P);
+        } else {
+          backward_plane(ez);
+          shift_s();
         }
       }
     }
   }
-
-  // ---- transposed y and x contractions, one coefficient plane at a time ----
-  const int ncomp = NG;
-#pragma unroll
-  for (int iz = 0; iz < NB; ++iz) {
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      double* S = &work[r][0];
-      if (MODE == 1) {
-        S[tid] = sx[r][iz];
-        S[NT + tid] = sy[r][iz];
-        S[2 * NT + tid] = s0[r][iz];
-      } else {
-        S[tid] = s0[r][iz];
-      }
-    }
-    __syncthreads();
-    // R[c][iy][qx]: c = 0 pairs with Dx (stiffness) or Bx (mass); c = 1 pairs with Bx
-    constexpr int NRV = (MODE == 1 ? 2 : 1) * NB * QT;
-    for (int i = tid; i < NR * NRV; i += NT) {
-      int r = i / NRV, b = i % NRV;
-      int q = b % QT, iy = (b / QT) % NB, c = b / (NB * QT);
-      const double* S = &work[r][0];
-      double acc = 0.0;
-#pragma unroll
-      for (int ey = 0; ey < TE; ++ey) {
-        int a = iy - ey;
-        if (a < 0 || a > P) continue;
-#pragma unroll
-        for (int jy = 0; jy < Q; ++jy) {
-          int qyy = ey * Q + jy;
-          double bvy = sB[1][(ey * Q + jy) * (P + 1) + a];
-          if (MODE == 1) {
-            if (c == 0) {
-              acc += bvy * S[qyy * QT + q];
-            } else {
-              double dvy = sD[1][(ey * Q + jy) * (P + 1) + a];
-              acc += dvy * S[NT + qyy * QT + q] + bvy * S[2 * NT + qyy * QT + q];
-            }
-          } else {
-            acc += bvy * S[qyy * QT + q];
-          }
-        }
-      }
-      work[r][ncomp * NT + b] = acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < NR * NPL; i += NT) {
-      int r = i / NPL, b = i % NPL;
-      int ix = b % NB, iy = b / NB;
-      const double* R = &work[r][ncomp * NT];
-      double acc = 0.0;
-#pragma unroll
-      for (int ex = 0; ex < TE; ++ex) {
-        int a = ix - ex;
-        if (a < 0 || a > P) continue;
-#pragma unroll
-        for (int jx = 0; jx < Q; ++jx) {
-          int q = ex * Q + jx;
-          if (MODE == 1)
-            acc += sD[0][(ex * Q + jx) * (P + 1) + a] * R[iy * QT + q] +
-                   sB[0][(ex * Q + jx) * (P + 1) + a] * R[NB * QT + iy * QT + q];
-          else
-            acc += sB[0][(ex * Q + jx) * (P + 1) + a] * R[iy * QT + q];
-        }
-      }
-      long long f = free_index3(g, e0[0] + ix, e0[1] + iy, e0[2] + iz);
-      if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
-    }
+#pragma unroll 1
+  for (int j = 0; j < P; ++j) {
+    backward_plane(ez1 + j);
+    shift_s();
   }
 }
 
-// Geometry factors at the Gauss points of one tile (setup, once per patch).
+// Geometry factors at the Gauss points of one element layer of one
+// stiffness-layout xy tile; W is written in the mass-kernel tiling.
 template <int P>
-__global__ void __launch_bounds__(Tile3<P>::NT)
+__global__ void __launch_bounds__((Tile3<P, te3_stiff(P)>::NT))
 geo3d_kernel(const double* __restrict__ ctrl,  // [3][N_dof] full grid, co-lex
              const double* __restrict__ tB0, const double* __restrict__ tB1,
              const double* __restrict__ tB2, const double* __restrict__ tD0,
              const double* __restrict__ tD1, const double* __restrict__ tD2,
              const double* __restrict__ w0, const double* __restrict__ w1,
-             const double* __restrict__ w2, Geo3 g, double* __restrict__ W,
+             const double* __restrict__ w2, Geo3 gk, int ntm0, double* __restrict__ W,
              double* __restrict__ G, int* __restrict__ bad) {
-  using T = Tile3<P>;
+  using T = Tile3<P, te3_stiff(P)>;
+  using TM = Tile3<P, te3_mass(P)>;
   constexpr int Q = T::Q, QT = T::QT, NT = T::NT, TE = T::TE;
   const int tid = threadIdx.x;
   const int qx = tid % QT, qy = tid / QT;
-  const long long tile = blockIdx.x;
-  const int tx = (int)(tile % g.nt[0]);
-  const int ty = (int)((tile / g.nt[0]) % g.nt[1]);
-  const int tz = (int)(tile / ((long long)g.nt[0] * g.nt[1]));
+  const int txy = blockIdx.x, ez = blockIdx.y;
+  const int tx = txy % gk.nt[0], ty = txy / gk.nt[0];
   const int ex = tx * TE + qx / Q, jx = qx % Q;
   const int ey = ty * TE + qy / Q, jy = qy % Q;
-  const long long ndof = (long long)g.m[0] * g.m[1] * g.m[2];
-  const size_t tile_qp = (size_t)QT * QT * QT;
-  for (int qz = 0; qz < QT; ++qz) {
-    const int ez = tz * TE + qz / Q, jz = qz % Q;
-    const size_t wi = (size_t)tile * tile_qp + (size_t)qz * NT + tid;
-    const size_t gi = (size_t)tile * tile_qp * 6 + (size_t)qz * 6 * NT + tid;
-    if (ex >= g.n[0] || ey >= g.n[1] || ez >= g.n[2]) {
-      W[wi] = 0.0;
-      for (int c = 0; c < 6; ++c) G[gi + (size_t)c * NT] = 0.0;
-      continue;
-    }
+  if (ex >= gk.n[0] || ey >= gk.n[1]) return;  // padding: W and G stay zero
+  const long long ndof = (long long)gk.m[0] * gk.m[1] * gk.m[2];
+  const int qz_tot = gk.n[2] * Q;
+  // global Gauss indices in x, y and the mass-layout position
+  const int gx = tx * QT + qx, gy = ty * QT + qy;
+  const int tm = gx / TM::QT + ntm0 * (gy / TM::QT);
+  const int lm = (gy % TM::QT) * TM::QT + gx % TM::QT;
+  for (int jz = 0; jz < Q; ++jz) {
+    const int qz = ez * Q + jz;
+    const size_t wi = ((size_t)tm * qz_tot + qz) * TM::NT + lm;
+    const size_t gi = ((size_t)txy * qz_tot + qz) * 6 * NT + tid;
     const double* bx = &tB0[((size_t)ex * Q + jx) * (P + 1)];
     const double* dx = &tD0[((size_t)ex * Q + jx) * (P + 1)];
     const double* by = &tB1[((size_t)ey * Q + jy) * (P + 1)];
@@ -313,7 +510,7 @@ geo3d_kernel(const double* __restrict__ ctrl,  // [3][N_dof] full grid, co-lex
     for (int c2 = 0; c2 <= P; ++c2)
       for (int c1 = 0; c1 <= P; ++c1)
         for (int c0 = 0; c0 <= P; ++c0) {
-          long long idx = (ex + c0) + (long long)g.m[0] * ((ey + c1) + (long long)g.m[1] * (ez + c2));
+          long long idx = (ex + c0) + (long long)gk.m[0] * ((ey + c1) + (long long)gk.m[1] * (ez + c2));
           double d0 = dx[c0] * by[c1] * bz[c2];
           double d1 = bx[c0] * dy[c1] * bz[c2];
           double d2 = bx[c0] * by[c1] * dz[c2];
@@ -338,8 +535,7 @@ geo3d_kernel(const double* __restrict__ ctrl,  // [3][N_dof] full grid, co-lex
     const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
     if (!(det > 0.0)) atomicOr(bad, 1);
     const double wq = w0[(size_t)ex * Q + jx] * w1[(size_t)ey * Q + jy] * w2[(size_t)ez * Q + jz];
-    const double wdet = wq * det;
-    W[wi] = wdet;
+    W[wi] = wq * det;
     // G = w det J^{-1} J^{-T} = (w / det) adj adj^T
     const double sc = wq / det;
     const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
@@ -351,24 +547,38 @@ geo3d_kernel(const double* __restrict__ ctrl,  // [3][N_dof] full grid, co-lex
   }
 }
 
+// element layers per workgroup: enough workgroups to fill the chip several times
+static int pick_ze(long long ntxy, int nz, int floor_ze) {
+  int ze = nz;
+  while (ze > floor_ze && ntxy * ((nz + ze - 1) / ze) < 4096) ze = (ze + 1) / 2;
+  return ze < 1 ? 1 : ze;
+}
+
 template <int P>
 static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const double* x, double* y,
                          double alpha, hipStream_t st) {
-  using T = Tile3<P>;
+  constexpr int TK = te3_stiff(P), TM = te3_mass(P);
   Geo3 g;
-  for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; g.nt[a] = pt->nt[a]; }
-  dim3 grid((unsigned)pt->n_tiles), block(T::NT);
+  for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; }
+  const int* nt = mode == 1 ? pt->ntk : pt->ntm;
+  g.nt[0] = nt[0];
+  g.nt[1] = nt[1];
+  const long long ntxy = (long long)nt[0] * nt[1];
+  const int ze = pt->ze > 0 ? pt->ze : pick_ze(ntxy, pt->n[2], mode == 1 ? 8 : 16);
+  const long long nwg = ntxy * ((pt->n[2] + ze - 1) / ze);
+  dim3 grid((unsigned)nwg);
   const double* const* B = (mode == 2) ? pt->tabB2 : pt->tabB;
   const double* fac = (mode == 1) ? pt->G : pt->W;
-#define GA_OP3(MODE, NRV)                                                                   \
-  hipLaunchKernelGGL((op3d_kernel<P, MODE, NRV>), grid, block, 0, st, x, y, fac, B[0], B[1], \
-                     B[2], pt->tabD[0], pt->tabD[1], pt->tabD[2], g, pt->n_free, alpha)
+#define GA_OP3(TE, MODE, NRV)                                                               \
+  hipLaunchKernelGGL((op3d_kernel<P, TE, MODE, NRV>), grid, dim3(Tile3<P, TE>::NT), 0, st,   \
+                     x, y, fac, B[0], B[1], B[2], pt->tabD[0], pt->tabD[1], pt->tabD[2], g,   \
+                     ze, pt->n_free, alpha)
   if (mode == 0) {
-    if (nr == 1) GA_OP3(0, 1); else if (nr == 2) GA_OP3(0, 2); else GA_OP3(0, 3);
+    if (nr == 1) GA_OP3(TM, 0, 1); else if (nr == 2) GA_OP3(TM, 0, 2); else GA_OP3(TM, 0, 3);
   } else if (mode == 1) {
-    if (nr == 1) GA_OP3(1, 1); else if (nr == 2) GA_OP3(1, 2); else GA_OP3(1, 3);
+    if (nr == 1) GA_OP3(TK, 1, 1); else if (nr == 2) GA_OP3(TK, 1, 2); else GA_OP3(TK, 1, 3);
   } else {
-    GA_OP3(2, 1);
+    GA_OP3(TM, 2, 1);
   }
 #undef GA_OP3
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -388,11 +598,14 @@ int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y
 int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
                  hipStream_t st) {
   Geo3 g;
-  for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; g.nt[a] = pt->nt[a]; }
+  for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; }
+  g.nt[0] = pt->ntk[0];
+  g.nt[1] = pt->ntk[1];
+  dim3 grid((unsigned)(pt->ntk[0] * pt->ntk[1]), (unsigned)pt->n[2]);
 #define GA_GEO3(PP)                                                                           \
-  hipLaunchKernelGGL(geo3d_kernel<PP>, dim3((unsigned)pt->n_tiles), dim3(Tile3<PP>::NT), 0, st, \
-                     ctrl, pt->tabB[0], pt->tabB[1], pt->tabB[2], pt->tabD[0], pt->tabD[1],    \
-                     pt->tabD[2], w[0], w[1], w[2], g, pt->W, pt->G, bad)
+  hipLaunchKernelGGL(geo3d_kernel<PP>, grid, dim3(Tile3<PP, te3_stiff(PP)>::NT), 0, st, ctrl,  \
+                     pt->tabB[0], pt->tabB[1], pt->tabB[2], pt->tabD[0], pt->tabD[1],          \
+                     pt->tabD[2], w[0], w[1], w[2], g, pt->ntm[0], pt->W, pt->G, bad)
   switch (pt->p) {
     case 1: GA_GEO3(1); break;
     case 2: GA_GEO3(2); break;
@@ -403,7 +616,5 @@ int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w,
 #undef GA_GEO3
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-
-int tile_threads3(int p) { return (TE3 * (p + 1)) * (TE3 * (p + 1)); }
 
 }  // namespace ga
