@@ -24,6 +24,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stiffness_apply_p3_n128_k2_traffic.txt")
+
+
+def measured_traffic():
+    """HBM bytes per stiffness launch from the committed counter summary, or
+    None if the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = dict(l.split("=", 1) for l in open(TRAFFIC_FILE).read().splitlines()
+                  if "=" in l and not l.startswith("#"))
+    except OSError:
+        return None
+    src = open(os.path.join(ROOT, "paper_2102_11536_amd", "csrc", "ops3d.hip"), "rb").read()
+    if kv.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -68,6 +84,10 @@ def main():
     ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--profile-ops", default="",
+                    help="counter-collection mode: run only these operator applies (e.g. K2,M2), "
+                         "three times each, then a 1 GiB device copy used to calibrate "
+                         "FETCH_SIZE/WRITE_SIZE, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
@@ -84,6 +104,19 @@ def main():
     U0 = workloads.grf(n, p, seed=2000)
     log("[bench] setup")
     pt = ga.ga_setup_patch(3, n, p, ctrl)
+    if args.profile_ops:
+        x = torch.as_tensor(np.concatenate([U0] * k), device=dev)
+        y = torch.empty_like(x)
+        for op in args.profile_ops.split(","):
+            for _ in range(3):
+                ga.ga_apply_MK(pt, op[0], x, y, nrhs=int(op[1:]))
+        a = torch.empty(2 ** 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] profile-ops done")
+        return
     lam = ga.ga_lambda_max(pt, 25)
     theta_s = ga.ga_stability_limit(rho)
     tau = 0.5 * np.sqrt(theta_s / lam)
@@ -144,7 +177,7 @@ def main():
                    "path": "fp64_pcg_zero_guess",
                    "pcg_iters_mean": float(np.mean(its)), "pcg_iters_max": int(np.max(its))},
         "roofline": {"bound": "hbm", "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": k_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": k_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "op3d_kernel<3,1,2> (stiffness apply, k right-hand sides)",
                      "avg_launch_ms": k_avg * 1e3, "algorithmic_bytes": k_bytes,
                      "mass_apply": {"achieved": m_gbs, "avg_launch_ms": m_avg * 1e3,
