@@ -43,7 +43,12 @@ enum {
   GA_EUNSTABLE = -6   /* a state norm became non-finite during stepping   */
 };
 
-enum { GA_FP64 = 0 };                /* arithmetic of operator applies      */
+/* Arithmetic of the mass solves.  GA_FP64: PCG in FP64 throughout.  GA_FP32:
+ * FP64 iterative refinement (residual r = b - M x with FP64 factors, FP64
+ * dot products and norms, FP64 solution) around an inner FP32 flexible PCG
+ * (FP32 mass factors, vectors and preconditioner; dots accumulated in FP64).
+ * The stiffness apply and the state update are FP64 in both modes. */
+enum { GA_FP64 = 0, GA_FP32 = 1 };
 enum { GA_GUESS_ZERO = 0, GA_GUESS_PREV = 1 }; /* CG initial guess in ga_step */
 
 /*
@@ -95,11 +100,14 @@ int ga_apply_Pinv(ga_patch* patch, int nrhs, const double* r_dev, double* z_dev,
  * paper's null guess) and the solutions on return.  Each right-hand side
  * stops when sqrt(r^T P^{-1} r) <= rtol * sqrt(b^T P^{-1} b); converged
  * right-hand sides are frozen while the others continue.
+ *   prec   GA_FP64 or GA_FP32 (3-D only; see above).  With GA_FP32 the
+ *          stopping test uses P^{-1} applied in FP32 and iters_out counts the
+ *          inner FP32 iterations.
  *   iters_out[nrhs], relres_out[nrhs]  host arrays or NULL.
  * Returns GA_ENOCONV if any right-hand side did not converge in maxit.
  */
 int ga_mass_solve(ga_patch* patch, int nrhs, const double* b_dev, double* x_dev,
-                  double rtol, int maxit, int* iters_out, double* relres_out,
+                  double rtol, int maxit, int prec, int* iters_out, double* relres_out,
                   void* stream);
 
 /*
@@ -114,11 +122,12 @@ double ga_stability_limit(double rho);
 
 /*
  * ga_integrator_create -- the order-2k scheme of Sec. 4 (k = 1, 2, 3, 4) with
- * rho_b = rho_s = rho in [0, 1), step tau > 0, PCG tolerance rtol and maxit.
+ * rho_b = rho_s = rho in [0, 1), step tau > 0, PCG tolerance rtol and maxit,
+ * mass-solve arithmetic prec (GA_FP64 or GA_FP32).
  * State vectors are L^a, a = -2 .. 3k-3 (U, V, A, then time derivatives of A).
  */
 int ga_integrator_create(ga_patch* patch, int k, double rho, double tau, double rtol,
-                         int maxit, int guess_mode, ga_integrator** out);
+                         int maxit, int prec, int guess_mode, ga_integrator** out);
 int ga_integrator_destroy(ga_integrator* integ);
 
 /*

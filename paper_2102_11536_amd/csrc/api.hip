@@ -142,12 +142,30 @@ int op_apply(ga_patch* pt, int mode, int nr, double alpha, const double* x, doub
   return GA_OK;
 }
 
-// z = P^{-1} r using two scratch vectors t0, t1 (each nr * n_free)
+// z = P^{-1} r using two scratch vectors t0, t1 (each nr * n_free): one dense
+// contraction per axis, the scaling folded into the first and last pass
+// (generic GEMM passes for axes longer than 256)
 int pinv_apply(ga_patch* pt, int nr, const double* r, double* z, double* t0, double* t1,
                hipStream_t st) {
   const size_t n = pt->n_free;
   const int m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
   ProfScope prof(2, st);
+  const bool fast = pinv_axis_supported(m0) && pinv_axis_supported(m1) &&
+                    (pt->dim == 2 || pinv_axis_supported(m2));
+  if (fast) {
+    launch_pinv_contig<double>(r, t1, pt->Minv[0], m0, (long long)nr * m1 * m2, (long long)m1 * m2,
+                       (long long)n, pt->s, nullptr, st);
+    if (pt->dim == 2) {
+      launch_pinv_strided<double>(t1, z, pt->Minv[1], m1, m0, m0, 0, 1, (long long)n, nr, nullptr,
+                          pt->s, st);
+    } else {
+      launch_pinv_strided<double>(t1, t0, pt->Minv[1], m1, m0, m0, (long long)m0 * m1, m2, (long long)n,
+                          nr, nullptr, nullptr, st);
+      launch_pinv_strided<double>(t0, z, pt->Minv[2], m2, (long long)m0 * m1, (long long)m0 * m1, 0, 1,
+                          (long long)n, nr, nullptr, pt->s, st);
+    }
+    return check_launch(0, "preconditioner");
+  }
   launch_scale_mul(t0, r, pt->s, nr, n, st);
   // x axis: rows of length m0:  t1[row][i] = sum_j t0[row][j] Ax[j][i]  (Ax symmetric)
   launch_gemm((int)((size_t)nr * m1 * m2), m0, m0, t0, m0, 0, pt->Minv[0], m0, 0, t1, m0, 0, 1, st);
@@ -256,6 +274,154 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
     return GA_ENOCONV;
   }
   return GA_OK;
+}
+
+// ---- mixed precision: FP32 inner PCG inside an FP64 iterative refinement ----
+
+// FP32 copies of W, the 1-D inverses and the scaling (built on first use)
+int ensure_mixed(ga_patch* pt, hipStream_t st) {
+  if (pt->W32) return GA_OK;
+  if (pt->dim != 3) { set_error("mixed precision needs a 3-D patch"); return GA_EINVAL; }
+  int rc;
+  if ((rc = dalloc((void**)&pt->W32, pt->nW * sizeof(float))) ||
+      (rc = dalloc((void**)&pt->s32, pt->n_free * sizeof(float))))
+    return rc;
+  launch_to_f32(pt->W32, pt->W, pt->nW, st);
+  launch_to_f32(pt->s32, pt->s, pt->n_free, st);
+  for (int a = 0; a < 3; ++a) {
+    const size_t mm = (size_t)pt->mf[a] * pt->mf[a];
+    if ((rc = dalloc((void**)&pt->Minv32[a], mm * sizeof(float)))) return rc;
+    launch_to_f32(pt->Minv32[a], pt->Minv[a], mm, st);
+  }
+  return check_launch(0, "mixed-precision setup");
+}
+
+int pinv_apply_f32(ga_patch* pt, int nr, const float* r, float* z, float* t0, float* t1,
+                   hipStream_t st) {
+  const size_t n = pt->n_free;
+  const int m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
+  if (!(pinv_axis_supported(m0) && pinv_axis_supported(m1) && pinv_axis_supported(m2))) {
+    set_error("mixed precision supports axes of at most 256 free coefficients");
+    return GA_EINVAL;
+  }
+  ProfScope prof(2, st);
+  launch_pinv_contig<float>(r, t1, pt->Minv32[0], m0, (long long)nr * m1 * m2,
+                            (long long)m1 * m2, (long long)n, pt->s32, nullptr, st);
+  launch_pinv_strided<float>(t1, t0, pt->Minv32[1], m1, m0, m0, (long long)m0 * m1, m2,
+                             (long long)n, nr, nullptr, nullptr, st);
+  launch_pinv_strided<float>(t0, z, pt->Minv32[2], m2, (long long)m0 * m1, (long long)m0 * m1, 0,
+                             1, (long long)n, nr, nullptr, pt->s32, st);
+  return check_launch(0, "FP32 preconditioner");
+}
+
+int mass_apply_f32(ga_patch* pt, int nr, const float* x, float* y, hipStream_t st) {
+  launch_fill_f32(y, (size_t)nr * pt->n_free, st);
+  for (int r0 = 0; r0 < nr; r0 += MAX_NR) {
+    const int c = nr - r0 < MAX_NR ? nr - r0 : MAX_NR;
+    ProfScope prof(0, st);
+    int rc = launch_mass3d_f32(c, pt, x + (size_t)r0 * pt->n_free, y + (size_t)r0 * pt->n_free,
+                               1.0f, st);
+    if (check_launch(rc, "FP32 mass apply")) return GA_EDEVICE;
+  }
+  return GA_OK;
+}
+
+int read_scalars(ga_patch* pt, int nr, hipStream_t st) {
+  GA_TRY_HIP(hipMemcpyAsync(pt->host_scal, pt->scal, sizeof(double) * NSCAL * nr,
+                            hipMemcpyDeviceToHost, st));
+  GA_TRY_HIP(hipStreamSynchronize(st));
+  return GA_OK;
+}
+
+// Outer FP64 refinement: r = b - M x (FP64 factors and arithmetic), stop when
+// sqrt(r^T P^{-1} r) <= rtol sqrt(b^T P^{-1} b) (P^{-1} applied in FP32, dots in
+// FP64); each correction M d = r comes from an FP32 flexible PCG (FP32 factors,
+// vectors and preconditioner) that reduces its residual by inner_tol.
+int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, int maxit,
+                     bool zero_guess, int* iters_out, double* relres_out, hipStream_t st) {
+  const size_t n = pt->n_free;
+  const size_t tot = (size_t)nr * n;
+  int rc = ensure_mixed(pt, st);
+  if (rc) return rc;
+  if ((rc = ensure_work(pt, 6 * nr))) return rc;
+  double* r64 = pt->work;
+  float* f = reinterpret_cast<float*>(pt->work + tot);
+  float *r32 = f, *z32 = f + tot, *p32 = f + 2 * tot, *q32 = f + 3 * tot, *d32 = f + 4 * tot,
+        *t0 = f + 5 * tot, *t1 = f + 6 * tot;
+  double* partA = pt->red;
+  double* partB = pt->red + (size_t)16 * RED_BLOCKS;
+  const double inner_tol = 1e-4;
+  // outer residual and the norm of b
+  launch_copy(r64, b, tot, st);
+  if (zero_guess) launch_fill(x, 0.0, tot, st);
+  else if ((rc = op_apply(pt, 0, nr, -1.0, x, r64, st))) return rc;
+  launch_to_f32(r32, b, tot, st);
+  if ((rc = pinv_apply_f32(pt, nr, r32, z32, t0, t1, st))) return rc;
+  launch_dot_df(nr, b, z32, n, partB, st);
+  std::vector<double> bn2(nr), rz(nr);
+  launch_sum_partials(nr, partB, pt->scal, st);
+  if ((rc = read_scalars(pt, nr, st))) return rc;
+  for (int r = 0; r < nr; ++r) bn2[r] = pt->host_scal[r];
+  int inner_total[16] = {0};
+  bool conv = false;
+  for (int outer = 0; outer < 50; ++outer) {
+    launch_to_f32(r32, r64, tot, st);
+    if ((rc = pinv_apply_f32(pt, nr, r32, z32, t0, t1, st))) return rc;
+    launch_dot_df(nr, r64, z32, n, partA, st);
+    launch_sum_partials(nr, partA, pt->scal, st);
+    if ((rc = read_scalars(pt, nr, st))) return rc;
+    bool all = true;
+    for (int r = 0; r < nr; ++r) {
+      rz[r] = pt->host_scal[r];
+      if (bn2[r] > 0.0 && rz[r] > rtol * rtol * bn2[r]) all = false;
+    }
+    int used = 0;
+    for (int r = 0; r < nr; ++r) used = std::max(used, inner_total[r]);
+    if (all) { conv = true; break; }
+    if (used >= maxit) break;
+    // inner FP32 flexible PCG for M d = r, d0 = 0: z32 already holds P^{-1} r
+    launch_fill_f32(d32, tot, st);
+    launch_dot_ff(nr, r32, z32, n, partA, st);
+    launch_cg_start(nr, partA, nullptr, pt->scal, inner_tol * inner_tol, st);
+    launch_copy_f32(p32, z32, tot, st);
+    for (int it = 0; it < 20; ++it) {
+      if ((rc = read_scalars(pt, nr, st))) return rc;
+      bool any = false;
+      for (int r = 0; r < nr; ++r) any |= pt->host_scal[r * NSCAL + S_ACTIVE] != 0.0;
+      if (!any) break;
+      if ((rc = mass_apply_f32(pt, nr, p32, q32, st))) return rc;
+      launch_dot_ff(nr, p32, q32, n, partA, st);
+      launch_cg_alpha(nr, partA, pt->scal, st);
+      launch_cg_xr_f32(nr, d32, r32, p32, q32, pt->scal, n, st);
+      if ((rc = pinv_apply_f32(pt, nr, r32, z32, t0, t1, st))) return rc;
+      launch_dot2_f32(nr, r32, z32, q32, n, partA, partB, st);
+      launch_cg_beta_flex(nr, partA, partB, pt->scal, st);
+      launch_cg_p_f32(nr, p32, z32, pt->scal, n, st);
+      if (check_launch(0, "inner PCG")) return GA_EDEVICE;
+    }
+    if ((rc = read_scalars(pt, nr, st))) return rc;
+    for (int r = 0; r < nr; ++r) inner_total[r] += (int)pt->host_scal[r * NSCAL + S_ITERS];
+    // x += d; r = b - M x in FP64
+    launch_add_f32(x, d32, tot, st);
+    launch_copy(r64, b, tot, st);
+    if ((rc = op_apply(pt, 0, nr, -1.0, x, r64, st))) return rc;
+  }
+  for (int r = 0; r < nr; ++r) {
+    if (iters_out) iters_out[r] = inner_total[r];
+    if (relres_out) relres_out[r] = bn2[r] > 0 ? std::sqrt(std::fabs(rz[r] / bn2[r])) : 0.0;
+  }
+  if (!conv) {
+    set_error("mixed-precision solve did not converge within maxit");
+    return GA_ENOCONV;
+  }
+  return GA_OK;
+}
+
+int solve_any(ga_patch* pt, int nr, const double* b, double* x, double rtol, int maxit, int prec,
+              bool zero_guess, int* iters_out, double* relres_out, hipStream_t st) {
+  if (prec == GA_FP32)
+    return solve_mixed_impl(pt, nr, b, x, rtol, maxit, zero_guess, iters_out, relres_out, st);
+  return solve_impl(pt, nr, b, x, rtol, maxit, zero_guess, iters_out, relres_out, st);
 }
 
 }  // namespace
@@ -431,6 +597,10 @@ int ga_destroy_patch(ga_patch* pt) {
   }
   if (pt->W) hipFree(pt->W);
   if (pt->G) hipFree(pt->G);
+  if (pt->W32) hipFree(pt->W32);
+  if (pt->s32) hipFree(pt->s32);
+  for (int a = 0; a < 3; ++a)
+    if (pt->Minv32[a]) hipFree(pt->Minv32[a]);
   if (pt->diagM) hipFree(pt->diagM);
   if (pt->s) hipFree(pt->s);
   if (pt->work) hipFree(pt->work);
@@ -478,11 +648,12 @@ int ga_apply_Pinv(ga_patch* pt, int nrhs, const double* r, double* z, void* stre
 }
 
 int ga_mass_solve(ga_patch* pt, int nrhs, const double* b, double* x, double rtol, int maxit,
-                  int* iters_out, double* relres_out, void* stream) {
+                  int prec, int* iters_out, double* relres_out, void* stream) {
   if (!pt || !b || !x) { set_error("null argument"); return GA_EINVAL; }
   if (nrhs < 1 || nrhs > 16) { set_error("nrhs must be in 1..16"); return GA_EINVAL; }
   if (!(rtol > 0.0) || maxit < 0) { set_error("rtol must be > 0 and maxit >= 0"); return GA_EINVAL; }
-  return solve_impl(pt, nrhs, b, x, rtol, maxit, false, iters_out, relres_out, S(stream));
+  if (prec != GA_FP64 && prec != GA_FP32) { set_error("prec must be GA_FP64 or GA_FP32"); return GA_EINVAL; }
+  return solve_any(pt, nrhs, b, x, rtol, maxit, prec, false, iters_out, relres_out, S(stream));
 }
 
 int ga_lambda_max(ga_patch* pt, int iters, double* out, void* stream) {
@@ -537,14 +708,17 @@ int ga_lambda_max(ga_patch* pt, int iters, double* out, void* stream) {
 }
 
 int ga_integrator_create(ga_patch* pt, int k, double rho, double tau, double rtol, int maxit,
-                         int guess_mode, ga_integrator** out) {
+                         int prec, int guess_mode, ga_integrator** out) {
   if (!pt || !out) { set_error("null argument"); return GA_EINVAL; }
   *out = nullptr;
   if (k < 1 || k > 4) { set_error("k must be in 1..4"); return GA_EINVAL; }
   if (!(rho >= 0.0 && rho < 1.0)) { set_error("rho must be in [0, 1)"); return GA_EINVAL; }
   if (!(tau > 0.0) || !(rtol > 0.0) || maxit < 1) { set_error("bad tau/rtol/maxit"); return GA_EINVAL; }
   if (guess_mode != GA_GUESS_ZERO && guess_mode != GA_GUESS_PREV) { set_error("bad guess mode"); return GA_EINVAL; }
+  if (prec != GA_FP64 && prec != GA_FP32) { set_error("prec must be GA_FP64 or GA_FP32"); return GA_EINVAL; }
+  if (prec == GA_FP32 && pt->dim != 3) { set_error("mixed precision needs a 3-D patch"); return GA_EINVAL; }
   ga_integrator* it = new ga_integrator();
+  it->prec = prec;
   it->patch = pt;
   it->k = k;
   it->rho = rho;
@@ -590,7 +764,8 @@ int ga_init_state(ga_integrator* it, const double* U0, const double* V0, double*
     launch_fill(it->Y, 0.0, n, st);
     int rc = op_apply(pt, 1, 1, -1.0, state[a], it->Y, st);  // -K L^{a-2}
     if (rc) return rc;
-    rc = solve_impl(pt, 1, it->Y, state[a + 2], it->rtol, it->maxit, true, nullptr, nullptr, st);
+    rc = solve_any(pt, 1, it->Y, state[a + 2], it->rtol, it->maxit, it->prec, true, nullptr,
+                   nullptr, st);
     if (rc) return rc;
   }
   it->have_prev = false;
@@ -621,7 +796,7 @@ int ga_step(ga_integrator* it, double* const* state, int nsteps, int* iters_out,
     int rc = op_apply(pt, 1, k, -1.0, it->Y, it->Bv, st);
     if (rc) return rc;
     bool zero = !(it->guess == GA_GUESS_PREV && it->have_prev);
-    rc = solve_impl(pt, k, it->Bv, it->X, it->rtol, it->maxit, zero, iters, nullptr, st);
+    rc = solve_any(pt, k, it->Bv, it->X, it->rtol, it->maxit, it->prec, zero, iters, nullptr, st);
     if (rc) return rc;
     if (iters_out)
       for (int j = 0; j < k; ++j) iters_out[(size_t)step * k + j] = iters[j];

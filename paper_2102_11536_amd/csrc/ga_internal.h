@@ -52,6 +52,9 @@ struct ga_patch {
   double* W = nullptr;        // w |det J|            (3-D: mass-kernel column layout)
   double* G = nullptr;        // w |det J| J^-1 J^-T  (3-D: stiffness-kernel column layout)
   size_t nW = 0, nG = 0;      // entries
+  float* W32 = nullptr;       // FP32 copy of W (mixed-precision inner solves)
+  float* Minv32[3] = {nullptr, nullptr, nullptr};  // FP32 copies of the 1-D inverses
+  float* s32 = nullptr;       // FP32 copy of the scaling
   double* diagM = nullptr;    // [n_free]
   double* s = nullptr;        // [n_free] (Dhat/D)^(1/2)
   double* Minv[3] = {nullptr, nullptr, nullptr};   // [mf][mf]
@@ -68,7 +71,7 @@ struct ga_integrator {
   ga_patch* patch = nullptr;
   int k = 1;
   double rho = 0.5, tau = 0.0, rtol = 1e-10;
-  int maxit = 200, guess = GA_GUESS_ZERO;
+  int maxit = 200, guess = GA_GUESS_ZERO, prec = GA_FP64;
   double alpha[8], beta[8], gamma[8];
   double* Y = nullptr;        // [k][n_free] stage arguments Y_j
   double* Bv = nullptr;       // [k][n_free] stage right-hand sides -K Y_j

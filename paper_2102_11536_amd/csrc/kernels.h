@@ -15,6 +15,8 @@ struct Coefs { double alpha[4], beta[4], gamma[4]; };
 
 int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
                 hipStream_t st);
+int launch_mass3d_f32(int nr, const ga_patch* pt, const float* x, float* y, float alpha,
+                      hipStream_t st);
 int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
                  hipStream_t st);
 int launch_op2d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
@@ -28,6 +30,15 @@ void launch_scale_mul(double* out, const double* in, const double* s, int nr, si
 void launch_gemm(int M, int N, int K, const double* X, long long ldx, long long sX,
                  const double* Y, long long ldy, long long sY, double* C, long long ldc,
                  long long sC, int batch, hipStream_t st);
+bool pinv_axis_supported(int L);
+template <typename S>
+void launch_pinv_strided(const S* in, S* out, const S* A, int L, long long row_stride,
+                         long long ncol, long long plane_stride, int planes_per_rhs,
+                         long long n_free, int nr, const S* si, const S* so, hipStream_t st);
+template <typename S>
+void launch_pinv_contig(const S* in, S* out, const S* A, int L, long long nrows,
+                        long long rows_per_rhs, long long n_free, const S* si, const S* so,
+                        hipStream_t st);
 void launch_scaling(double* s, const double* diagM, const double* dh0, const double* dh1,
                     const double* dh2, int mf0, int mf1, int mf2, hipStream_t st);
 void launch_dot_partial(int nr, const double* a, const double* b, size_t n, double* part,
@@ -44,6 +55,19 @@ void launch_update(int k, double tau, Coefs c, StatePtrs sp, const double* X, si
                    hipStream_t st);
 void launch_axpby(double* out, double a, const double* x, double b, const double* y, size_t n,
                   hipStream_t st);
+void launch_to_f32(float* o, const double* i, size_t n, hipStream_t st);
+void launch_add_f32(double* x, const float* d, size_t n, hipStream_t st);
+void launch_fill_f32(float* p, size_t n, hipStream_t st);
+void launch_copy_f32(float* d, const float* s, size_t n, hipStream_t st);
+void launch_dot_ff(int nr, const float* a, const float* b, size_t n, double* part, hipStream_t st);
+void launch_dot_df(int nr, const double* a, const float* b, size_t n, double* part, hipStream_t st);
+void launch_dot2_f32(int nr, const float* r, const float* z, const float* q, size_t n, double* p1,
+                     double* p2, hipStream_t st);
+void launch_cg_beta_flex(int nr, const double* p1, const double* p2, double* scal, hipStream_t st);
+void launch_cg_xr_f32(int nr, float* x, float* r, const float* p, const float* q,
+                      const double* scal, size_t n, hipStream_t st);
+void launch_cg_p_f32(int nr, float* p, const float* z, const double* scal, size_t n,
+                     hipStream_t st);
 void launch_sum_partials(int nr, const double* part, double* out, hipStream_t st);
 
 }  // namespace ga

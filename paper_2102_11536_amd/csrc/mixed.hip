@@ -1,0 +1,181 @@
+// FP32 vector kernels of the mixed-precision mass solve: conversions between the
+// FP64 outer iteration and the FP32 inner PCG, dot products accumulated in FP64,
+// and the flexible (Polak-Ribiere) PCG updates of the inner solve.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace ga {
+
+namespace {
+
+constexpr int VB = 256;
+
+inline unsigned nb(size_t n) {
+  size_t b = (n + VB - 1) / VB;
+  if (b > 8192) b = 8192;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < VB / 64; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ void to_f32_k(float* __restrict__ o, const double* __restrict__ i, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * VB + threadIdx.x; k < n; k += (size_t)gridDim.x * VB)
+    o[k] = (float)i[k];
+}
+
+__global__ void add_f32_k(double* __restrict__ x, const float* __restrict__ d, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * VB + threadIdx.x; k < n; k += (size_t)gridDim.x * VB)
+    x[k] += (double)d[k];
+}
+
+__global__ void fill_f32_k(float* p, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * VB + threadIdx.x; k < n; k += (size_t)gridDim.x * VB)
+    p[k] = 0.0f;
+}
+
+__global__ void copy_f32_k(float* __restrict__ d, const float* __restrict__ s, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * VB + threadIdx.x; k < n; k += (size_t)gridDim.x * VB)
+    d[k] = s[k];
+}
+
+// part[r][block] = sum a_r * b_r with FP64 accumulation (a, b FP32 or FP64)
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(VB)
+dotm_k(const TA* __restrict__ a, const TB* __restrict__ b, size_t n, double* __restrict__ part) {
+  __shared__ double sh[VB / 64];
+  const int r = blockIdx.y;
+  const TA* ar = a + (size_t)r * n;
+  const TB* br = b + (size_t)r * n;
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB)
+    s += (double)ar[i] * (double)br[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = s;
+}
+
+// two dots in one pass: r.z and z.q (FP32 vectors, FP64 accumulation)
+__global__ void __launch_bounds__(VB)
+dot2_k(const float* __restrict__ r, const float* __restrict__ z, const float* __restrict__ q,
+       size_t n, double* __restrict__ p1, double* __restrict__ p2) {
+  __shared__ double sh[VB / 64];
+  const int rr = blockIdx.y;
+  const size_t off = (size_t)rr * n;
+  double s1 = 0.0, s2 = 0.0;
+  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB) {
+    const double zv = z[off + i];
+    s1 += (double)r[off + i] * zv;
+    s2 += zv * (double)q[off + i];
+  }
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    p1[(size_t)rr * gridDim.x + blockIdx.x] = s1;
+    p2[(size_t)rr * gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+__device__ double sum_part(const double* part, int r, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += VB) v += part[(size_t)r * RED_BLOCKS + i];
+  return block_sum(v, sh);
+}
+
+// flexible beta: rz_new = r.z, zq = z.q (q = M p), beta = -alpha zq / rz_old
+__global__ void __launch_bounds__(VB) cg_beta_flex_k(const double* p1, const double* p2,
+                                                     double* scal) {
+  __shared__ double sh[VB / 64];
+  const int r = blockIdx.x;
+  const double rz = sum_part(p1, r, sh);
+  const double zq = sum_part(p2, r, sh);
+  if (threadIdx.x == 0) {
+    double* s = scal + (size_t)r * NSCAL;
+    if (s[S_ACTIVE] != 0.0) {
+      s[S_BETA] = -s[S_ALPHA] * zq / s[S_RZ];
+      s[S_RZ] = rz;
+      s[S_ITERS] += 1.0;
+      if (!(rz > s[S_TOL2] * s[S_BN2])) s[S_ACTIVE] = 0.0;
+    } else {
+      s[S_BETA] = 0.0;
+    }
+  }
+}
+
+__global__ void cg_xr_f32_k(float* __restrict__ x, float* __restrict__ r,
+                            const float* __restrict__ p, const float* __restrict__ q,
+                            const double* __restrict__ scal, size_t n) {
+  const int rr = blockIdx.y;
+  const float a = (float)scal[(size_t)rr * NSCAL + S_ALPHA];
+  if (a == 0.0f) return;
+  const size_t off = (size_t)rr * n;
+  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB) {
+    x[off + i] += a * p[off + i];
+    r[off + i] -= a * q[off + i];
+  }
+}
+
+__global__ void cg_p_f32_k(float* __restrict__ p, const float* __restrict__ z,
+                           const double* __restrict__ scal, size_t n) {
+  const int rr = blockIdx.y;
+  if (scal[(size_t)rr * NSCAL + S_ACTIVE] == 0.0) return;
+  const float b = (float)scal[(size_t)rr * NSCAL + S_BETA];
+  const size_t off = (size_t)rr * n;
+  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB)
+    p[off + i] = z[off + i] + b * p[off + i];
+}
+
+}  // namespace
+
+void launch_to_f32(float* o, const double* i, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(to_f32_k, dim3(nb(n)), dim3(VB), 0, st, o, i, n);
+}
+void launch_add_f32(double* x, const float* d, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(add_f32_k, dim3(nb(n)), dim3(VB), 0, st, x, d, n);
+}
+void launch_fill_f32(float* p, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(fill_f32_k, dim3(nb(n)), dim3(VB), 0, st, p, n);
+}
+void launch_copy_f32(float* d, const float* s, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_f32_k, dim3(nb(n)), dim3(VB), 0, st, d, s, n);
+}
+void launch_dot_ff(int nr, const float* a, const float* b, size_t n, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((dotm_k<float, float>), dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part);
+}
+void launch_dot_df(int nr, const double* a, const float* b, size_t n, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((dotm_k<double, float>), dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part);
+}
+void launch_dot2_f32(int nr, const float* r, const float* z, const float* q, size_t n, double* p1,
+                     double* p2, hipStream_t st) {
+  hipLaunchKernelGGL(dot2_k, dim3(RED_BLOCKS, nr), dim3(VB), 0, st, r, z, q, n, p1, p2);
+}
+void launch_cg_beta_flex(int nr, const double* p1, const double* p2, double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(cg_beta_flex_k, dim3(nr), dim3(VB), 0, st, p1, p2, scal);
+}
+void launch_cg_xr_f32(int nr, float* x, float* r, const float* p, const float* q,
+                      const double* scal, size_t n, hipStream_t st) {
+  unsigned b = nb(n) > 2048 ? 2048 : nb(n);
+  hipLaunchKernelGGL(cg_xr_f32_k, dim3(b, nr), dim3(VB), 0, st, x, r, p, q, scal, n);
+}
+void launch_cg_p_f32(int nr, float* p, const float* z, const double* scal, size_t n,
+                     hipStream_t st) {
+  unsigned b = nb(n) > 2048 ? 2048 : nb(n);
+  hipLaunchKernelGGL(cg_p_f32_k, dim3(b, nr), dim3(VB), 0, st, p, z, scal, n);
+}
+
+}  // namespace ga

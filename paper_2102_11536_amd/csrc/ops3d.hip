@@ -74,14 +74,14 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned nwg) {
 #endif
 
 // MODE: 0 mass, 1 stiffness, 2 diag(M) (tables hold squared values, x unused)
-template <int P, int TE, int MODE, int NR>
+template <int P, int TE, int MODE, int NR, typename S>
 __global__ void __launch_bounds__((Tile3<P, TE>::NT), (MODE == 1 ? GA_OP3_WAVES_K : GA_OP3_WAVES_M))
-op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
-            const double* __restrict__ fac,
+op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
+            const S* __restrict__ fac,
             const double* __restrict__ tB0, const double* __restrict__ tB1,
             const double* __restrict__ tB2, const double* __restrict__ tD0,
             const double* __restrict__ tD1, const double* __restrict__ tD2,
-            Geo3 g, int ze, long long n_free, double alpha) {
+            Geo3 g, int ze, long long n_free, S alpha) {
   using T = Tile3<P, TE>;
   constexpr int Q = T::Q, QT = T::QT, NB = T::NB, NT = T::NT;
   constexpr int NPL = NB * NB;                  // coefficients per plane of the box
@@ -92,18 +92,18 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
   constexpr int XPR = (NR * NPL + NT - 1) / NT; // prefetched plane values per thread
   constexpr int QP = QT + 1;                    // padded LDS row (no bank conflicts)
 
-  __shared__ double sB[2][T::TAB];
-  __shared__ double sD[2][T::TAB];
+  __shared__ S sB[2][T::TAB];
+  __shared__ S sD[2][T::TAB];
   // x tables by local index: xB[a][q] = value of basis ex(q)+a at tile Gauss point q
-  __shared__ double xB[P + 1][QT];
-  __shared__ double xD[P + 1][QT];
+  __shared__ S xB[P + 1][QT];
+  __shared__ S xD[P + 1][QT];
   // transposed, zero-padded: tBs[a][i * QP + q] = basis i of the box at tile Gauss point q
-  __shared__ double tBs[2][NB * QP];
-  __shared__ double tDs[2][NB * QP];
-  __shared__ double Xs[NR][NPL];
-  __shared__ double As[NR][NA][NB * QT];
-  __shared__ double Ss[NR][NF][NT];
-  __shared__ double Rs[NR][NRF][NB * QP];
+  __shared__ S tBs[2][NB * QP];
+  __shared__ S tDs[2][NB * QP];
+  __shared__ S Xs[NR][NPL];
+  __shared__ S As[NR][NA][NB * QT];
+  __shared__ S Ss[NR][NF][NT];
+  __shared__ S Rs[NR][NRF][NB * QP];
 
   const int tid = threadIdx.x;
   const int qx = tid % QT, qy = tid / QT;
@@ -118,11 +118,11 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
   const int qz_tot = g.n[2] * Q;
 
   for (int i = tid; i < T::TAB; i += NT) {
-    sB[0][i] = tB0[(size_t)e0x * Q * (P + 1) + i];
-    sB[1][i] = tB1[(size_t)e0y * Q * (P + 1) + i];
+    sB[0][i] = (S)tB0[(size_t)e0x * Q * (P + 1) + i];
+    sB[1][i] = (S)tB1[(size_t)e0y * Q * (P + 1) + i];
     if (MODE == 1) {
-      sD[0][i] = tD0[(size_t)e0x * Q * (P + 1) + i];
-      sD[1][i] = tD1[(size_t)e0y * Q * (P + 1) + i];
+      sD[0][i] = (S)tD0[(size_t)e0x * Q * (P + 1) + i];
+      sD[1][i] = (S)tD1[(size_t)e0y * Q * (P + 1) + i];
     }
   }
   for (int i = tid; i < 2 * NB * QT; i += NT) {
@@ -132,19 +132,19 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
     const double* tb = ax == 0 ? tB0 + (size_t)e0x * Q * (P + 1) : tB1 + (size_t)e0y * Q * (P + 1);
     const double* td = ax == 0 ? tD0 + (size_t)e0x * Q * (P + 1) : tD1 + (size_t)e0y * Q * (P + 1);
     const bool in = a >= 0 && a <= P;
-    tBs[ax][ib * QP + q] = in ? tb[(el * Q + jq) * (P + 1) + a] : 0.0;
-    tDs[ax][ib * QP + q] = (in && MODE == 1) ? td[(el * Q + jq) * (P + 1) + a] : 0.0;
+    tBs[ax][ib * QP + q] = in ? (S)tb[(el * Q + jq) * (P + 1) + a] : (S)0;
+    tDs[ax][ib * QP + q] = (in && MODE == 1) ? (S)td[(el * Q + jq) * (P + 1) + a] : (S)0;
   }
   for (int i = tid; i < (P + 1) * QT; i += NT) {
     const int a = i / QT, q = i % QT;
-    xB[a][q] = tB0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a];
-    xD[a][q] = MODE == 1 ? tD0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a] : 0.0;
+    xB[a][q] = (S)tB0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a];
+    xD[a][q] = MODE == 1 ? (S)tD0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a] : (S)0;
   }
   const int eyq = qy / Q, jyq = qy % Q;
-  const double* fcol = fac + (size_t)txy * qz_tot * NC * NT + tid;
+  const S* fcol = fac + (size_t)txy * qz_tot * NC * NT + tid;
 
-  double c[NR][NF][P + 1];   // forward fields of the coefficient planes ez..ez+P
-  double s[NR][NF][P + 1];   // transposed-z accumulators of the same planes
+  S c[NR][NF][P + 1];   // forward fields of the coefficient planes ez..ez+P
+  S s[NR][NF][P + 1];   // transposed-z accumulators of the same planes
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -153,12 +153,12 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
       for (int j = 0; j <= P; ++j) { c[r][f][j] = 0.0; s[r][f][j] = 0.0; }
 
   // prefetch of the next coefficient plane (global -> registers)
-  double xpre[XPR];
+  S xpre[XPR];
   auto load_plane = [&](int iz) {
 #pragma unroll
     for (int k = 0; k < XPR; ++k) {
       const int i = tid + k * NT;
-      double v = 0.0;
+      S v = 0.0;
       if (i < NR * NPL) {
         const int r = i / NPL, b = i % NPL;
         const long long f = free_index3(g, e0x + b % NB, e0y + b / NB, iz);
@@ -183,8 +183,8 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
       const int r = i / (NB * QT), b = i % (NB * QT);
       const int q = b % QT, iy = b / QT;
       const int ex = q / Q, jx = q % Q;
-      const double* xs = &Xs[r][iy * NB + ex];
-      double a0 = 0.0, a1 = 0.0;
+      const S* xs = &Xs[r][iy * NB + ex];
+      S a0 = 0.0, a1 = 0.0;
 #pragma unroll
       for (int a = 0; a <= P; ++a) a0 += xB[a][q + lz] * xs[a];
       As[r][0][b] = a0;
@@ -195,14 +195,14 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
       }
     }
     __syncthreads();
-    const double* by = &sB[1][(eyq * Q + jyq) * (P + 1) + lz];
-    const double* dy = &sD[1][(eyq * Q + jyq) * (P + 1) + lz];
+    const S* by = &sB[1][(eyq * Q + jyq) * (P + 1) + lz];
+    const S* dy = &sD[1][(eyq * Q + jyq) * (P + 1) + lz];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+      S v0 = 0.0, v1 = 0.0, v2 = 0.0;
 #pragma unroll
       for (int b = 0; b <= P; ++b) {
-        const double a0 = As[r][0][(eyq + b) * QT + qx];
+        const S a0 = As[r][0][(eyq + b) * QT + qx];
         v0 += by[b] * a0;
         if (MODE == 1) {
           v1 += by[b] * As[r][1][(eyq + b) * QT + qx];
@@ -232,9 +232,9 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
     for (int i = tid; i < NR * NRF * NB * QT; i += NT) {
       const int r = i / (NRF * NB * QT), b = i % (NRF * NB * QT);
       const int q = b % QT, iy = (b / QT) % NB, cf = b / (NB * QT);
-      const double* ty_ = &tBs[1][iy * QP + lz];
-      const double* tdy = &tDs[1][iy * QP + lz];
-      double acc = 0.0;
+      const S* ty_ = &tBs[1][iy * QP + lz];
+      const S* tdy = &tDs[1][iy * QP + lz];
+      S acc = 0.0;
       if (MODE == 1 && cf == 1) {
 #pragma unroll 4
         for (int k = 0; k < QT; ++k)
@@ -249,9 +249,9 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
     for (int i = tid; i < NR * NPL; i += NT) {
       const int r = i / NPL, b = i % NPL;
       const int ix = b % NB, iy = b / NB;
-      const double* tx_ = &tBs[0][ix * QP + lz];
-      const double* tdx = &tDs[0][ix * QP + lz];
-      double acc = 0.0;
+      const S* tx_ = &tBs[0][ix * QP + lz];
+      const S* tdx = &tDs[0][ix * QP + lz];
+      S acc = 0.0;
 #pragma unroll 4
       for (int k = 0; k < QT; ++k) {
         if (MODE == 1) acc += tdx[k] * Rs[r][0][iy * QP + k] + tx_[k] * Rs[r][1][iy * QP + k];
@@ -289,9 +289,9 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
     for (int i = tid; i < NR * NRF * NB * QT; i += NT) {
       const int r = i / (NRF * NB * QT), b = i % (NRF * NB * QT);
       const int q = b % QT, iy = (b / QT) % NB, cf = b / (NB * QT);
-      const double* ty_ = &tBs[1][iy * QP + lz];
-      const double* tdy = &tDs[1][iy * QP + lz];
-      double acc = 0.0;
+      const S* ty_ = &tBs[1][iy * QP + lz];
+      const S* tdy = &tDs[1][iy * QP + lz];
+      S acc = 0.0;
       if (MODE == 1 && cf == 1) {
 #pragma unroll 4
         for (int k = 0; k < QT; ++k)
@@ -306,8 +306,8 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
       const int r = i / (NB * QT), b = i % (NB * QT);
       const int q = b % QT, iy = b / QT;
       const int ex = q / Q, jx = q % Q;
-      const double* xs = &Xs[r][iy * NB + ex];
-      double a0 = 0.0, a1 = 0.0;
+      const S* xs = &Xs[r][iy * NB + ex];
+      S a0 = 0.0, a1 = 0.0;
 #pragma unroll
       for (int a = 0; a <= P; ++a) a0 += xB[a][q + lz] * xs[a];
       As[r][0][b] = a0;
@@ -321,9 +321,9 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
     for (int i = tid; i < NR * NPL; i += NT) {
       const int r = i / NPL, b = i % NPL;
       const int ix = b % NB, iy = b / NB;
-      const double* tx_ = &tBs[0][ix * QP + lz];
-      const double* tdx = &tDs[0][ix * QP + lz];
-      double acc = 0.0;
+      const S* tx_ = &tBs[0][ix * QP + lz];
+      const S* tdx = &tDs[0][ix * QP + lz];
+      S acc = 0.0;
 #pragma unroll 4
       for (int k = 0; k < QT; ++k) {
         if (MODE == 1) acc += tdx[k] * Rs[r][0][iy * QP + k] + tx_[k] * Rs[r][1][iy * QP + k];
@@ -333,14 +333,14 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
       if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
     }
     shift_c_();
-    const double* by = &sB[1][(eyq * Q + jyq) * (P + 1) + lz];
-    const double* dy = &sD[1][(eyq * Q + jyq) * (P + 1) + lz];
+    const S* by = &sB[1][(eyq * Q + jyq) * (P + 1) + lz];
+    const S* dy = &sD[1][(eyq * Q + jyq) * (P + 1) + lz];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+      S v0 = 0.0, v1 = 0.0, v2 = 0.0;
 #pragma unroll
       for (int b = 0; b <= P; ++b) {
-        const double a0 = As[r][0][(eyq + b) * QT + qx];
+        const S a0 = As[r][0][(eyq + b) * QT + qx];
         v0 += by[b] * a0;
         if (MODE == 1) {
           v1 += by[b] * As[r][1][(eyq + b) * QT + qx];
@@ -390,7 +390,7 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
   // z sweep over Gauss layers with a ring of D prefetched factor planes
   constexpr int D = (MODE == 1) ? 2 : 4;
   const int q0 = ez0 * Q, q1 = ez1 * Q;
-  double gq[D][NC];
+  S gq[D][NC];
 #pragma unroll
   for (int d = 0; d < D; ++d)
 #pragma unroll
@@ -403,7 +403,7 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
       const int q = qb + d;
       if (q >= q1) break;
       const int ez = q / Q, jz = q - ez * Q;
-      double cur[NC];
+      S cur[NC];
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) cur[cc] = gq[d][cc];
       if (q + D < q1) {
@@ -412,25 +412,25 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
       }
       const double* bzt = tB2 + ((size_t)ez * Q + jz) * (P + 1);
       const double* dzt = tD2 + ((size_t)ez * Q + jz) * (P + 1);
-      double bz[P + 1], dz[P + 1];
+      S bz[P + 1], dz[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) {
-        bz[a] = bzt[a];
-        if (MODE == 1) dz[a] = dzt[a];
+        bz[a] = (S)bzt[a];
+        if (MODE == 1) dz[a] = (S)dzt[a];
       }
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         if (MODE == 1) {
-          double ux = 0.0, uy = 0.0, uz = 0.0;
+          S ux = 0.0, uy = 0.0, uz = 0.0;
 #pragma unroll
           for (int a = 0; a <= P; ++a) {
             ux += bz[a] * c[r][0][a];
             uy += bz[a] * c[r][1][a];
             uz += dz[a] * c[r][2][a];
           }
-          const double fx = cur[0] * ux + cur[1] * uy + cur[2] * uz;
-          const double fy = cur[1] * ux + cur[3] * uy + cur[4] * uz;
-          const double fz = cur[2] * ux + cur[4] * uy + cur[5] * uz;
+          const S fx = cur[0] * ux + cur[1] * uy + cur[2] * uz;
+          const S fy = cur[1] * ux + cur[3] * uy + cur[4] * uz;
+          const S fz = cur[2] * ux + cur[4] * uy + cur[5] * uz;
 #pragma unroll
           for (int a = 0; a <= P; ++a) {
             s[r][0][a] += bz[a] * fx;
@@ -438,13 +438,13 @@ op3d_kernel(const double* __restrict__ x, double* __restrict__ y,
             s[r][2][a] += dz[a] * fz;
           }
         } else {
-          double u = 1.0;
+          S u = 1.0;
           if (MODE == 0) {
             u = 0.0;
 #pragma unroll
             for (int a = 0; a <= P; ++a) u += bz[a] * c[r][0][a];
           }
-          const double v = cur[0] * u;
+          const S v = cur[0] * u;
 #pragma unroll
           for (int a = 0; a <= P; ++a) s[r][0][a] += bz[a] * v;
         }
@@ -554,9 +554,9 @@ static int pick_ze(long long ntxy, int nz, int floor_ze) {
   return ze < 1 ? 1 : ze;
 }
 
-template <int P>
-static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const double* x, double* y,
-                         double alpha, hipStream_t st) {
+template <int P, typename S>
+static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const S* x, S* y, S alpha,
+                         const S* fac, hipStream_t st) {
   constexpr int TK = te3_stiff(P), TM = te3_mass(P);
   Geo3 g;
   for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; }
@@ -568,15 +568,18 @@ static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const double* x, 
   const long long nwg = ntxy * ((pt->n[2] + ze - 1) / ze);
   dim3 grid((unsigned)nwg);
   const double* const* B = (mode == 2) ? pt->tabB2 : pt->tabB;
-  const double* fac = (mode == 1) ? pt->G : pt->W;
 #define GA_OP3(TE, MODE, NRV)                                                               \
-  hipLaunchKernelGGL((op3d_kernel<P, TE, MODE, NRV>), grid, dim3(Tile3<P, TE>::NT), 0, st,   \
+  hipLaunchKernelGGL((op3d_kernel<P, TE, MODE, NRV, S>), grid, dim3(Tile3<P, TE>::NT), 0, st, \
                      x, y, fac, B[0], B[1], B[2], pt->tabD[0], pt->tabD[1], pt->tabD[2], g,   \
                      ze, pt->n_free, alpha)
   if (mode == 0) {
     if (nr == 1) GA_OP3(TM, 0, 1); else if (nr == 2) GA_OP3(TM, 0, 2); else GA_OP3(TM, 0, 3);
   } else if (mode == 1) {
-    if (nr == 1) GA_OP3(TK, 1, 1); else if (nr == 2) GA_OP3(TK, 1, 2); else GA_OP3(TK, 1, 3);
+    if constexpr (sizeof(S) == 8) {  // the stiffness apply always runs in FP64
+      if (nr == 1) GA_OP3(TK, 1, 1); else if (nr == 2) GA_OP3(TK, 1, 2); else GA_OP3(TK, 1, 3);
+    } else {
+      return -1;
+    }
   } else {
     GA_OP3(TM, 2, 1);
   }
@@ -586,11 +589,26 @@ static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const double* x, 
 
 int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
                 hipStream_t st) {
+  const double* fac = (mode == 1) ? pt->G : pt->W;
   switch (pt->p) {
-    case 1: return launch_op3d_p<1>(mode, nr, pt, x, y, alpha, st);
-    case 2: return launch_op3d_p<2>(mode, nr, pt, x, y, alpha, st);
-    case 3: return launch_op3d_p<3>(mode, nr, pt, x, y, alpha, st);
-    case 4: return launch_op3d_p<4>(mode, nr, pt, x, y, alpha, st);
+    case 1: return launch_op3d_p<1, double>(mode, nr, pt, x, y, alpha, fac, st);
+    case 2: return launch_op3d_p<2, double>(mode, nr, pt, x, y, alpha, fac, st);
+    case 3: return launch_op3d_p<3, double>(mode, nr, pt, x, y, alpha, fac, st);
+    case 4: return launch_op3d_p<4, double>(mode, nr, pt, x, y, alpha, fac, st);
+  }
+  return -1;
+}
+
+// FP32 mass apply (inner solves of the mixed-precision path): FP32 factors W32,
+// FP32 vectors and FP32 arithmetic
+int launch_mass3d_f32(int nr, const ga_patch* pt, const float* x, float* y, float alpha,
+                      hipStream_t st) {
+  if (!pt->W32) return -1;
+  switch (pt->p) {
+    case 1: return launch_op3d_p<1, float>(0, nr, pt, x, y, alpha, pt->W32, st);
+    case 2: return launch_op3d_p<2, float>(0, nr, pt, x, y, alpha, pt->W32, st);
+    case 3: return launch_op3d_p<3, float>(0, nr, pt, x, y, alpha, pt->W32, st);
+    case 4: return launch_op3d_p<4, float>(0, nr, pt, x, y, alpha, pt->W32, st);
   }
   return -1;
 }

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libga.so")
 
 GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EGEOMETRY, GA_ENOCONV, GA_EUNSTABLE = 0, -1, -2, -3, -4, -5, -6
 GA_GUESS_ZERO, GA_GUESS_PREV = 0, 1
+GA_FP64, GA_FP32 = 0, 1
 
 EXPORTS = ["ga_setup_patch", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
            "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
@@ -45,11 +46,11 @@ def load_library(path=LIB_PATH):
     lib.ga_diag_M.argtypes = [vp, dp, vp]
     lib.ga_apply_MK.argtypes = [vp, ctypes.c_char, i, d, dp, dp, vp]
     lib.ga_apply_Pinv.argtypes = [vp, i, dp, dp, vp]
-    lib.ga_mass_solve.argtypes = [vp, i, dp, dp, d, i, ctypes.POINTER(i), ctypes.POINTER(d), vp]
+    lib.ga_mass_solve.argtypes = [vp, i, dp, dp, d, i, i, ctypes.POINTER(i), ctypes.POINTER(d), vp]
     lib.ga_lambda_max.argtypes = [vp, i, ctypes.POINTER(d), vp]
     lib.ga_stability_limit.argtypes = [d]
     lib.ga_stability_limit.restype = d
-    lib.ga_integrator_create.argtypes = [vp, i, d, d, d, i, i, ctypes.POINTER(vp)]
+    lib.ga_integrator_create.argtypes = [vp, i, d, d, d, i, i, i, ctypes.POINTER(vp)]
     lib.ga_integrator_destroy.argtypes = [vp]
     lib.ga_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
     lib.ga_step.argtypes = [vp, ctypes.POINTER(vp), i, ctypes.POINTER(i), vp]
@@ -129,12 +130,13 @@ def ga_apply_Pinv(patch, r, z, nrhs=1):
     _check(_lib.ga_apply_Pinv(patch.h, nrhs, _ptr(r, n), _ptr(z, n), _stream()))
 
 
-def ga_mass_solve(patch, b, x, nrhs=1, rtol=1e-12, maxit=500, raise_on_noconv=True):
+def ga_mass_solve(patch, b, x, nrhs=1, rtol=1e-12, maxit=500, raise_on_noconv=True, prec=GA_FP64):
     """Returns (iterations[nrhs], relres[nrhs], status)."""
     n = nrhs * patch.n_free
     its = (ctypes.c_int * nrhs)()
     rel = (ctypes.c_double * nrhs)()
-    rc = _lib.ga_mass_solve(patch.h, nrhs, _ptr(b, n), _ptr(x, n), float(rtol), int(maxit), its, rel, _stream())
+    rc = _lib.ga_mass_solve(patch.h, nrhs, _ptr(b, n), _ptr(x, n), float(rtol), int(maxit), int(prec),
+                            its, rel, _stream())
     if rc != GA_ENOCONV or raise_on_noconv:
         _check(rc)
     return list(its), list(rel), rc
@@ -151,10 +153,10 @@ def ga_stability_limit(rho):
 
 
 class Integrator:
-    def __init__(self, patch, k, rho, tau, rtol=1e-10, maxit=200, guess=GA_GUESS_ZERO):
+    def __init__(self, patch, k, rho, tau, rtol=1e-10, maxit=200, guess=GA_GUESS_ZERO, prec=GA_FP64):
         h = ctypes.c_void_p()
         _check(_lib.ga_integrator_create(patch.h, k, float(rho), float(tau), float(rtol), int(maxit),
-                                         int(guess), ctypes.byref(h)))
+                                         int(prec), int(guess), ctypes.byref(h)))
         self.h, self.patch, self.k = h, patch, k
 
     def close(self):
@@ -169,8 +171,8 @@ class Integrator:
             pass
 
 
-def ga_integrator_create(patch, k, rho, tau, rtol=1e-10, maxit=200, guess=GA_GUESS_ZERO):
-    return Integrator(patch, k, rho, tau, rtol, maxit, guess)
+def ga_integrator_create(patch, k, rho, tau, rtol=1e-10, maxit=200, guess=GA_GUESS_ZERO, prec=GA_FP64):
+    return Integrator(patch, k, rho, tau, rtol, maxit, guess, prec)
 
 
 def _state_array(integ, state):

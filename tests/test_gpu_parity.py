@@ -271,3 +271,41 @@ def test_unstable_step_detected():
         for _ in range(50):
             ga.ga_step(integ, state, 40)
     assert e.value.code in (ga.GA_EUNSTABLE, ga.GA_ENOCONV)
+
+
+# ---- mixed precision: FP32 inner PCG inside FP64 iterative refinement ----
+
+@pytest.mark.parametrize("n,p", [(6, 3), (5, 4), ((7, 4, 6), 2)])
+def test_mixed_mass_solve_matches_cholesky(n, p):
+    _say("mixed solve", n, p)
+    pr = OracleProblem(3, n, p)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    B = np.random.default_rng(12).standard_normal((2, pt.n_free))
+    b = _t(B.ravel())
+    x = torch.zeros_like(b)
+    its, relres, rc = ga.ga_mass_solve(pt, b, x, nrhs=2, rtol=1e-12, prec=ga.GA_FP32)
+    got = _np(x).reshape(2, -1)
+    for i in range(2):
+        ref = pr.chol.solve(B[i])
+        e = rel(got[i], ref)
+        _say("  rel err", e, "inner its", its[i], "relres", relres[i])
+        assert e < 1e-10 and relres[i] <= 1e-12
+
+
+@pytest.mark.parametrize("k,p,n", [(2, 3, 6), (3, 2, 5)])
+def test_mixed_step_matches_oracle(k, p, n):
+    _say("mixed step", k, p, n)
+    pr = OracleProblem(3, n, p, seed=44)
+    tau = pr.tau()
+    U0 = workloads.grf(n, p, seed=3)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    integ = ga.ga_integrator_create(pt, k, 0.5, tau, rtol=1e-12, maxit=200, prec=ga.GA_FP32)
+    state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    ga.ga_init_state(integ, _t(U0), _t(0 * U0), state)
+    hist = [[_np(s) for s in state]]
+    for _ in range(6):
+        ga.ga_step(integ, state, 4)
+        hist.append([_np(s) for s in state])
+    ora = pr.run(U0, 0 * U0, k, 0.5, tau, 24)
+    w = _compare(hist, ora, k, 4, 1e-10, pr.M)
+    _say("  worst rel L2 error vs oracle", w)
