@@ -136,8 +136,9 @@ def main():
     ref_state = None
     for name, prec, guess in (("fp64_zero_guess", ga.GA_FP64, ga.GA_GUESS_ZERO),
                               ("fp64_prev_guess", ga.GA_FP64, ga.GA_GUESS_PREV),
+                              ("fp64_extrap_guess", ga.GA_FP64, ga.GA_GUESS_EXTRAP),
                               ("mixed_fp32_zero_guess", ga.GA_FP32, ga.GA_GUESS_ZERO),
-                              ("mixed_fp32_prev_guess", ga.GA_FP32, ga.GA_GUESS_PREV)):
+                              ("mixed_fp32_extrap_guess", ga.GA_FP32, ga.GA_GUESS_EXTRAP)):
         integ = ga.ga_integrator_create(pt, k, rho, tau, rtol=args.rtol, maxit=200, prec=prec,
                                         guess=guess)
         state = [t.clone() for t in state0]
@@ -145,6 +146,7 @@ def main():
         if args.warmup:
             ga.ga_step(integ, state, args.warmup)
         torch.cuda.synchronize()
+        ga.ga_solve_stats(pt)
         ga.ga_profile(True)
         log(f"[bench] {name}: timed region")
         t0 = time.perf_counter()
@@ -152,6 +154,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = {kind: ga.ga_profile_query(kind) for kind in (ga.PROF_MASS, ga.PROF_STIFF, ga.PROF_PINV)}
+        sstats = ga.ga_solve_stats(pt)
         ga.ga_profile(False)
         if ref_state is None:
             ref_state = state
@@ -159,7 +162,9 @@ def main():
         else:
             err = mnorm(state[0] - ref_state[0]) / mnorm(ref_state[0])
         paths[name] = {"dof_steps_per_s": ndof * args.steps / dt, "ms_per_step": dt / args.steps * 1e3,
-                       "pcg_iters_mean": float(np.mean(its)), "rel_l2_err_vs_fp64": err, "prof": prof}
+                       "pcg_iters_mean": float(np.mean(its)), "rel_l2_err_vs_fp64": err,
+                       "guess_fallbacks": sstats["fallbacks"],
+                       "mean_guess_relres": sstats["mean_guess_relres"], "prof": prof}
         log(f"[bench] {name}: {dt / args.steps * 1e3:.3f} ms/step, iters {np.mean(its):.2f}, "
             f"rel err vs fp64 {err:.2e}")
         integ.close()

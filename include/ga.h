@@ -49,7 +49,13 @@ enum {
  * (FP32 mass factors, vectors and preconditioner; dots accumulated in FP64).
  * The stiffness apply and the state update are FP64 in both modes. */
 enum { GA_FP64 = 0, GA_FP32 = 1 };
-enum { GA_GUESS_ZERO = 0, GA_GUESS_PREV = 1 }; /* CG initial guess in ga_step */
+/* Initial guess of the stage solves in ga_step, from the stage solutions of
+ * the previous steps: zero (the paper's choice), the previous step's, or the
+ * polynomial extrapolation through the last (up to 4) steps.  A nonzero guess
+ * is kept only if its preconditioned residual is smaller than that of the
+ * zero guess; otherwise the solve restarts from zero (counted in
+ * ga_solve_stats). */
+enum { GA_GUESS_ZERO = 0, GA_GUESS_PREV = 1, GA_GUESS_EXTRAP = 2 };
 
 /*
  * ga_setup_patch -- build one patch (Sec. 5.1-5.2, eq. mass_matrix and the
@@ -72,6 +78,12 @@ int ga_destroy_patch(ga_patch* patch);
 /* Sizes: free coefficients, quadrature points, free coefficients per axis. */
 int ga_patch_info(const ga_patch* patch, long long* n_free, long long* n_quad,
                   int* mf /* [3]; mf[2] = 1 for dim 2 */);
+
+/* Counters of the mass solves since the last reset: solves, solves started
+ * from a nonzero guess, guesses rejected by the residual test, and the mean of
+ * |r0|_P / |b|_P over the guessed solves (P-norm: sqrt(r^T P^{-1} r)). */
+int ga_solve_stats(ga_patch* patch, long long* solves, long long* guessed, long long* fallbacks,
+                   double* mean_guess_relres, int reset);
 
 /* d_dev[N_free] <- diag(M) (the D of Sec. 5.4). */
 int ga_diag_M(ga_patch* patch, double* d_dev, void* stream);

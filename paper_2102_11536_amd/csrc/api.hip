@@ -240,6 +240,7 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
     pbn = partB;
   }
   launch_cg_start(nr, partA, pbn, pt->scal, rtol * rtol, st);
+  if (!zero_guess) launch_cg_fallback(nr, x, w.r, w.z, b, w.q, pt->scal, n, st);
   launch_copy(w.p, w.z, tot, st);
   if (check_launch(0, "pcg start")) return GA_EDEVICE;
   int it = 0;
@@ -264,6 +265,12 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
   bool ok = true;
   for (int r = 0; r < nr; ++r) {
     const double* s = pt->host_scal + r * NSCAL;
+    pt->n_solves += 1;
+    if (!zero_guess) {
+      pt->n_guessed += 1;
+      pt->n_fallbacks += s[S_FALLBACK] != 0.0 ? 1 : 0;
+      pt->guess_rel_sum += s[S_BN2] > 0 ? std::sqrt(std::fabs(s[S_RZ0] / s[S_BN2])) : 0.0;
+    }
     if (iters_out) iters_out[r] = (int)s[S_ITERS];
     if (relres_out) relres_out[r] = s[S_BN2] > 0 ? std::sqrt(std::fabs(s[S_RZ] / s[S_BN2])) : 0.0;
     if (s[S_ACTIVE] != 0.0) ok = false;
@@ -370,6 +377,23 @@ int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rt
     launch_dot_df(nr, r64, z32, n, partA, st);
     launch_sum_partials(nr, partA, pt->scal, st);
     if ((rc = read_scalars(pt, nr, st))) return rc;
+    if (outer == 0 && !zero_guess) {
+      // keep the initial guess only if its residual is smaller than b's
+      bool reset = false;
+      for (int r = 0; r < nr; ++r) {
+        pt->n_guessed += 1;
+        pt->guess_rel_sum += bn2[r] > 0 ? std::sqrt(std::fabs(pt->host_scal[r] / bn2[r])) : 0.0;
+        if (!(pt->host_scal[r] < bn2[r])) {  // restart this right-hand side from zero
+          reset = true;
+          pt->n_fallbacks += 1;
+          launch_fill(x + (size_t)r * n, 0.0, n, st);
+          launch_copy(r64 + (size_t)r * n, b + (size_t)r * n, n, st);
+          launch_to_f32(r32 + (size_t)r * n, b + (size_t)r * n, n, st);
+          pt->host_scal[r] = bn2[r];
+        }
+      }
+      if (reset && (rc = pinv_apply_f32(pt, nr, r32, z32, t0, t1, st))) return rc;
+    }
     bool all = true;
     for (int r = 0; r < nr; ++r) {
       rz[r] = pt->host_scal[r];
@@ -406,6 +430,7 @@ int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rt
     launch_copy(r64, b, tot, st);
     if ((rc = op_apply(pt, 0, nr, -1.0, x, r64, st))) return rc;
   }
+  pt->n_solves += nr;
   for (int r = 0; r < nr; ++r) {
     if (iters_out) iters_out[r] = inner_total[r];
     if (relres_out) relres_out[r] = bn2[r] > 0 ? std::sqrt(std::fabs(rz[r] / bn2[r])) : 0.0;
@@ -612,6 +637,17 @@ int ga_destroy_patch(ga_patch* pt) {
   return GA_OK;
 }
 
+int ga_solve_stats(ga_patch* pt, long long* solves, long long* guessed, long long* fallbacks,
+                   double* mean_guess_relres, int reset) {
+  if (!pt) { set_error("null patch"); return GA_EINVAL; }
+  if (solves) *solves = pt->n_solves;
+  if (guessed) *guessed = pt->n_guessed;
+  if (fallbacks) *fallbacks = pt->n_fallbacks;
+  if (mean_guess_relres) *mean_guess_relres = pt->n_guessed ? pt->guess_rel_sum / pt->n_guessed : 0.0;
+  if (reset) { pt->n_solves = pt->n_guessed = pt->n_fallbacks = 0; pt->guess_rel_sum = 0.0; }
+  return GA_OK;
+}
+
 int ga_patch_info(const ga_patch* pt, long long* n_free, long long* n_quad, int* mf) {
   if (!pt) { set_error("null patch"); return GA_EINVAL; }
   if (n_free) *n_free = pt->n_free;
@@ -714,7 +750,7 @@ int ga_integrator_create(ga_patch* pt, int k, double rho, double tau, double rto
   if (k < 1 || k > 4) { set_error("k must be in 1..4"); return GA_EINVAL; }
   if (!(rho >= 0.0 && rho < 1.0)) { set_error("rho must be in [0, 1)"); return GA_EINVAL; }
   if (!(tau > 0.0) || !(rtol > 0.0) || maxit < 1) { set_error("bad tau/rtol/maxit"); return GA_EINVAL; }
-  if (guess_mode != GA_GUESS_ZERO && guess_mode != GA_GUESS_PREV) { set_error("bad guess mode"); return GA_EINVAL; }
+  if (guess_mode < GA_GUESS_ZERO || guess_mode > GA_GUESS_EXTRAP) { set_error("bad guess mode"); return GA_EINVAL; }
   if (prec != GA_FP64 && prec != GA_FP32) { set_error("prec must be GA_FP64 or GA_FP32"); return GA_EINVAL; }
   if (prec == GA_FP32 && pt->dim != 3) { set_error("mixed precision needs a 3-D patch"); return GA_EINVAL; }
   ga_integrator* it = new ga_integrator();
@@ -733,7 +769,8 @@ int ga_integrator_create(ga_patch* pt, int k, double rho, double tau, double rto
   int rc;
   if ((rc = dalloc((void**)&it->Y, (size_t)k * pt->n_free * 8)) ||
       (rc = dalloc((void**)&it->Bv, (size_t)k * pt->n_free * 8)) ||
-      (rc = dalloc((void**)&it->X, (size_t)k * pt->n_free * 8))) {
+      (rc = dalloc((void**)&it->X, (size_t)k * pt->n_free * 8)) ||
+      (rc = dalloc((void**)&it->H, (size_t)4 * k * pt->n_free * 8))) {
     ga_integrator_destroy(it);
     return rc;
   }
@@ -746,6 +783,7 @@ int ga_integrator_destroy(ga_integrator* it) {
   if (it->Y) hipFree(it->Y);
   if (it->Bv) hipFree(it->Bv);
   if (it->X) hipFree(it->X);
+  if (it->H) hipFree(it->H);
   delete it;
   return GA_OK;
 }
@@ -769,6 +807,8 @@ int ga_init_state(ga_integrator* it, const double* U0, const double* V0, double*
     if (rc) return rc;
   }
   it->have_prev = false;
+  it->head = -1;
+  it->nhist = 0;
   return GA_OK;
 }
 
@@ -795,9 +835,24 @@ int ga_step(ga_integrator* it, double* const* state, int nsteps, int* iters_out,
     launch_fill(it->Bv, 0.0, (size_t)k * n, st);
     int rc = op_apply(pt, 1, k, -1.0, it->Y, it->Bv, st);
     if (rc) return rc;
-    bool zero = !(it->guess == GA_GUESS_PREV && it->have_prev);
+    // initial guess from the history of stage solutions (newest first)
+    bool zero = true;
+    if (it->guess != GA_GUESS_ZERO && it->nhist > 0) {
+      const int nh = it->guess == GA_GUESS_PREV ? 1 : it->nhist;
+      const double* hp[16] = {nullptr};
+      for (int h = 0; h < nh; ++h)
+        for (int j = 0; j < k; ++j)
+          hp[h * 4 + j] = it->H + ((size_t)((it->head - h + 4) % 4) * k + j) * n;
+      launch_extrap(k, nh, hp, it->X, n, st);
+      zero = false;
+    }
     rc = solve_any(pt, k, it->Bv, it->X, it->rtol, it->maxit, it->prec, zero, iters, nullptr, st);
     if (rc) return rc;
+    if (it->guess != GA_GUESS_ZERO) {  // push the solutions into the history ring
+      it->head = (it->head + 1) % 4;
+      launch_copy(it->H + (size_t)it->head * k * n, it->X, (size_t)k * n, st);
+      it->nhist = std::min(it->nhist + 1, 4);
+    }
     if (iters_out)
       for (int j = 0; j < k; ++j) iters_out[(size_t)step * k + j] = iters[j];
     launch_update(k, it->tau, cf, sp, it->X, n, st);

@@ -65,6 +65,9 @@ struct ga_patch {
   double* scal = nullptr;     // device scalars
   int* flags = nullptr;       // device flags
   double* host_scal = nullptr;  // pinned host mirror of scalars
+  // solve statistics
+  long long n_solves = 0, n_guessed = 0, n_fallbacks = 0;
+  double guess_rel_sum = 0.0;   // sum over guessed solves of |r0|_P / |b|_P
 };
 
 struct ga_integrator {
@@ -76,5 +79,7 @@ struct ga_integrator {
   double* Y = nullptr;        // [k][n_free] stage arguments Y_j
   double* Bv = nullptr;       // [k][n_free] stage right-hand sides -K Y_j
   double* X = nullptr;        // [k][n_free] stage solutions
+  double* H = nullptr;        // [4][k][n_free] ring of past stage solutions
+  int head = -1, nhist = 0;   // newest ring slot, number of valid slots
   bool have_prev = false;
 };

@@ -7,10 +7,12 @@
 namespace ga {
 
 constexpr int RED_BLOCKS = 256;   // partial sums per reduction
-constexpr int NSCAL = 8;          // device scalars per right-hand side
-enum { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_BETA = 3, S_BN2 = 4, S_ACTIVE = 5, S_ITERS = 6, S_TOL2 = 7 };
+constexpr int NSCAL = 12;         // device scalars per right-hand side
+enum { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_BETA = 3, S_BN2 = 4, S_ACTIVE = 5, S_ITERS = 6, S_TOL2 = 7,
+       S_FALLBACK = 8, S_RZ0 = 9 };
 
 struct StatePtrs { double* L[12]; };
+struct HistPtrs { const double* H[16]; };  // [h * 4 + j]: history slot h (newest first), stage j
 struct Coefs { double alpha[4], beta[4], gamma[4]; };
 
 int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
@@ -45,6 +47,9 @@ void launch_dot_partial(int nr, const double* a, const double* b, size_t n, doub
                         hipStream_t st);
 void launch_cg_start(int nr, const double* part_rz, const double* part_bn, double* scal,
                      double tol2, hipStream_t st);
+void launch_cg_fallback(int nr, double* x, double* r, double* z, const double* b, const double* zb,
+                        const double* scal, size_t n, hipStream_t st);
+void launch_extrap(int k, int nh, const double* const* hist, double* X, size_t n, hipStream_t st);
 void launch_cg_alpha(int nr, const double* part, double* scal, hipStream_t st);
 void launch_cg_beta(int nr, const double* part, double* scal, hipStream_t st);
 void launch_cg_xr(int nr, double* x, double* r, const double* p, const double* q,

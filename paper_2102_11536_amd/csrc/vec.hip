@@ -152,6 +152,11 @@ cg_start_k(const double* part_rz, const double* part_bn, double* scal, double to
   double bn = part_bn ? sum_part(part_bn, r, sh) : rz;
   if (threadIdx.x == 0) {
     double* s = scal + (size_t)r * NSCAL;
+    // a nonzero initial guess is kept only if its preconditioned residual is
+    // smaller than that of the zero guess (b itself); otherwise restart from zero
+    s[S_RZ0] = rz;
+    s[S_FALLBACK] = (part_bn && !(rz < bn)) ? 1.0 : 0.0;
+    if (s[S_FALLBACK] != 0.0) rz = bn;
     s[S_RZ] = rz;
     s[S_BN2] = bn;
     s[S_TOL2] = tol2;
@@ -195,6 +200,34 @@ __global__ void sum_partials_k(const double* part, double* out) {
   const int r = blockIdx.x;
   double v = sum_part(part, r, sh);
   if (threadIdx.x == 0) out[r] = v;
+}
+
+__global__ void cg_fallback_k(double* __restrict__ x, double* __restrict__ r,
+                              double* __restrict__ z, const double* __restrict__ b,
+                              const double* __restrict__ zb, const double* __restrict__ scal,
+                              size_t n) {
+  const int rr = blockIdx.y;
+  if (scal[(size_t)rr * NSCAL + S_FALLBACK] == 0.0) return;
+  const size_t off = (size_t)rr * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    x[off + i] = 0.0;
+    r[off + i] = b[off + i];
+    z[off + i] = zb[off + i];
+  }
+}
+
+// polynomial extrapolation of the stage solutions from their last nh values:
+// X = sum_h c_h H_h with c = [1], [2,-1], [3,-3,1], [4,-6,4,-1] (newest first)
+__global__ void extrap_k(int k, int nh, HistPtrs hp, double* __restrict__ X, size_t n) {
+  const double c[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    for (int j = 0; j < k; ++j) {
+      double v = 0.0;
+      for (int h = 0; h < nh; ++h) v += c[nh - 1][h] * hp.H[h * 4 + j][i];
+      X[(size_t)j * n + i] = v;
+    }
 }
 
 __global__ void cg_xr_k(double* __restrict__ x, double* __restrict__ r,
@@ -307,6 +340,16 @@ void launch_dot_partial(int nr, const double* a, const double* b, size_t n, doub
 void launch_cg_start(int nr, const double* prz, const double* pbn, double* scal, double tol2,
                      hipStream_t st) {
   hipLaunchKernelGGL(cg_start_k, dim3(nr), dim3(VB), 0, st, prz, pbn, scal, tol2);
+}
+void launch_cg_fallback(int nr, double* x, double* r, double* z, const double* b, const double* zb,
+                        const double* scal, size_t n, hipStream_t st) {
+  unsigned bl = nblocks(n) > 2048 ? 2048 : nblocks(n);
+  hipLaunchKernelGGL(cg_fallback_k, dim3(bl, nr), dim3(VB), 0, st, x, r, z, b, zb, scal, n);
+}
+void launch_extrap(int k, int nh, const double* const* hist, double* X, size_t n, hipStream_t st) {
+  HistPtrs hp;
+  for (int i = 0; i < 16; ++i) hp.H[i] = hist[i];
+  hipLaunchKernelGGL(extrap_k, dim3(nblocks(n)), dim3(VB), 0, st, k, nh, hp, X, n);
 }
 void launch_cg_alpha(int nr, const double* part, double* scal, hipStream_t st) {
   hipLaunchKernelGGL(cg_alpha_k, dim3(nr), dim3(VB), 0, st, part, scal);

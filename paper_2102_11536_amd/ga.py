@@ -12,13 +12,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libga.so")
 
 GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EGEOMETRY, GA_ENOCONV, GA_EUNSTABLE = 0, -1, -2, -3, -4, -5, -6
-GA_GUESS_ZERO, GA_GUESS_PREV = 0, 1
+GA_GUESS_ZERO, GA_GUESS_PREV, GA_GUESS_EXTRAP = 0, 1, 2
 GA_FP64, GA_FP32 = 0, 1
 
 EXPORTS = ["ga_setup_patch", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
            "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
            "ga_integrator_create", "ga_integrator_destroy", "ga_init_state", "ga_step",
-           "ga_profile", "ga_profile_query", "ga_last_error"]
+           "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error"]
 
 
 class GAError(RuntimeError):
@@ -54,6 +54,8 @@ def load_library(path=LIB_PATH):
     lib.ga_integrator_destroy.argtypes = [vp]
     lib.ga_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
     lib.ga_step.argtypes = [vp, ctypes.POINTER(vp), i, ctypes.POINTER(i), vp]
+    lib.ga_solve_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
+                                   ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d), i]
     lib.ga_profile.argtypes = [i]
     lib.ga_profile_query.argtypes = [i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
     lib.ga_last_error.restype = ctypes.c_char_p
@@ -206,3 +208,12 @@ def ga_profile_query(kind):
     ms, cnt = ctypes.c_double(), ctypes.c_longlong()
     _check(_lib.ga_profile_query(int(kind), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def ga_solve_stats(patch, reset=True):
+    """dict(solves, guessed, fallbacks, mean_guess_relres) since the last reset."""
+    a, b, c = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+    m = ctypes.c_double()
+    _check(_lib.ga_solve_stats(patch.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(m),
+                               1 if reset else 0))
+    return {"solves": a.value, "guessed": b.value, "fallbacks": c.value, "mean_guess_relres": m.value}

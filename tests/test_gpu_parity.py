@@ -309,3 +309,46 @@ def test_mixed_step_matches_oracle(k, p, n):
     ora = pr.run(U0, 0 * U0, k, 0.5, tau, 24)
     w = _compare(hist, ora, k, 4, 1e-10, pr.M)
     _say("  worst rel L2 error vs oracle", w)
+
+
+# ---- initial guesses and the residual fallback ----
+
+@pytest.mark.parametrize("prec", [ga.GA_FP64, ga.GA_FP32])
+def test_bad_guess_falls_back_to_zero(prec):
+    pr = OracleProblem(3, 5, 3)
+    pt = ga.ga_setup_patch(3, 5, 3, pr.ctrl)
+    B = np.random.default_rng(21).standard_normal(pt.n_free)
+    b = _t(B)
+    x = _t(100.0 * np.random.default_rng(22).standard_normal(pt.n_free))  # far worse than zero
+    ga.ga_solve_stats(pt)
+    ga.ga_mass_solve(pt, b, x, rtol=1e-12, prec=prec)
+    st = ga.ga_solve_stats(pt)
+    assert st["guessed"] == 1 and st["fallbacks"] == 1 and st["mean_guess_relres"] > 1.0
+    assert rel(_np(x), pr.chol.solve(B)) < 1e-10
+    # a good guess is kept
+    xs = pr.chol.solve(B)
+    x = _t(xs + 1e-6 * np.random.default_rng(23).standard_normal(pt.n_free))
+    ga.ga_mass_solve(pt, b, x, rtol=1e-12, prec=prec)
+    st = ga.ga_solve_stats(pt)
+    assert st["guessed"] == 1 and st["fallbacks"] == 0 and st["mean_guess_relres"] < 1e-3
+    assert rel(_np(x), xs) < 1e-10
+
+
+@pytest.mark.parametrize("guess", [ga.GA_GUESS_PREV, ga.GA_GUESS_EXTRAP])
+def test_history_guesses_same_answer(guess):
+    pr = OracleProblem(3, 8, 3)
+    tau = pr.tau()
+    U0 = workloads.grf(8, 3, seed=9)
+    pt = ga.ga_setup_patch(3, 8, 3, pr.ctrl)
+    h0, i0 = _run_gpu(pt, U0, 2, 0.5, tau, 16, chunk=16)
+    ga.ga_solve_stats(pt)
+    h1, i1 = _run_gpu(pt, U0, 2, 0.5, tau, 16, guess=guess, chunk=16)
+    st = ga.ga_solve_stats(pt)
+    _say("guess", guess, "iters", i0.sum(), "->", i1.sum(), st)
+    for s in range(6):
+        assert rel(h1[-1][s], h0[-1][s]) < 1e-10
+    # every solve after the first step starts from a guess; the guess residual
+    # test keeps only guesses better than zero
+    assert st["guessed"] == 2 * 15 and st["mean_guess_relres"] < 1.0
+    if guess == ga.GA_GUESS_EXTRAP:
+        assert i1.sum() < i0.sum()
