@@ -32,6 +32,8 @@ extern "C" {
 
 typedef struct ga_patch ga_patch;
 typedef struct ga_integrator ga_integrator;
+typedef struct ga_gnet ga_gnet;
+typedef struct ga_batch ga_batch;
 
 enum {
   GA_OK = 0,
@@ -51,11 +53,13 @@ enum {
 enum { GA_FP64 = 0, GA_FP32 = 1 };
 /* Initial guess of the stage solves in ga_step, from the stage solutions of
  * the previous steps: zero (the paper's choice), the previous step's, or the
- * polynomial extrapolation through the last (up to 4) steps.  A nonzero guess
- * is kept only if its preconditioned residual is smaller than that of the
- * zero guess; otherwise the solve restarts from zero (counted in
- * ga_solve_stats). */
-enum { GA_GUESS_ZERO = 0, GA_GUESS_PREV = 1, GA_GUESS_EXTRAP = 2 };
+ * polynomial extrapolation through the last (up to 4) steps, or the learned
+ * guess (a convolutional net attached per stage with ga_integrator_set_net;
+ * stages without a net, and steps with fewer than 4 past solutions, use the
+ * extrapolation).  A nonzero guess is kept only if its preconditioned
+ * residual is smaller than that of the zero guess; otherwise the solve
+ * restarts from zero (counted in ga_solve_stats). */
+enum { GA_GUESS_ZERO = 0, GA_GUESS_PREV = 1, GA_GUESS_EXTRAP = 2, GA_GUESS_LEARNED = 3 };
 
 /*
  * ga_setup_patch -- build one patch (Sec. 5.1-5.2, eq. mass_matrix and the
@@ -162,9 +166,125 @@ int ga_step(ga_integrator* integ, double* const* state_dev, int nsteps,
             int* iters_out, void* stream);
 
 /*
+ * ga_stage_solution -- copy the stage-j solution X_j of `age` steps ago
+ * (age 0 = the last step; ages 1..3 need a guess mode other than
+ * GA_GUESS_ZERO, which keeps the ring of past solutions) into out_dev
+ * [n_free].  GA_EINVAL if that solution does not exist yet.
+ */
+int ga_stage_solution(ga_integrator* integ, int stage, int age, double* out_dev, void* stream);
+
+/*
+ * Learned initial guess (not in the paper; an addition on top of its zero
+ * initial guess).  From the last four solutions H1..H4 of stage j (newest
+ * first) form the backward differences
+ *   D0 = H1, D1 = H1 - H2, D2 = H1 - 2H2 + H3, D3 = H1 - 3H2 + 3H3 - H4,
+ * their RMS values s_c (1 where D_c = 0) and the cubic extrapolation
+ * E = D0 + D1 + D2 + D3; then
+ *   guess_j = E + s_3 * net(D0/s_0, D1/s_1, D2/s_2, D3/s_3).
+ * net: a 3-layer convolutional net on the free-coefficient grid, 3x3x3
+ * kernels, channels 4 -> 32 -> 32 -> 1, ReLU after layers 1 and 2, zero
+ * padding at the grid boundary (the homogeneous Dirichlet data).
+ * Parameters: GA_GNET_NPARAM FP32 values, tap-major:
+ *   W1[27][4][32] b1[32] W2[27][32][32] b2[32] W3[27][32][1] b3[1],
+ *   tap t = 9 kz + 3 ky + kx; W[t][ci][co] multiplies input channel ci at
+ *   offset (kx-1, ky-1, kz-1) in the output channel co.
+ * Training runs in FP32 on crops of S^3 points (the target is the interior
+ * (S-6)^3); inference runs in BF16 (weights and activations) with FP32
+ * accumulation, layer 2 on MFMA.  A net owns its parameters, Adam moments and
+ * work buffers; calls that use one net on overlapping streams race.
+ */
+#define GA_GNET_NPARAM 32033
+/* params_host: GA_GNET_NPARAM floats, or NULL for all-zero parameters. */
+int ga_gnet_create(const float* params_host, ga_gnet** out);
+int ga_gnet_destroy(ga_gnet* net);
+int ga_gnet_set_params(ga_gnet* net, const float* params_host);  /* resets Adam */
+int ga_gnet_get_params(ga_gnet* net, float* params_host);
+/*
+ * ga_gnet_make_batch -- training crops from one stage of a 3-D patch:
+ *   in_dev  [nb][4][S^3]  D_c / s_c at grid points origin_b + (0..S-1)^3, zero
+ *                          outside the grid (s_c over the whole grid);
+ *   tgt_dev [nb][(S-6)^3] (X - E) / s_3 at origin_b + 3 + (0..S-7)^3.
+ * hist_dev: 4 device vectors H1..H4 [n_free]; x_dev: the solution paired with
+ * them.  origins_host [nb][3] (x, y, z); the target region must lie inside
+ * the grid: -3 <= origin_a and origin_a + S - 3 <= mf_a.  S >= 7.
+ */
+int ga_gnet_make_batch(ga_gnet* net, ga_patch* patch, const double* const* hist_dev,
+                       const double* x_dev, int nb, int S, const int* origins_host,
+                       float* in_dev, float* tgt_dev, void* stream);
+/*
+ * ga_gnet_forward -- FP32 forward pass on crops: out_dev [nb][(S-6)^3].
+ * grid3 (host, 3 ints) and origins_host (as in ga_gnet_make_batch) place the
+ * crops in the grid: layer-1 and layer-2 activations outside it are zero.
+ */
+int ga_gnet_forward(ga_gnet* net, int nb, int S, const int* grid3, const int* origins_host,
+                    const float* in_dev, float* out_dev, void* stream);
+/*
+ * ga_gnet_loss_grad -- loss = mean over the nb (S-6)^3 targets of
+ * (net - tgt)^2 and its gradient w.r.t. the parameters into grad_dev
+ * [GA_GNET_NPARAM] (FP32).  loss_out (host) may be NULL; if given, the call
+ * waits for the stream.
+ */
+int ga_gnet_loss_grad(ga_gnet* net, int nb, int S, const int* grid3, const int* origins_host,
+                      const float* in_dev, const float* tgt_dev, float* grad_dev,
+                      double* loss_out, void* stream);
+/* ga_gnet_adam -- one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with grad_dev. */
+int ga_gnet_adam(ga_gnet* net, const float* grad_dev, float lr, void* stream);
+/*
+ * ga_gnet_infer -- the learned guess on the whole free grid of a 3-D patch:
+ * x_dev [n_free] = E + s_3 * net(D / s) from hist_dev[4] (newest first), BF16
+ * inference.
+ */
+int ga_gnet_infer(ga_gnet* net, ga_patch* patch, const double* const* hist_dev, double* x_dev,
+                  void* stream);
+/* ga_integrator_set_net -- net for stage j (0-based) in GA_GUESS_LEARNED mode;
+ * NULL detaches.  The integrator does not own the net. */
+int ga_integrator_set_net(ga_integrator* integ, int stage, ga_gnet* net);
+
+/*
+ * Batched independent patches (an addition, not in the paper: the patches are
+ * not glued to each other).  One call advances R 3-D patches (p = 2..4, each
+ * axis at most 256 free coefficients) by the order-2k scheme with a common
+ * step tau, FP64 PCG with the zero initial guess.  Work on all patches shares
+ * launches: one per spline degree for each mass or stiffness apply, one per
+ * preconditioner pass and axis-length class, one for each vector operation.
+ * Batched vectors hold patch r's free coefficients (in that patch's
+ * co-lexicographic order) at entries off_r .. off_r + n_free_r - 1, with
+ * N = sum n_free_r entries in all (ga_batch_info gives N and off_r).  The
+ * patches are borrowed: they must outlive the batch.
+ */
+int ga_batch_create(int npatch, ga_patch* const* patches, int k, double rho, double tau,
+                    double rtol, int maxit, ga_batch** out);
+int ga_batch_destroy(ga_batch* batch);
+/* n_total: N; offsets_out[npatch] (may be NULL); graph_replays: PCG iterations
+ * run so far as replays of the captured iteration graph (may be NULL). */
+int ga_batch_info(const ga_batch* batch, long long* n_total, long long* offsets_out,
+                  long long* graph_replays);
+/*
+ * ga_batch_tune -- autotuner: for each operator launch (mass, stiffness; per
+ * degree) time `reps` launches of each candidate tile shape (element layers
+ * per tile along z) and workgroup count of the tile queue, keep the fastest.
+ * best_ms (may be NULL): summed time of one launch of each tuned operator.
+ */
+int ga_batch_tune(ga_batch* batch, int reps, double* best_ms, void* stream);
+/* L^{-2} = U0, L^{-1} = V0, L^a = M^{-1}(-K L^{a-2}) patch by patch; batched
+ * vectors of N entries. */
+int ga_batch_init_state(ga_batch* batch, const double* U0_dev, const double* V0_dev,
+                        double* const* state_dev, void* stream);
+/*
+ * ga_batch_step -- nsteps steps of every patch.  use_graph != 0: each PCG
+ * iteration is a replay of a captured hipGraph (run on a stream the batch
+ * owns, ordered after `stream`).  iters_out: host [nsteps][k * npatch] PCG
+ * iterations of system j * npatch + r (stage j, patch r), or NULL.  Waits for
+ * the work before returning.
+ */
+int ga_batch_step(ga_batch* batch, double* const* state_dev, int nsteps, int use_graph,
+                  int* iters_out, void* stream);
+
+/*
  * Launch timing (instrumentation, not part of the method): with profiling on,
- * every operator launch (kind 0 = mass apply, 1 = stiffness apply) and every
- * preconditioner application (kind 2) is bracketed by HIP events on the
+ * every operator launch (kind 0 = mass apply, 1 = stiffness apply), every
+ * preconditioner application (kind 2) and every learned-guess inference in
+ * ga_step (kind 3) is bracketed by HIP events on the
  * stream it runs on.  ga_profile(enable) clears the totals;
  * ga_profile_query waits for the recorded events and returns the summed
  * duration in ms and the number of launches of one kind.  Host-global state,

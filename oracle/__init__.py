@@ -19,6 +19,8 @@ with sparse-matrix library calls as the only building blocks:
 * ``galpha``    -- parameters, predictor/stage/update step and initialisation of
                    the order-2k scheme (Sec. 3-4, eqs. ho1-ho3), and the scalar
                    amplification matrix used by the pins.
+* ``convnet``   -- the learned initial guess (an addition, not in the paper):
+                   network definition, crop loss and its gradient, Adam.
 
 Readings of passages that are silent, ambiguous or garbled are listed in the
 module docstrings where they apply.  Parity status: every function is pinned

@@ -20,27 +20,31 @@ void set_error(const std::string& m) { g_err = m; }
 
 using namespace ga;
 
-#define GA_TRY_HIP(call)                                                                   \
-  do {                                                                                     \
-    hipError_t e_ = (call);                                                                \
-    if (e_ != hipSuccess) {                                                                \
-      set_error(std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_));      \
-      return GA_EDEVICE;                                                                   \
-    }                                                                                      \
-  } while (0)
+namespace ga {
+
+// Stability limit: the lambda = -1 crossing of the characteristic polynomial
+// of the last diagonal block (printed in Sec. 3), i.e. Theta (8 beta - 4 gamma)
+// = 16 alpha - 8, with the block-k parameters.
+void block_k_params(double rho, double& a, double& b, double& g) {
+  const double rb = rho, rs = rho;
+  a = (2 + (1 - rb) * rs) / ((1 + rb) * (1 + rs));
+  b = (-5 - 3 * rb - 4 * rs + 2 * rb * rs + 2 * rb * rb * rs - rs * rs + rb * rs * rs) /
+      ((1 + rb) * (1 + rb) * (-2 - 3 * rs + rb * rs - rs * rs + rb * rs * rs));
+  g = 0.5 + a;  // gamma = 1/2 - alpha_f + alpha with alpha_f = 0
+}
+
+// blocks j < k: the printed formulas evaluated at rho_b = rho_s = -rho
+void block_j_params(double rho, double& a, double& b, double& g) {
+  const double rb = -rho, rs = -rho;
+  a = (2 - (1 + rb) * rs) / ((-1 + rb) * (-1 + rs));
+  b = (1 + rb) * (-1 + rb * rs) * (-1 + rb * rs) /
+      ((-1 + rb) * (-1 + rb) * (-1 + rs) * (-2 + rs + rb * rs));
+  g = 0.5 - 1.0 + a;  // alpha_f = 1
+}
+
+}  // namespace ga
 
 namespace {
-
-hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
-int dalloc(void** p, size_t bytes) {
-  if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("hipMalloc failed (" + std::to_string(bytes) + " bytes)");
-    return GA_ENOMEM;
-  }
-  return GA_OK;
-}
 
 template <class T>
 int upload(T** dst, const std::vector<T>& v) {
@@ -50,22 +54,14 @@ int upload(T** dst, const std::vector<T>& v) {
   return GA_OK;
 }
 
-int check_launch(int rc, const char* what) {
-  hipError_t e = hipGetLastError();
-  if (rc != 0 || e != hipSuccess) {
-    set_error(std::string("kernel launch failed: ") + what + " (" + hipGetErrorString(e) + ")");
-    return GA_EDEVICE;
-  }
-  return GA_OK;
-}
 
 // ---- optional HIP-event timing of the operator and preconditioner launches ----
 struct ProfState {
   bool on = false;
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
-  double total_ms[3] = {0, 0, 0};
-  long long count[3] = {0, 0, 0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];
+  double total_ms[4] = {0, 0, 0, 0};
+  long long count[4] = {0, 0, 0, 0};
 };
 ProfState g_prof;
 
@@ -181,26 +177,6 @@ int pinv_apply(ga_patch* pt, int nr, const double* r, double* z, double* t0, dou
   }
   launch_scale_mul(z, last, pt->s, nr, n, st);
   return check_launch(0, "preconditioner");
-}
-
-// Stability limit: the lambda = -1 crossing of the characteristic polynomial
-// of the last diagonal block (printed in Sec. 3), i.e. Theta (8 beta - 4 gamma)
-// = 16 alpha - 8, with the block-k parameters.
-void block_k_params(double rho, double& a, double& b, double& g) {
-  const double rb = rho, rs = rho;
-  a = (2 + (1 - rb) * rs) / ((1 + rb) * (1 + rs));
-  b = (-5 - 3 * rb - 4 * rs + 2 * rb * rs + 2 * rb * rb * rs - rs * rs + rb * rs * rs) /
-      ((1 + rb) * (1 + rb) * (-2 - 3 * rs + rb * rs - rs * rs + rb * rs * rs));
-  g = 0.5 + a;  // gamma = 1/2 - alpha_f + alpha with alpha_f = 0
-}
-
-// blocks j < k: the printed formulas evaluated at rho_b = rho_s = -rho
-void block_j_params(double rho, double& a, double& b, double& g) {
-  const double rb = -rho, rs = -rho;
-  a = (2 - (1 + rb) * rs) / ((-1 + rb) * (-1 + rs));
-  b = (1 + rb) * (-1 + rb * rs) * (-1 + rb * rs) /
-      ((-1 + rb) * (-1 + rb) * (-1 + rs) * (-2 + rs + rb * rs));
-  g = 0.5 - 1.0 + a;  // alpha_f = 1
 }
 
 struct SolveBufs {
@@ -456,14 +432,14 @@ extern "C" {
 const char* ga_last_error(void) { return g_err.c_str(); }
 
 int ga_profile(int enable) {
-  for (int k = 0; k < 3; ++k) prof_drain(k);
-  for (int k = 0; k < 3; ++k) { g_prof.total_ms[k] = 0.0; g_prof.count[k] = 0; }
+  for (int k = 0; k < 4; ++k) prof_drain(k);
+  for (int k = 0; k < 4; ++k) { g_prof.total_ms[k] = 0.0; g_prof.count[k] = 0; }
   g_prof.on = enable != 0;
   return GA_OK;
 }
 
 int ga_profile_query(int kind, double* total_ms, long long* launches) {
-  if (kind < 0 || kind > 2 || !total_ms || !launches) { set_error("bad argument"); return GA_EINVAL; }
+  if (kind < 0 || kind > 3 || !total_ms || !launches) { set_error("bad argument"); return GA_EINVAL; }
   prof_drain(kind);
   *total_ms = g_prof.total_ms[kind];
   *launches = g_prof.count[kind];
@@ -750,7 +726,7 @@ int ga_integrator_create(ga_patch* pt, int k, double rho, double tau, double rto
   if (k < 1 || k > 4) { set_error("k must be in 1..4"); return GA_EINVAL; }
   if (!(rho >= 0.0 && rho < 1.0)) { set_error("rho must be in [0, 1)"); return GA_EINVAL; }
   if (!(tau > 0.0) || !(rtol > 0.0) || maxit < 1) { set_error("bad tau/rtol/maxit"); return GA_EINVAL; }
-  if (guess_mode < GA_GUESS_ZERO || guess_mode > GA_GUESS_EXTRAP) { set_error("bad guess mode"); return GA_EINVAL; }
+  if (guess_mode < GA_GUESS_ZERO || guess_mode > GA_GUESS_LEARNED) { set_error("bad guess mode"); return GA_EINVAL; }
   if (prec != GA_FP64 && prec != GA_FP32) { set_error("prec must be GA_FP64 or GA_FP32"); return GA_EINVAL; }
   if (prec == GA_FP32 && pt->dim != 3) { set_error("mixed precision needs a 3-D patch"); return GA_EINVAL; }
   ga_integrator* it = new ga_integrator();
@@ -786,6 +762,26 @@ int ga_integrator_destroy(ga_integrator* it) {
   if (it->H) hipFree(it->H);
   delete it;
   return GA_OK;
+}
+
+int ga_integrator_set_net(ga_integrator* it, int stage, ga_gnet* net) {
+  if (!it) { set_error("null integrator"); return GA_EINVAL; }
+  if (stage < 0 || stage >= it->k) { set_error("stage out of range"); return GA_EINVAL; }
+  if (net && it->patch->dim != 3) { set_error("the learned guess needs a 3-D patch"); return GA_EINVAL; }
+  it->nets[stage] = net;
+  return GA_OK;
+}
+
+int ga_stage_solution(ga_integrator* it, int stage, int age, double* out, void* stream) {
+  if (!it || !out) { set_error("null argument"); return GA_EINVAL; }
+  if (stage < 0 || stage >= it->k || age < 0 || age > 3) { set_error("stage or age out of range"); return GA_EINVAL; }
+  const size_t n = it->patch->n_free;
+  const double* src = nullptr;
+  if (age < it->nhist) src = it->H + ((size_t)((it->head - age + 4) % 4) * it->k + stage) * n;
+  else if (age == 0 && it->have_prev) src = it->X + (size_t)stage * n;
+  if (!src) { set_error("no stage solution of that age yet"); return GA_EINVAL; }
+  launch_copy(out, src, n, S(stream));
+  return check_launch(0, "stage solution copy");
 }
 
 int ga_init_state(ga_integrator* it, const double* U0, const double* V0, double* const* state,
@@ -844,6 +840,15 @@ int ga_step(ga_integrator* it, double* const* state, int nsteps, int* iters_out,
         for (int j = 0; j < k; ++j)
           hp[h * 4 + j] = it->H + ((size_t)((it->head - h + 4) % 4) * k + j) * n;
       launch_extrap(k, nh, hp, it->X, n, st);
+      if (it->guess == GA_GUESS_LEARNED && it->nhist == 4) {
+        for (int j = 0; j < k; ++j) {
+          if (!it->nets[j]) continue;
+          const double* hj[4] = {hp[j], hp[4 + j], hp[8 + j], hp[12 + j]};
+          ProfScope prof(3, st);
+          rc = gnet_guess(it->nets[j], pt, hj, it->X + (size_t)j * n, st);
+          if (rc) return rc;
+        }
+      }
       zero = false;
     }
     rc = solve_any(pt, k, it->Bv, it->X, it->rtol, it->maxit, it->prec, zero, iters, nullptr, st);

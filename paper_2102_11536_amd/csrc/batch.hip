@@ -1,0 +1,520 @@
+// Batched independent patches: one order-2k step advances every patch of the
+// batch together.  The patches do not interact (no interface coupling); they
+// share launches instead of each paying its own:
+//   - vectors are batched: patch r's free coefficients occupy entries
+//     off_r .. off_r + n_r - 1 of one long vector of N = sum n_r entries, and
+//     the k stage vectors are N entries apart, so the Taylor predictors and the
+//     state update are single streaming launches over N;
+//   - the mass and stiffness applies run as one launch per spline degree over
+//     a queue of the tiles of every patch of that degree (the workgroup shape
+//     depends on p, so degrees cannot share a launch);
+//   - each preconditioner pass runs as one launch per register-tile class of
+//     the axis length over all patches;
+//   - the PCG vector updates and inner products are segment-aware: the k*R
+//     systems (stage j, patch r) keep their own scalars and stop on their own.
+// One PCG iteration is a fixed sequence of launches; it is captured once in a
+// hipGraph (on a stream the batch owns, ordered after the caller's stream by
+// events) and replayed, the host reading the per-system convergence flags
+// between replays.  ga_batch_tune times the element layers per tile (ze) and
+// the number of workgroups of the tile-queue launches and keeps the fastest.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "ga_internal.h"
+#include "kernels.h"
+
+using namespace ga;
+
+namespace {
+
+struct OpGroup {
+  int p = 0, mode = 0;
+  std::vector<const ga_patch*> pts;
+  std::vector<long long> offs;
+  int ze_override = 0;        // 0: each patch's default
+  int nwg = 0;                // 0: one workgroup per tile
+  OpGroupEntry* ents = nullptr;
+  int nent = 0, total = 0;
+};
+
+struct PGroup {
+  int nr = 0, pass = 0, ra = 0;
+  PinvEntry* ents = nullptr;
+  int nent = 0, nblk = 0;
+};
+
+}  // namespace
+
+struct ga_batch {
+  int R = 0, k = 1, maxit = 200;
+  double rho = 0.5, tau = 0.0, rtol = 1e-10;
+  double alpha[4], beta[4], gamma[4];
+  std::vector<ga_patch*> pts;
+  std::vector<long long> off;
+  long long N = 0, maxlen = 0;
+  std::vector<OpGroup> ops[2];   // mass, stiffness
+  std::vector<PGroup> pgroups;
+  long long* seg = nullptr;      // [k*R][2]
+  double *Y = nullptr, *Bv = nullptr, *X = nullptr, *work = nullptr;
+  double *red = nullptr, *scal = nullptr, *host_scal = nullptr;
+  hipStream_t gs = nullptr;      // stream of the captured iteration
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  long long n_iters = 0, n_replays = 0;
+};
+
+namespace {
+
+int upload_op_group(OpGroup& g) {
+  std::vector<OpGroupEntry> h;
+  int tile = 0;
+  for (size_t i = 0; i < g.pts.size(); ++i) {
+    const int ze = g.ze_override > 0 ? std::min(g.ze_override, g.pts[i]->n[2])
+                                     : op3d_default_ze(g.mode, g.pts[i]);
+    OpGroupEntry e = op3d_group_entry(g.mode, g.pts[i], ze, g.offs[i], tile, false);
+    tile += e.ntiles;
+    h.push_back(e);
+  }
+  if (g.ents) hipFree(g.ents);
+  g.ents = nullptr;
+  int rc = dalloc((void**)&g.ents, h.size() * sizeof(OpGroupEntry));
+  if (rc) return rc;
+  GA_TRY_HIP(hipMemcpy(g.ents, h.data(), h.size() * sizeof(OpGroupEntry), hipMemcpyHostToDevice));
+  g.nent = (int)h.size();
+  g.total = tile;
+  return GA_OK;
+}
+
+int op_batch(ga_batch* b, int mode, int nr, double alpha, const double* x, double* y,
+             hipStream_t st) {
+  for (int r0 = 0; r0 < nr; r0 += 3) {   // at most 3 right-hand sides per launch
+    const int c = std::min(3, nr - r0);
+    for (OpGroup& g : b->ops[mode]) {
+      const int nwg = g.nwg > 0 ? std::min(g.nwg, g.total) : g.total;
+      if (launch_op3d_group<double>(g.p, mode, c, g.ents, g.nent, x + (size_t)r0 * b->N,
+                                    y + (size_t)r0 * b->N, b->N, alpha, g.total, nwg, st))
+        return check_launch(-1, "batched operator");
+    }
+  }
+  return GA_OK;
+}
+
+// entries of one preconditioner pass for nr right-hand sides, grouped by the
+// register-tile class of the axis length
+int build_pgroups(ga_batch* b, int nr) {
+  for (int pass = 0; pass < 3; ++pass) {
+    std::vector<PinvEntry> cls[3];
+    int blk[3] = {0, 0, 0};
+    for (int r = 0; r < b->R; ++r) {
+      const ga_patch* pt = b->pts[r];
+      const long long m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
+      PinvEntry e{};
+      e.off = b->off[r];
+      e.si = e.so = nullptr;
+      long long nb = 0;
+      if (pass == 0) {
+        e.A = pt->Minv[0];
+        e.L = (int)m0;
+        e.si = pt->s;
+        e.p[0] = nr * m1 * m2;
+        e.p[1] = m1 * m2;
+        nb = (e.p[0] + 63) / 64;
+      } else if (pass == 1) {
+        e.A = pt->Minv[1];
+        e.L = (int)m1;
+        e.p[0] = m0;
+        e.p[1] = m0;
+        e.p[2] = m0 * m1;
+        e.p[3] = m0 * m2;
+        nb = (e.p[3] + 63) / 64;
+      } else {
+        e.A = pt->Minv[2];
+        e.L = (int)m2;
+        e.so = pt->s;
+        e.p[0] = m0 * m1;
+        e.p[1] = m0 * m1;
+        e.p[2] = 0;
+        e.p[3] = m0 * m1;
+        nb = (e.p[3] + 63) / 64;
+      }
+      const int c = pinv_ra_class(e.L);
+      e.blk0 = blk[c];
+      blk[c] += (int)nb;
+      cls[c].push_back(e);
+    }
+    for (int c = 0; c < 3; ++c) {
+      if (cls[c].empty()) continue;
+      PGroup g;
+      g.nr = nr;
+      g.pass = pass;
+      g.ra = c;
+      g.nent = (int)cls[c].size();
+      g.nblk = blk[c];
+      int rc = dalloc((void**)&g.ents, cls[c].size() * sizeof(PinvEntry));
+      if (rc) return rc;
+      GA_TRY_HIP(hipMemcpy(g.ents, cls[c].data(), cls[c].size() * sizeof(PinvEntry),
+                           hipMemcpyHostToDevice));
+      b->pgroups.push_back(g);
+    }
+  }
+  return GA_OK;
+}
+
+// z = P^{-1} r for every patch (three passes, scaling folded into the first and last)
+int pinv_batch(ga_batch* b, int nr, const double* r, double* z, double* t0, double* t1,
+               hipStream_t st) {
+  const double* in[3] = {r, t1, t0};
+  double* out[3] = {t1, t0, z};
+  for (int pass = 0; pass < 3; ++pass)
+    for (const PGroup& g : b->pgroups)
+      if (g.nr == nr && g.pass == pass)
+        launch_pinv_group<double>(pass, g.ra, g.ents, g.nent, g.nblk, nr, in[pass], out[pass], b->N, st);
+  return check_launch(0, "batched preconditioner");
+}
+
+struct Bufs {
+  double *r, *z, *p, *q, *t0, *t1;
+};
+
+Bufs bufs(ga_batch* b) {
+  const size_t kn = (size_t)b->k * b->N;
+  Bufs w{b->work, b->work + kn, b->work + 2 * kn, b->work + 3 * kn, b->work + 4 * kn, b->work + 5 * kn};
+  return w;
+}
+
+// one PCG iteration of every active system (fixed launch sequence)
+int pcg_iteration(ga_batch* b, int nr, double* x, hipStream_t st) {
+  const int ns = nr * b->R;
+  Bufs w = bufs(b);
+  double* partA = b->red;
+  launch_fill(w.q, 0.0, (size_t)nr * b->N, st);
+  int rc = op_batch(b, 0, nr, 1.0, w.p, w.q, st);
+  if (rc) return rc;
+  launch_dot_partial_seg(ns, w.p, w.q, b->seg, partA, st);
+  launch_cg_alpha(ns, partA, b->scal, st);
+  launch_cg_xr_seg(ns, x, w.r, w.p, w.q, b->scal, b->seg, b->maxlen, st);
+  if ((rc = pinv_batch(b, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+  launch_dot_partial_seg(ns, w.r, w.z, b->seg, partA, st);
+  launch_cg_beta(ns, partA, b->scal, st);
+  launch_cg_p_seg(ns, w.p, w.z, b->scal, b->seg, b->maxlen, st);
+  return check_launch(0, "batched pcg iteration");
+}
+
+void drop_graph(ga_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+int capture_iteration(ga_batch* b) {
+  drop_graph(b);
+  GA_TRY_HIP(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
+  int rc = pcg_iteration(b, b->k, b->X, b->gs);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->gs, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+    return GA_EDEVICE;
+  }
+  b->graph = g;
+  GA_TRY_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return GA_OK;
+}
+
+// batched PCG, zero initial guess, nr right-hand sides per patch: systems
+// s = j*R + r, rhs j of patch r; x and b are [nr][N]
+int solve_batch(ga_batch* b, int nr, const double* rhs, double* x, bool graph, int* iters_out,
+                hipStream_t st) {
+  const int ns = nr * b->R;
+  const size_t tot = (size_t)nr * b->N;
+  Bufs w = bufs(b);
+  double* partA = b->red;
+  launch_fill(x, 0.0, tot, st);
+  launch_copy(w.r, rhs, tot, st);
+  int rc = pinv_batch(b, nr, w.r, w.z, w.t0, w.t1, st);
+  if (rc) return rc;
+  launch_dot_partial_seg(ns, w.r, w.z, b->seg, partA, st);
+  launch_cg_start(ns, partA, nullptr, b->scal, b->rtol * b->rtol, st);
+  launch_copy(w.p, w.z, tot, st);
+  if (check_launch(0, "batched pcg start")) return GA_EDEVICE;
+  const bool use_graph = graph && nr == b->k && x == b->X;
+  if (use_graph && !b->exec && (rc = capture_iteration(b))) return rc;
+  for (int it = 0;; ++it) {
+    GA_TRY_HIP(hipMemcpyAsync(b->host_scal, b->scal, sizeof(double) * NSCAL * ns,
+                              hipMemcpyDeviceToHost, st));
+    GA_TRY_HIP(hipStreamSynchronize(st));
+    bool any = false;
+    for (int s = 0; s < ns; ++s) any |= b->host_scal[s * NSCAL + S_ACTIVE] != 0.0;
+    if (!any || it >= b->maxit) break;
+    if (use_graph) {
+      GA_TRY_HIP(hipGraphLaunch(b->exec, st));
+      b->n_replays += 1;
+    } else if ((rc = pcg_iteration(b, nr, x, st))) {
+      return rc;
+    }
+    b->n_iters += 1;
+  }
+  bool ok = true;
+  for (int s = 0; s < ns; ++s) {
+    const double* sc = b->host_scal + s * NSCAL;
+    if (iters_out) iters_out[s] = (int)sc[S_ITERS];
+    if (sc[S_ACTIVE] != 0.0 || !std::isfinite(sc[S_RZ])) ok = false;
+  }
+  if (!ok) {
+    set_error("batched PCG did not converge within maxit");
+    return GA_ENOCONV;
+  }
+  return GA_OK;
+}
+
+void free_batch(ga_batch* b) {
+  drop_graph(b);
+  for (int m = 0; m < 2; ++m)
+    for (OpGroup& g : b->ops[m])
+      if (g.ents) hipFree(g.ents);
+  for (PGroup& g : b->pgroups)
+    if (g.ents) hipFree(g.ents);
+  for (void* p : {(void*)b->seg, (void*)b->Y, (void*)b->Bv, (void*)b->X, (void*)b->work,
+                  (void*)b->red, (void*)b->scal})
+    if (p) hipFree(p);
+  if (b->host_scal) hipHostFree(b->host_scal);
+  for (hipEvent_t e : b->ev)
+    if (e) hipEventDestroy(e);
+  if (b->gs) hipStreamDestroy(b->gs);
+  delete b;
+}
+
+// order the batch stream after the caller's stream (or the reverse)
+int join(hipStream_t from, hipStream_t to, hipEvent_t ev) {
+  GA_TRY_HIP(hipEventRecord(ev, from));
+  GA_TRY_HIP(hipStreamWaitEvent(to, ev, 0));
+  return GA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ga_batch_create(int npatch, ga_patch* const* patches, int k, double rho, double tau,
+                    double rtol, int maxit, ga_batch** out) {
+  if (!out || !patches) { set_error("null argument"); return GA_EINVAL; }
+  *out = nullptr;
+  if (npatch < 1 || npatch > 64) { set_error("npatch must be in 1..64"); return GA_EINVAL; }
+  if (k < 1 || k > 4) { set_error("k must be in 1..4"); return GA_EINVAL; }
+  if (!(rho >= 0.0 && rho < 1.0) || !(tau > 0.0) || !(rtol > 0.0) || maxit < 1) {
+    set_error("bad rho/tau/rtol/maxit");
+    return GA_EINVAL;
+  }
+  for (int r = 0; r < npatch; ++r) {
+    const ga_patch* pt = patches[r];
+    if (!pt) { set_error("null patch"); return GA_EINVAL; }
+    if (pt->dim != 3 || pt->p < 2 || pt->p > 4) {
+      set_error("batched patches must be 3-D with p in 2..4");
+      return GA_EINVAL;
+    }
+    for (int a = 0; a < 3; ++a)
+      if (!pinv_axis_supported(pt->mf[a])) {
+        set_error("batched patches need at most 256 free coefficients per axis");
+        return GA_EINVAL;
+      }
+  }
+  ga_batch* b = new ga_batch();
+  b->R = npatch;
+  b->k = k;
+  b->rho = rho;
+  b->tau = tau;
+  b->rtol = rtol;
+  b->maxit = maxit;
+  for (int j = 0; j < k; ++j) {
+    if (j < k - 1) block_j_params(rho, b->alpha[j], b->beta[j], b->gamma[j]);
+    else block_k_params(rho, b->alpha[j], b->beta[j], b->gamma[j]);
+  }
+  for (int r = 0; r < npatch; ++r) {
+    b->pts.push_back(patches[r]);
+    b->off.push_back(b->N);
+    b->N += patches[r]->n_free;
+    b->maxlen = std::max(b->maxlen, patches[r]->n_free);
+  }
+  int rc = GA_OK;
+  auto fail = [&](int code) {
+    free_batch(b);
+    return code;
+  };
+  for (int mode = 0; mode < 2; ++mode)
+    for (int p = 2; p <= 4; ++p) {
+      OpGroup g;
+      g.p = p;
+      g.mode = mode;
+      for (int r = 0; r < npatch; ++r)
+        if (patches[r]->p == p) {
+          g.pts.push_back(patches[r]);
+          g.offs.push_back(b->off[r]);
+        }
+      if (g.pts.empty()) continue;
+      b->ops[mode].push_back(g);
+      if ((rc = upload_op_group(b->ops[mode].back()))) return fail(rc);
+    }
+  if ((rc = build_pgroups(b, 1))) return fail(rc);
+  if (k > 1 && (rc = build_pgroups(b, k))) return fail(rc);
+  std::vector<long long> seg;
+  for (int j = 0; j < k; ++j)
+    for (int r = 0; r < npatch; ++r) {
+      seg.push_back((long long)j * b->N + b->off[r]);
+      seg.push_back(patches[r]->n_free);
+    }
+  const size_t kn = (size_t)k * b->N;
+  const int ns = k * npatch;
+  if ((rc = dalloc((void**)&b->seg, seg.size() * sizeof(long long))) ||
+      (rc = dalloc((void**)&b->Y, kn * 8)) || (rc = dalloc((void**)&b->Bv, kn * 8)) ||
+      (rc = dalloc((void**)&b->X, kn * 8)) || (rc = dalloc((void**)&b->work, 6 * kn * 8)) ||
+      (rc = dalloc((void**)&b->red, (size_t)ns * RED_BLOCKS * 8)) ||
+      (rc = dalloc((void**)&b->scal, (size_t)ns * NSCAL * 8)))
+    return fail(rc);
+  if (hipHostMalloc((void**)&b->host_scal, (size_t)ns * NSCAL * 8, hipHostMallocDefault) != hipSuccess) {
+    set_error("pinned host allocation failed");
+    return fail(GA_ENOMEM);
+  }
+  if (hipMemcpy(b->seg, seg.data(), seg.size() * sizeof(long long), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) != hipSuccess) {
+    set_error("batch stream/event setup failed");
+    return fail(GA_EDEVICE);
+  }
+  *out = b;
+  return GA_OK;
+}
+
+int ga_batch_destroy(ga_batch* b) {
+  if (!b) return GA_OK;
+  hipDeviceSynchronize();
+  free_batch(b);
+  return GA_OK;
+}
+
+int ga_batch_info(const ga_batch* b, long long* n_total, long long* offsets, long long* replays) {
+  if (!b) { set_error("null batch"); return GA_EINVAL; }
+  if (n_total) *n_total = b->N;
+  if (offsets)
+    for (int r = 0; r < b->R; ++r) offsets[r] = b->off[r];
+  if (replays) *replays = b->n_replays;
+  return GA_OK;
+}
+
+int ga_batch_tune(ga_batch* b, int reps, double* best_ms, void* stream) {
+  if (!b || reps < 1) { set_error("bad argument"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  Bufs w = bufs(b);
+  hipEvent_t e0, e1;
+  GA_TRY_HIP(hipEventCreate(&e0));
+  GA_TRY_HIP(hipEventCreate(&e1));
+  double total = 0.0;
+  int rc = GA_OK;
+  const int nr = std::min(b->k, 3);
+  launch_fill(w.t0, 0.0, (size_t)b->k * b->N, st);
+  launch_fill(w.t1, 0.0, (size_t)b->k * b->N, st);
+  for (int mode = 0; mode < 2 && !rc; ++mode)
+    for (OpGroup& g : b->ops[mode]) {
+      int best_ze = g.ze_override, best_nwg = g.nwg;
+      double best = 1e30;
+      std::vector<int> zes = {0, 2, 4, 8, 16, 32};
+      for (int ze : zes) {
+        g.ze_override = ze;
+        if ((rc = upload_op_group(g))) break;
+        for (int nwgc : {0, 2048, 1024}) {
+          if (nwgc > 0 && nwgc >= g.total) continue;
+          g.nwg = nwgc;
+          const int nwg = nwgc > 0 ? nwgc : g.total;
+          // warm-up, then timed launches (k right-hand sides, scratch vectors)
+          launch_op3d_group<double>(g.p, mode, nr, g.ents, g.nent, w.t0, w.t1, b->N, 1.0,
+                                    g.total, nwg, st);
+          hipEventRecord(e0, st);
+          for (int i = 0; i < reps; ++i)
+            launch_op3d_group<double>(g.p, mode, nr, g.ents, g.nent, w.t0, w.t1, b->N, 1.0,
+                                      g.total, nwg, st);
+          hipEventRecord(e1, st);
+          if (hipEventSynchronize(e1) != hipSuccess) { rc = check_launch(-1, "tuning"); break; }
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, e0, e1);
+          if (ms < best) { best = ms; best_ze = ze; best_nwg = nwgc; }
+        }
+        if (rc) break;
+      }
+      if (rc) break;
+      g.ze_override = best_ze;
+      g.nwg = best_nwg;
+      if ((rc = upload_op_group(g))) break;
+      total += best / reps;
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  drop_graph(b);   // the captured iteration used the old launch shapes
+  if (best_ms) *best_ms = total;
+  return check_launch(0, "tuning");
+}
+
+int ga_batch_init_state(ga_batch* b, const double* U0, const double* V0, double* const* state,
+                        void* stream) {
+  if (!b || !U0 || !V0 || !state) { set_error("null argument"); return GA_EINVAL; }
+  for (int s = 0; s < 3 * b->k; ++s)
+    if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  const size_t n = b->N;
+  launch_copy(state[0], U0, n, st);
+  launch_copy(state[1], V0, n, st);
+  for (int a = 0; a <= 3 * b->k - 3; ++a) {
+    launch_fill(b->Y, 0.0, n, st);
+    int rc = op_batch(b, 1, 1, -1.0, state[a], b->Y, st);
+    if (rc) return rc;
+    if ((rc = solve_batch(b, 1, b->Y, state[a + 2], false, nullptr, st))) return rc;
+  }
+  return GA_OK;
+}
+
+int ga_batch_step(ga_batch* b, double* const* state, int nsteps, int use_graph, int* iters_out,
+                  void* stream) {
+  if (!b || !state || nsteps < 0) { set_error("bad argument"); return GA_EINVAL; }
+  const int k = b->k, ns = 3 * k;
+  for (int s = 0; s < ns; ++s)
+    if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+  hipStream_t cst = S(stream);
+  hipStream_t st = use_graph ? b->gs : cst;
+  int rc;
+  if (use_graph && (rc = join(cst, st, b->ev[0]))) return rc;
+  const size_t n = b->N;
+  StatePtrs sp;
+  for (int s = 0; s < 12; ++s) sp.L[s] = s < ns ? state[s] : nullptr;
+  Coefs cf;
+  for (int j = 0; j < 4; ++j) {
+    cf.alpha[j] = j < k ? b->alpha[j] : 1.0;
+    cf.beta[j] = j < k ? b->beta[j] : 0.0;
+    cf.gamma[j] = j < k ? b->gamma[j] : 0.0;
+  }
+  std::vector<int> its((size_t)k * b->R);
+  for (int step = 0; step < nsteps; ++step) {
+    launch_predict(k, b->tau, sp, b->Y, n, st);
+    launch_fill(b->Bv, 0.0, (size_t)k * n, st);
+    if ((rc = op_batch(b, 1, k, -1.0, b->Y, b->Bv, st))) return rc;
+    if ((rc = solve_batch(b, k, b->Bv, b->X, use_graph != 0, its.data(), st))) return rc;
+    if (iters_out)
+      for (size_t s = 0; s < its.size(); ++s) iters_out[(size_t)step * its.size() + s] = its[s];
+    launch_update(k, b->tau, cf, sp, b->X, n, st);
+    if (check_launch(0, "batched update")) return GA_EDEVICE;
+  }
+  if (use_graph && (rc = join(st, cst, b->ev[1]))) return rc;
+  GA_TRY_HIP(hipStreamSynchronize(cst));
+  return GA_OK;
+}
+
+}  // extern "C"

@@ -1,6 +1,8 @@
 // Internal declarations of the ga library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstddef>
 #include <string>
 #include <vector>
@@ -34,6 +36,43 @@ constexpr int te3_mass(int p) { return (p + 1) * GA_TE3_MASS > 32 ? 32 / (p + 1)
 constexpr int TE2 = 8;   // 2-D tile: 8 x 8 elements
 
 void set_error(const std::string& msg);
+
+#define GA_TRY_HIP(call)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      ga::set_error(std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_));  \
+      return GA_EDEVICE;                                                                   \
+    }                                                                                      \
+  } while (0)
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int dalloc(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+    return GA_ENOMEM;
+  }
+  return GA_OK;
+}
+
+inline int check_launch(int rc, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (rc != 0 || e != hipSuccess) {
+    set_error(std::string("kernel launch failed: ") + what + " (" + hipGetErrorString(e) + ")");
+    return GA_EDEVICE;
+  }
+  return GA_OK;
+}
+
+// parameters (alpha, beta, gamma) of the blocks j < k and of block k of the
+// order-2k scheme with rho_b = rho_s = rho
+void block_j_params(double rho, double& a, double& b, double& g);
+void block_k_params(double rho, double& a, double& b, double& g);
+
+// whole-grid learned guess of one stage from its four newest solutions h[0..3]
+int gnet_guess(ga_gnet* net, ga_patch* pt, const double* const* h, double* X, hipStream_t st);
 
 }  // namespace ga
 
@@ -82,4 +121,22 @@ struct ga_integrator {
   double* H = nullptr;        // [4][k][n_free] ring of past stage solutions
   int head = -1, nhist = 0;   // newest ring slot, number of valid slots
   bool have_prev = false;
+  ga_gnet* nets[4] = {nullptr, nullptr, nullptr, nullptr};  // learned guess per stage (not owned)
+};
+
+struct ga_gnet {
+  float* params = nullptr;    // FP32 master weights, tap-major layout
+  float* m = nullptr;         // Adam moments
+  float* v = nullptr;
+  long long adam_t = 0;
+  void* w2pk = nullptr;       // BF16 layer-2 weights packed for MFMA
+  bool packed = false;
+  float* tw = nullptr;        // training activations and gradients
+  size_t tw_bytes = 0;
+  int* org = nullptr;         // crop origins [nb][3]
+  int org_cap = 0;
+  double* scal = nullptr;     // [0..3]: sums of squares of the history differences D_0..D_3
+  double* part = nullptr;     // reduction partials
+  void* iw = nullptr;         // inference activations (BF16, channels-last)
+  size_t iw_bytes = 0;
 };

@@ -1,0 +1,48 @@
+// Learned initial guess: parameter layout and launchers (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ga {
+
+// FP32 parameters, tap-major: W1[27][4][32] b1[32] W2[27][32][32] b2[32] W3[27][32] b3[1];
+// tap t = 9 kz + 3 ky + kx, weight W[t][ci][co] multiplies in[z+kz-1][y+ky-1][x+kx-1][ci]
+constexpr int GNET_W1 = 0;
+constexpr int GNET_B1 = GNET_W1 + 27 * 4 * 32;
+constexpr int GNET_W2 = GNET_B1 + 32;
+constexpr int GNET_B2 = GNET_W2 + 27 * 32 * 32;
+constexpr int GNET_W3 = GNET_B2 + 32;
+constexpr int GNET_B3 = GNET_W3 + 27 * 32;
+constexpr int GNET_NPARAM = GNET_B3 + 1;   // 32033
+constexpr int GNET_PACK2 = 27 * 2 * 64 * 8;  // bf16 entries of the MFMA-packed W2
+
+// four history fields (newest first) and the solution they are paired with
+struct GnetFields {
+  const double* h[4];
+  const double* x;
+};
+
+// training (FP32, channel-major crops [b][c][S^3], valid convolutions; activations of
+// layers 1-2 at positions outside the grid are zero, as with per-layer zero padding)
+void gnet_forward_batch(const float* params, const float* in, int nb, int S, const int* grid3,
+                        const int* org_dev, float* a1, float* a2, float* out, hipStream_t st);
+void gnet_backward_batch(const float* params, const float* in, int nb, int S, const float* a1,
+                         const float* a2, const float* d3, float* d2, float* d1, float* grad,
+                         hipStream_t st);
+void gnet_mse_grad(const float* out, const float* tgt, long long n, float* d, double* part,
+                   int nparts, hipStream_t st);
+void gnet_adam(float* p, float* m, float* v, const float* g, int n, float lr, float b1, float b2,
+               float eps, float c1, float c2, hipStream_t st);
+// partial sums of the squared backward differences D_0..D_3 of the history,
+// part[c * nparts + block]
+void gnet_diff_norms(GnetFields f, long long n, double* part, int nparts, hipStream_t st);
+void gnet_make_batch(GnetFields f, const int* grid3, const int* org_dev, int S, int nb,
+                     const double* sq, float* in, float* tgt, hipStream_t st);
+
+// inference on the whole grid (BF16 weights and activations, FP32 accumulation):
+// X = E + s_3 * net(D / s), sq[c] = sum of D_c^2
+void gnet_pack_bf16(const float* params, void* w2pk, hipStream_t st);
+void gnet_infer_grid(const float* params, const void* w2pk, GnetFields f, const int* grid3,
+                     const double* sq, void* a1, void* a2, double* X, hipStream_t st);
+
+}  // namespace ga

@@ -1,0 +1,514 @@
+// Learned initial guess for the stage solves: a 3-layer 3x3x3 convolutional net
+// (4 -> 32 -> 32 -> 1 channels, ReLU after the first two layers, zero padding at
+// the grid boundary as the homogeneous Dirichlet condition gives) that corrects
+// the cubic extrapolation E of the last four solutions H1..H4 of one stage:
+//     D0 = H1, D1 = H1 - H2, D2 = H1 - 2H2 + H3, D3 = H1 - 3H2 + 3H3 - H4
+//        (backward differences; E = D0 + D1 + D2 + D3 = 4H1 - 6H2 + 4H3 - H4)
+//     c_i = D_i / s_i,  s_i = RMS(D_i)       (1 where D_i = 0)
+//     guess = E + s_3 * net(c_0, c_1, c_2, c_3).
+// Scaling every channel by its own RMS keeps inputs and target of order one,
+// although the differences are orders of magnitude below the fields.
+//
+// Training (FP32, on crops):  forward / backward-data / backward-weight / MSE / Adam.
+//   Crops are channel-major [b][c][S^3]; the convolutions are "valid" and the
+//   activations of layers 1 and 2 at positions outside the grid are forced to zero,
+//   which makes a crop reproduce the whole-grid net on its interior.
+// Inference (BF16 weights and activations, FP32 accumulation, whole grid):
+//   layer 1 forms the channels from the FP64 history on the vector ALU, layer 2
+//   (55,296 of the 63,936 flops per point) runs on MFMA 32x32x16 from an LDS
+//   brick, layer 3 forms the guess.  Activations are channels-last [point][32]
+//   in BF16 (64 bytes per point).
+#include <hip/hip_runtime.h>
+
+#include "gnet.h"
+
+namespace ga {
+
+namespace {
+
+constexpr int VB = 256;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+inline unsigned nbk(long long n) {
+  long long b = (n + VB - 1) / VB;
+  if (b > 65535 * 4) b = 65535 * 4;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+struct Dims {
+  int x, y, z;
+  __host__ __device__ long long vol() const { return (long long)x * y * z; }
+};
+
+__device__ __forceinline__ bool inside(int x, int y, int z, Dims g) {
+  return x >= 0 && y >= 0 && z >= 0 && x < g.x && y < g.y && z < g.z;
+}
+
+// sq[i] = sum of D_i^2 over the grid -> 1 / s_i
+__device__ __forceinline__ double inv_rms(const double* sq, int i, long long n) {
+  const double s = sqrt(sq[i] / (double)n);
+  return s > 0.0 ? 1.0 / s : 1.0;
+}
+
+__device__ __forceinline__ void differences(double h0, double h1, double h2, double h3, double d[4]) {
+  d[0] = h0;
+  d[1] = h0 - h1;
+  d[2] = h0 - 2.0 * h1 + h2;
+  d[3] = h0 - 3.0 * h1 + 3.0 * h2 - h3;
+}
+
+// ---------------------------------------------------------------- training
+
+// valid convolution of a batch of crops; output o reads input o + (0..2) per axis.
+// With org != nullptr, outputs whose grid position org + o + shift lies outside
+// the grid are zero.
+template <int CI, int CO>
+__global__ void __launch_bounds__(VB)
+conv_fwd_k(const float* __restrict__ in, Dims di, Dims dout, int nb, const float* __restrict__ W,
+           const float* __restrict__ bias, float* __restrict__ out, int relu, Dims grid,
+           const int* __restrict__ org, int shift) {
+  const long long vi = di.vol(), vo = dout.vol();
+  for (long long g = (long long)blockIdx.x * VB + threadIdx.x; g < nb * vo;
+       g += (long long)gridDim.x * VB) {
+    const long long bi = g / vo, o = g % vo;
+    const int ox = (int)(o % dout.x), oy = (int)((o / dout.x) % dout.y),
+              oz = (int)(o / ((long long)dout.x * dout.y));
+    float* ob = out + bi * CO * vo + o;
+    if (org && !inside(org[3 * bi] + ox + shift, org[3 * bi + 1] + oy + shift,
+                       org[3 * bi + 2] + oz + shift, grid)) {
+#pragma unroll
+      for (int c = 0; c < CO; ++c) ob[c * vo] = 0.0f;
+      continue;
+    }
+    float acc[CO];
+#pragma unroll
+    for (int c = 0; c < CO; ++c) acc[c] = bias[c];
+    const float* ib = in + bi * CI * vi;
+    for (int t = 0; t < 27; ++t) {
+      const long long p = (ox + t % 3) + (long long)di.x * ((oy + (t / 3) % 3) + (long long)di.y * (oz + t / 9));
+#pragma unroll 4
+      for (int ci = 0; ci < CI; ++ci) {
+        const float v = ib[ci * vi + p];
+        const float* w = W + (t * CI + ci) * CO;
+#pragma unroll
+        for (int c = 0; c < CO; ++c) acc[c] += w[c] * v;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CO; ++c) ob[c * vo] = relu ? fmaxf(acc[c], 0.0f) : acc[c];
+  }
+}
+
+// gradient w.r.t. the input of a valid convolution, times the ReLU mask of the
+// layer that produced that input (act > 0)
+template <int CI, int CO>
+__global__ void __launch_bounds__(VB)
+conv_bwd_data_k(const float* __restrict__ dout, Dims di, Dims dov, int nb,
+                const float* __restrict__ W, const float* __restrict__ act, float* __restrict__ din) {
+  const long long vi = di.vol(), vo = dov.vol();
+  for (long long g = (long long)blockIdx.x * VB + threadIdx.x; g < nb * vi;
+       g += (long long)gridDim.x * VB) {
+    const long long bi = g / vi, q = g % vi;
+    const int qx = (int)(q % di.x), qy = (int)((q / di.x) % di.y), qz = (int)(q / ((long long)di.x * di.y));
+    float acc[CI];
+#pragma unroll
+    for (int c = 0; c < CI; ++c) acc[c] = 0.0f;
+    const float* db = dout + bi * CO * vo;
+    for (int t = 0; t < 27; ++t) {
+      const int ox = qx - t % 3, oy = qy - (t / 3) % 3, oz = qz - t / 9;
+      if (ox < 0 || oy < 0 || oz < 0 || ox >= dov.x || oy >= dov.y || oz >= dov.z) continue;
+      const long long o = ox + (long long)dov.x * (oy + (long long)dov.y * oz);
+      float dv[CO];
+#pragma unroll
+      for (int co = 0; co < CO; ++co) dv[co] = db[co * vo + o];
+#pragma unroll 4
+      for (int c = 0; c < CI; ++c) {
+        const float* w = W + (t * CI + c) * CO;
+        float s = 0.0f;
+#pragma unroll
+        for (int co = 0; co < CO; ++co) s += w[co] * dv[co];
+        acc[c] += s;
+      }
+    }
+    const float* ab = act + bi * CI * vi + q;
+    float* ib = din + bi * CI * vi + q;
+#pragma unroll
+    for (int c = 0; c < CI; ++c) ib[c * vi] = ab[c * vi] > 0.0f ? acc[c] : 0.0f;
+  }
+}
+
+__device__ __forceinline__ float wsum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// gradient w.r.t. the weights and bias of a valid convolution: one workgroup per
+// (co, ci) pair, summed over every output point of the batch
+template <int CI, int CO>
+__global__ void __launch_bounds__(VB)
+conv_bwd_w_k(const float* __restrict__ in, Dims di, const float* __restrict__ dout, Dims dov,
+             int nb, float* __restrict__ dW, float* __restrict__ dbias) {
+  const int co = blockIdx.x / CI, ci = blockIdx.x % CI;
+  const long long vi = di.vol(), vo = dov.vol();
+  float acc[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = 0.0f;
+  float accb = 0.0f;
+  for (long long g = threadIdx.x; g < nb * vo; g += VB) {
+    const long long bi = g / vo, o = g % vo;
+    const int ox = (int)(o % dov.x), oy = (int)((o / dov.x) % dov.y), oz = (int)(o / ((long long)dov.x * dov.y));
+    const float d = dout[bi * CO * vo + co * vo + o];
+    accb += d;
+    const float* ib = in + (bi * CI + ci) * vi + ox + (long long)di.x * (oy + (long long)di.y * oz);
+#pragma unroll
+    for (int t = 0; t < 27; ++t)
+      acc[t] += d * ib[(t % 3) + (long long)di.x * ((t / 3) % 3 + (long long)di.y * (t / 9))];
+  }
+  __shared__ float sh[28][VB / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 27; ++t) {
+    const float v = wsum(acc[t]);
+    if (lane == 0) sh[t][wv] = v;
+  }
+  {
+    const float v = wsum(accb);
+    if (lane == 0) sh[27][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 28) {
+    float v = 0.0f;
+    for (int w = 0; w < VB / 64; ++w) v += sh[threadIdx.x][w];
+    if (threadIdx.x < 27) dW[(threadIdx.x * CI + ci) * CO + co] = v;
+    else if (ci == 0) dbias[co] = v;
+  }
+}
+
+// d = 2 (out - tgt) / n; per-block partial sums of (out - tgt)^2
+__global__ void __launch_bounds__(VB)
+mse_grad_k(const float* __restrict__ out, const float* __restrict__ tgt, long long n,
+           float* __restrict__ d, double* __restrict__ part) {
+  double s = 0.0;
+  const float sc = 2.0f / (float)n;
+  for (long long i = (long long)blockIdx.x * VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    const float e = out[i] - tgt[i];
+    d[i] = sc * e;
+    s += (double)e * e;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ double sh[VB / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < VB / 64; ++w) t += sh[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void adam_k(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int i = blockIdx.x * VB + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// per-block partial sums of D_i^2, part[i * gridDim.x + block]
+__global__ void __launch_bounds__(VB)
+diff_norms_k(GnetFields f, long long n, double* __restrict__ part) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    double d[4];
+    differences(f.h[0][i], f.h[1][i], f.h[2][i], f.h[3][i], d);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] += d[c] * d[c];
+  }
+  __shared__ double sh[4][VB / 64];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double v = acc[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[c][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int w = 0; w < VB / 64; ++w) t += sh[threadIdx.x][w];
+    part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// crops: in[b][c][S^3] = D_c / s_c around origin org_b (zero outside the grid);
+// tgt[b][(S-6)^3] = (X - E) / s_3 on the crop interior
+__global__ void __launch_bounds__(VB)
+make_batch_k(GnetFields f, Dims grid, const int* __restrict__ org, int S, int nb,
+             const double* __restrict__ sq, float* __restrict__ in, float* __restrict__ tgt) {
+  const long long vs = (long long)S * S * S;
+  const int T = S - 6;
+  const long long vt = (long long)T * T * T;
+  double is[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) is[c] = inv_rms(sq, c, grid.vol());
+  for (long long g = (long long)blockIdx.x * VB + threadIdx.x; g < nb * vs;
+       g += (long long)gridDim.x * VB) {
+    const long long bi = g / vs, l = g % vs;
+    const int lx = (int)(l % S), ly = (int)((l / S) % S), lz = (int)(l / ((long long)S * S));
+    const int x = org[3 * bi] + lx, y = org[3 * bi + 1] + ly, z = org[3 * bi + 2] + lz;
+    const bool ok = inside(x, y, z, grid);
+    const long long p = ok ? x + (long long)grid.x * (y + (long long)grid.y * z) : 0;
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    if (ok) differences(f.h[0][p], f.h[1][p], f.h[2][p], f.h[3][p], d);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) in[(bi * 4 + c) * vs + l] = (float)(d[c] * is[c]);
+    if (lx >= 3 && ly >= 3 && lz >= 3 && lx < S - 3 && ly < S - 3 && lz < S - 3) {
+      const double e = d[0] + d[1] + d[2] + d[3];
+      const double xv = ok ? f.x[p] : 0.0;
+      tgt[bi * vt + (lx - 3) + (long long)T * ((ly - 3) + (long long)T * (lz - 3))] =
+          (float)((xv - e) * is[3]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- inference
+
+// W2 packed for the MFMA A operand: entry ((t*2 + kc)*64 + lane)*8 + i holds
+// W2[t][ci = 16 kc + 8 (lane/32) + i][co = lane % 32]
+__global__ void pack_w2_k(const float* __restrict__ W2, __bf16* __restrict__ pk) {
+  const int e = blockIdx.x * VB + threadIdx.x;
+  if (e >= GNET_PACK2) return;
+  const int i = e % 8, lane = (e / 8) % 64, kc = (e / 512) % 2, t = e / 1024;
+  const int ci = 16 * kc + 8 * (lane / 32) + i, co = lane % 32;
+  pk[e] = (__bf16)W2[(t * 32 + ci) * 32 + co];
+}
+
+// layer 1 on the whole grid, input channels D_c / s_c formed from the FP64
+// history, output BF16 channels-last
+__global__ void __launch_bounds__(VB)
+conv1_hist_k(GnetFields f, Dims grid, const double* __restrict__ sq,
+             const float* __restrict__ W, const float* __restrict__ bias, bf16x8* __restrict__ out) {
+  const long long v = grid.vol();
+  double is[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) is[c] = inv_rms(sq, c, v);
+  for (long long o = (long long)blockIdx.x * VB + threadIdx.x; o < v; o += (long long)gridDim.x * VB) {
+    const int ox = (int)(o % grid.x), oy = (int)((o / grid.x) % grid.y),
+              oz = (int)(o / ((long long)grid.x * grid.y));
+    float acc[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc[c] = bias[c];
+    for (int t = 0; t < 27; ++t) {
+      const int x = ox + t % 3 - 1, y = oy + (t / 3) % 3 - 1, z = oz + t / 9 - 1;
+      if (!inside(x, y, z, grid)) continue;
+      const long long p = x + (long long)grid.x * (y + (long long)grid.y * z);
+      double d[4];
+      differences(f.h[0][p], f.h[1][p], f.h[2][p], f.h[3][p], d);
+#pragma unroll
+      for (int ci = 0; ci < 4; ++ci) {
+        const float val = (float)(d[ci] * is[ci]);
+        const float* w = W + (t * 4 + ci) * 32;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc[c] += w[c] * val;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      bf16x8 r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) r[i] = (__bf16)fmaxf(acc[8 * q + i], 0.0f);
+      out[o * 4 + q] = r;
+    }
+  }
+}
+
+// layer 2 on MFMA.  Workgroup tile: 16 (x) x 8 (y) x 4 (z) output points; its input
+// brick with a one-point halo (18 x 10 x 6 points x 32 channels, BF16) sits in LDS,
+// 16-byte channel chunk c of brick point n stored at slot c ^ ((n >> 1) & 3) so that
+// 8 consecutive points read by one LDS phase hit distinct banks.  Wave w owns z-plane
+// w of the tile; each MFMA covers 32 output channels x 32 points (16 x by 2 y) and one
+// 16-channel slice of one tap: 54 MFMAs per group of 32 points.
+constexpr int TX = 16, TY = 8, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+constexpr int HP = HX * HY * HZ;
+
+__device__ __forceinline__ unsigned xcd_tile(unsigned bid, unsigned nwg) {
+  // consecutive tiles (which share halo data) on the same XCD
+  const unsigned nx = 8, per = nwg / nx, rem = nwg % nx;
+  const unsigned xcd = bid % nx, loc = bid / nx;
+  const unsigned base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+  return base + loc;
+}
+
+__global__ void __launch_bounds__(256)
+conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wpk,
+             const float* __restrict__ bias, __bf16* __restrict__ a2, int ntx, int nty) {
+  __shared__ uint4 brick[HP * 4];
+  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < HP * 4; e += 256) {
+    const int n = e >> 2, c = e & 3;
+    const int hx = n % HX, hy = (n / HX) % HY, hz = n / (HX * HY);
+    const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (inside(x, y, z, g)) v = a1[(x + (long long)g.x * (y + (long long)g.y * z)) * 4 + c];
+    brick[n * 4 + (c ^ ((n >> 1) & 3))] = v;
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int n32 = lane & 31, half = lane >> 5, lx = n32 & 15, ly = n32 >> 4;
+  f32x16 acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[r][v] = 0.0f;
+  for (int t = 0; t < 27; ++t) {
+    const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      const bf16x8 A = wpk[(t * 2 + kc) * 64 + lane];
+      const int c = kc * 2 + half;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = ((w + dz) * HY + (2 * r + ly + dy)) * HX + (lx + dx);
+        const uint4 raw = brick[n * 4 + (c ^ ((n >> 1) & 3))];
+        bf16x8 B;
+        __builtin_memcpy(&B, &raw, 16);
+        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[r], 0, 0, 0);
+      }
+    }
+  }
+  // accumulator v of lane l holds channel 8 (v/4) + 4 (l/32) + v%4 of point l%32
+  const int oz = z0 + w;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ox = x0 + lx, oy = y0 + 2 * r + ly;
+    if (!inside(ox, oy, oz, g)) continue;
+    __bf16* dst = a2 + (ox + (long long)g.x * (oy + (long long)g.y * oz)) * 32;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c0 = 8 * q + 4 * half;
+      bf16x4 o4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o4[i] = (__bf16)fmaxf(acc[r][4 * q + i] + bias[c0 + i], 0.0f);
+      *reinterpret_cast<bf16x4*>(dst + c0) = o4;
+    }
+  }
+}
+
+// layer 3 and the guess: X = E + s_3 * (b3 + sum W3 * a2)
+__global__ void __launch_bounds__(VB)
+conv3_guess_k(const bf16x8* __restrict__ a2, GnetFields f, Dims grid,
+              const double* __restrict__ sq, const float* __restrict__ W,
+              const float* __restrict__ bias, double* __restrict__ X) {
+  const long long v = grid.vol();
+  const double s3 = 1.0 / inv_rms(sq, 3, v);
+  for (long long o = (long long)blockIdx.x * VB + threadIdx.x; o < v; o += (long long)gridDim.x * VB) {
+    const int ox = (int)(o % grid.x), oy = (int)((o / grid.x) % grid.y),
+              oz = (int)(o / ((long long)grid.x * grid.y));
+    float acc = bias[0];
+    for (int t = 0; t < 27; ++t) {
+      const int x = ox + t % 3 - 1, y = oy + (t / 3) % 3 - 1, z = oz + t / 9 - 1;
+      if (!inside(x, y, z, grid)) continue;
+      const long long p = x + (long long)grid.x * (y + (long long)grid.y * z);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bf16x8 a = a2[p * 4 + q];
+        const float* wq = W + t * 32 + 8 * q;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc += wq[i] * (float)a[i];
+      }
+    }
+    const double e = 4.0 * f.h[0][o] - 6.0 * f.h[1][o] + 4.0 * f.h[2][o] - f.h[3][o];
+    X[o] = e + s3 * (double)acc;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+static Dims cube(int s) { return Dims{s, s, s}; }
+
+void gnet_forward_batch(const float* params, const float* in, int nb, int S, const int* grid3,
+                        const int* org_dev, float* a1, float* a2, float* out, hipStream_t st) {
+  const int S1 = S - 2, S2 = S - 4, S3 = S - 6;
+  const Dims g{grid3[0], grid3[1], grid3[2]};
+  hipLaunchKernelGGL((conv_fwd_k<4, 32>), dim3(nbk((long long)nb * S1 * S1 * S1)), dim3(VB), 0, st,
+                     in, cube(S), cube(S1), nb, params + GNET_W1, params + GNET_B1, a1, 1, g,
+                     org_dev, 1);
+  hipLaunchKernelGGL((conv_fwd_k<32, 32>), dim3(nbk((long long)nb * S2 * S2 * S2)), dim3(VB), 0, st,
+                     a1, cube(S1), cube(S2), nb, params + GNET_W2, params + GNET_B2, a2, 1, g,
+                     org_dev, 2);
+  hipLaunchKernelGGL((conv_fwd_k<32, 1>), dim3(nbk((long long)nb * S3 * S3 * S3)), dim3(VB), 0, st,
+                     a2, cube(S2), cube(S3), nb, params + GNET_W3, params + GNET_B3, out, 0, g,
+                     (const int*)nullptr, 0);
+}
+
+void gnet_backward_batch(const float* params, const float* in, int nb, int S, const float* a1,
+                         const float* a2, const float* d3, float* d2, float* d1, float* grad,
+                         hipStream_t st) {
+  const int S1 = S - 2, S2 = S - 4, S3 = S - 6;
+  hipLaunchKernelGGL((conv_bwd_w_k<32, 1>), dim3(32), dim3(VB), 0, st, a2, cube(S2), d3, cube(S3),
+                     nb, grad + GNET_W3, grad + GNET_B3);
+  hipLaunchKernelGGL((conv_bwd_data_k<32, 1>), dim3(nbk((long long)nb * S2 * S2 * S2)), dim3(VB), 0,
+                     st, d3, cube(S2), cube(S3), nb, params + GNET_W3, a2, d2);
+  hipLaunchKernelGGL((conv_bwd_w_k<32, 32>), dim3(32 * 32), dim3(VB), 0, st, a1, cube(S1), d2,
+                     cube(S2), nb, grad + GNET_W2, grad + GNET_B2);
+  hipLaunchKernelGGL((conv_bwd_data_k<32, 32>), dim3(nbk((long long)nb * S1 * S1 * S1)), dim3(VB), 0,
+                     st, d2, cube(S1), cube(S2), nb, params + GNET_W2, a1, d1);
+  hipLaunchKernelGGL((conv_bwd_w_k<4, 32>), dim3(32 * 4), dim3(VB), 0, st, in, cube(S), d1,
+                     cube(S1), nb, grad + GNET_W1, grad + GNET_B1);
+}
+
+void gnet_mse_grad(const float* out, const float* tgt, long long n, float* d, double* part,
+                   int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(mse_grad_k, dim3(nparts), dim3(VB), 0, st, out, tgt, n, d, part);
+}
+
+void gnet_adam(float* p, float* m, float* v, const float* g, int n, float lr, float b1, float b2,
+               float eps, float c1, float c2, hipStream_t st) {
+  hipLaunchKernelGGL(adam_k, dim3((n + VB - 1) / VB), dim3(VB), 0, st, p, m, v, g, n, lr, b1, b2,
+                     eps, c1, c2);
+}
+
+void gnet_diff_norms(GnetFields f, long long n, double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(diff_norms_k, dim3(nparts), dim3(VB), 0, st, f, n, part);
+}
+
+void gnet_make_batch(GnetFields f, const int* grid3, const int* org_dev, int S, int nb,
+                     const double* sq, float* in, float* tgt, hipStream_t st) {
+  hipLaunchKernelGGL(make_batch_k, dim3(nbk((long long)nb * S * S * S)), dim3(VB), 0, st, f,
+                     Dims{grid3[0], grid3[1], grid3[2]}, org_dev, S, nb, sq, in, tgt);
+}
+
+void gnet_pack_bf16(const float* params, void* w2pk, hipStream_t st) {
+  hipLaunchKernelGGL(pack_w2_k, dim3((GNET_PACK2 + VB - 1) / VB), dim3(VB), 0, st,
+                     params + GNET_W2, (__bf16*)w2pk);
+}
+
+void gnet_infer_grid(const float* params, const void* w2pk, GnetFields f, const int* grid3,
+                     const double* sq, void* a1, void* a2, double* X, hipStream_t st) {
+  const Dims g{grid3[0], grid3[1], grid3[2]};
+  const long long v = g.vol();
+  hipLaunchKernelGGL(conv1_hist_k, dim3(nbk(v)), dim3(VB), 0, st, f, g, sq,
+                     params + GNET_W1, params + GNET_B1, (bf16x8*)a1);
+  const int ntx = (g.x + TX - 1) / TX, nty = (g.y + TY - 1) / TY, ntz = (g.z + TZ - 1) / TZ;
+  hipLaunchKernelGGL(conv2_mfma_k, dim3((unsigned)(ntx * nty * ntz)), dim3(256), 0, st,
+                     (const uint4*)a1, g, (const bf16x8*)w2pk, params + GNET_B2, (__bf16*)a2, ntx, nty);
+  hipLaunchKernelGGL(conv3_guess_k, dim3(nbk(v)), dim3(VB), 0, st, (const bf16x8*)a2, f, g,
+                     sq, params + GNET_W3, params + GNET_B3, X);
+}
+
+}  // namespace ga

@@ -15,8 +15,33 @@ struct StatePtrs { double* L[12]; };
 struct HistPtrs { const double* H[16]; };  // [h * 4 + j]: history slot h (newest first), stage j
 struct Coefs { double alpha[4], beta[4], gamma[4]; };
 
+// element/tile geometry of one 3-D patch as the operator kernels see it
+struct Geo3 {
+  int n[3], m[3], mf[3], nt[2];
+};
+
+// one patch of a multi-patch operator launch (all patches of one degree)
+struct OpGroupEntry {
+  const void* fac;            // W (mass, FP64 or FP32) or G (stiffness) of the patch
+  const double* tB[3];
+  const double* tD[3];
+  Geo3 g;
+  int ze;                     // element layers per tile along z
+  long long off;              // offset of the patch's segment in the batched vectors
+  int tile0, ntiles;          // the patch's entries in the tile queue
+};
+
 int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
                 hipStream_t st);
+long long op3d_tiles(int mode, const ga_patch* pt, int ze);
+int op3d_default_ze(int mode, const ga_patch* pt);
+OpGroupEntry op3d_group_entry(int mode, const ga_patch* pt, int ze, long long off, int tile0,
+                              bool f32);
+// y += alpha * Op x over every patch in ents (one degree p), nr right-hand sides
+// `stride` entries apart, the tile queue split over at most nwg workgroups
+template <typename S>
+int launch_op3d_group(int p, int mode, int nr, const OpGroupEntry* ents, int nent, const S* x,
+                      S* y, long long stride, S alpha, int total, int nwg, hipStream_t st);
 int launch_mass3d_f32(int nr, const ga_patch* pt, const float* x, float* y, float alpha,
                       hipStream_t st);
 int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
@@ -41,6 +66,22 @@ template <typename S>
 void launch_pinv_contig(const S* in, S* out, const S* A, int L, long long nrows,
                         long long rows_per_rhs, long long n_free, const S* si, const S* so,
                         hipStream_t st);
+// one patch of a multi-patch preconditioner pass.  Pass 0 (x axis, contiguous rows):
+// p = {rows, rows per right-hand side}; passes 1-2 (strided): p = {row stride,
+// columns per plane, plane stride, columns}.  Workgroup columns blk0 ..
+struct PinvEntry {
+  const void* A;              // the axis' inverse 1-D mass matrix (L x L)
+  const void* si;             // scaling applied to the input, or null
+  const void* so;             // scaling applied to the output, or null
+  int L;
+  long long p[4];
+  long long off;              // segment offset in the batched vectors
+  int blk0;
+};
+int pinv_ra_class(int L);
+template <typename S>
+void launch_pinv_group(int pass, int ra_class, const PinvEntry* ents, int nent, int nblk, int nr,
+                       const S* in, S* out, long long stride, hipStream_t st);
 void launch_scaling(double* s, const double* diagM, const double* dh0, const double* dh1,
                     const double* dh2, int mf0, int mf1, int mf2, hipStream_t st);
 void launch_dot_partial(int nr, const double* a, const double* b, size_t n, double* part,
@@ -74,5 +115,15 @@ void launch_cg_xr_f32(int nr, float* x, float* r, const float* p, const float* q
 void launch_cg_p_f32(int nr, float* p, const float* z, const double* scal, size_t n,
                      hipStream_t st);
 void launch_sum_partials(int nr, const double* part, double* out, hipStream_t st);
+// segment-aware CG kernels: system s = entries seg[2s] .. seg[2s] + seg[2s+1] of each vector
+void launch_dot_partial_seg(int ns, const double* a, const double* b, const long long* seg,
+                            double* part, hipStream_t st);
+void launch_cg_fallback_seg(int ns, double* x, double* r, double* z, const double* b,
+                            const double* zb, const double* scal, const long long* seg,
+                            size_t maxlen, hipStream_t st);
+void launch_cg_xr_seg(int ns, double* x, double* r, const double* p, const double* q,
+                      const double* scal, const long long* seg, size_t maxlen, hipStream_t st);
+void launch_cg_p_seg(int ns, double* p, const double* z, const double* scal, const long long* seg,
+                     size_t maxlen, hipStream_t st);
 
 }  // namespace ga

@@ -45,9 +45,6 @@ struct Tile3 {
   static constexpr int TAB = TE * Q * (P + 1);
 };
 
-struct Geo3 {
-  int n[3], m[3], mf[3], nt[2];
-};
 
 // index of a full-grid coefficient (i0,i1,i2) in the free vector, or -1
 __device__ __forceinline__ long long free_index3(const Geo3& g, int i0, int i1, int i2) {
@@ -74,14 +71,16 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned nwg) {
 #endif
 
 // MODE: 0 mass, 1 stiffness, 2 diag(M) (tables hold squared values, x unused)
+// One workgroup's share: logical tile `lid` = (xy column, z range) of one patch.
+// x and y hold NR right-hand sides `n_free` entries apart.
 template <int P, int TE, int MODE, int NR, typename S>
-__global__ void __launch_bounds__((Tile3<P, TE>::NT), (MODE == 1 ? GA_OP3_WAVES_K : GA_OP3_WAVES_M))
-op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
-            const S* __restrict__ fac,
-            const double* __restrict__ tB0, const double* __restrict__ tB1,
-            const double* __restrict__ tB2, const double* __restrict__ tD0,
-            const double* __restrict__ tD1, const double* __restrict__ tD2,
-            Geo3 g, int ze, long long n_free, S alpha) {
+__device__ __forceinline__ void
+op3d_body(const S* __restrict__ x, S* __restrict__ y,
+          const S* __restrict__ fac,
+          const double* __restrict__ tB0, const double* __restrict__ tB1,
+          const double* __restrict__ tB2, const double* __restrict__ tD0,
+          const double* __restrict__ tD1, const double* __restrict__ tD2,
+          Geo3 g, int ze, long long n_free, S alpha, unsigned lid) {
   using T = Tile3<P, TE>;
   constexpr int Q = T::Q, QT = T::QT, NB = T::NB, NT = T::NT;
   constexpr int NPL = NB * NB;                  // coefficients per plane of the box
@@ -107,7 +106,6 @@ op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
 
   const int tid = threadIdx.x;
   const int qx = tid % QT, qy = tid / QT;
-  const unsigned lid = xcd_remap(blockIdx.x, gridDim.x);
   const int ntxy = g.nt[0] * g.nt[1];
   const int txy = (int)(lid % ntxy);
   const int zc = (int)(lid / ntxy);
@@ -469,6 +467,41 @@ op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
   }
 }
 
+template <int P, int TE, int MODE, int NR, typename S>
+__global__ void __launch_bounds__((Tile3<P, TE>::NT), (MODE == 1 ? GA_OP3_WAVES_K : GA_OP3_WAVES_M))
+op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
+            const S* __restrict__ fac,
+            const double* __restrict__ tB0, const double* __restrict__ tB1,
+            const double* __restrict__ tB2, const double* __restrict__ tD0,
+            const double* __restrict__ tD1, const double* __restrict__ tD2,
+            Geo3 g, int ze, long long n_free, S alpha) {
+  op3d_body<P, TE, MODE, NR, S>(x, y, fac, tB0, tB1, tB2, tD0, tD1, tD2, g, ze, n_free, alpha,
+                                xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Several patches of one degree in one launch: a static queue of tiles, the
+// tiles of patch e numbered tile0..tile0+ntiles-1; workgroup w walks `per_wg`
+// consecutive queue entries (w remapped so that each XCD owns a contiguous
+// stretch of the queue).  Patch e's vectors start at offset `off` of x and y,
+// right-hand sides `stride` entries apart.
+template <int P, int TE, int MODE, int NR, typename S>
+__global__ void __launch_bounds__((Tile3<P, TE>::NT), (MODE == 1 ? GA_OP3_WAVES_K : GA_OP3_WAVES_M))
+op3d_group_kernel(const OpGroupEntry* __restrict__ ents, int nent, const S* __restrict__ x,
+                  S* __restrict__ y, long long stride, S alpha, int total, int per_wg) {
+  const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
+  for (int i = 0; i < per_wg; ++i) {
+    const int t = (int)w * per_wg + i;
+    if (t >= total) return;
+    int e = 0;
+    while (e + 1 < nent && t >= ents[e + 1].tile0) ++e;
+    const OpGroupEntry& d = ents[e];
+    __syncthreads();  // the previous tile has finished with the LDS
+    op3d_body<P, TE, MODE, NR, S>(x + d.off, y + d.off, (const S*)d.fac, d.tB[0], d.tB[1], d.tB[2],
+                                  d.tD[0], d.tD[1], d.tD[2], d.g, d.ze, stride, alpha,
+                                  (unsigned)(t - d.tile0));
+  }
+}
+
 // Geometry factors at the Gauss points of one element layer of one
 // stiffness-layout xy tile; W is written in the mass-kernel tiling.
 template <int P>
@@ -612,6 +645,74 @@ int launch_mass3d_f32(int nr, const ga_patch* pt, const float* x, float* y, floa
   }
   return -1;
 }
+
+// tiles of one patch in the layout of `mode` with ze element layers per tile
+long long op3d_tiles(int mode, const ga_patch* pt, int ze) {
+  const int* nt = mode == 1 ? pt->ntk : pt->ntm;
+  return (long long)nt[0] * nt[1] * ((pt->n[2] + ze - 1) / ze);
+}
+
+int op3d_default_ze(int mode, const ga_patch* pt) {
+  const int* nt = mode == 1 ? pt->ntk : pt->ntm;
+  return pt->ze > 0 ? pt->ze : pick_ze((long long)nt[0] * nt[1], pt->n[2], mode == 1 ? 8 : 16);
+}
+
+OpGroupEntry op3d_group_entry(int mode, const ga_patch* pt, int ze, long long off, int tile0,
+                              bool f32) {
+  OpGroupEntry d;
+  for (int a = 0; a < 3; ++a) {
+    d.g.n[a] = pt->n[a]; d.g.m[a] = pt->m[a]; d.g.mf[a] = pt->mf[a];
+    d.tB[a] = pt->tabB[a];
+    d.tD[a] = pt->tabD[a];
+  }
+  const int* nt = mode == 1 ? pt->ntk : pt->ntm;
+  d.g.nt[0] = nt[0];
+  d.g.nt[1] = nt[1];
+  d.fac = mode == 1 ? (const void*)pt->G : (f32 ? (const void*)pt->W32 : (const void*)pt->W);
+  d.ze = ze;
+  d.off = off;
+  d.tile0 = tile0;
+  d.ntiles = (int)op3d_tiles(mode, pt, ze);
+  return d;
+}
+
+template <int P, typename S>
+static int group_p(int mode, int nr, const OpGroupEntry* ents, int nent, const S* x, S* y,
+                   long long stride, S alpha, int total, int nwg, hipStream_t st) {
+  constexpr int TK = te3_stiff(P), TM = te3_mass(P);
+  const int per = (total + nwg - 1) / nwg;
+  const dim3 grid((unsigned)((total + per - 1) / per));
+#define GA_OPG(TE, MODE, NRV)                                                                    \
+  hipLaunchKernelGGL((op3d_group_kernel<P, TE, MODE, NRV, S>), grid, dim3(Tile3<P, TE>::NT), 0, st, \
+                     ents, nent, x, y, stride, alpha, total, per)
+  if (mode == 0) {
+    if (nr == 1) GA_OPG(TM, 0, 1); else if (nr == 2) GA_OPG(TM, 0, 2); else GA_OPG(TM, 0, 3);
+  } else {
+    if constexpr (sizeof(S) == 8) {
+      if (nr == 1) GA_OPG(TK, 1, 1); else if (nr == 2) GA_OPG(TK, 1, 2); else GA_OPG(TK, 1, 3);
+    } else {
+      return -1;
+    }
+  }
+#undef GA_OPG
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename S>
+int launch_op3d_group(int p, int mode, int nr, const OpGroupEntry* ents, int nent, const S* x,
+                      S* y, long long stride, S alpha, int total, int nwg, hipStream_t st) {
+  if (nr < 1 || nr > 3 || total < 1 || nwg < 1 || (mode != 0 && mode != 1)) return -1;
+  switch (p) {
+    case 2: return group_p<2, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st);
+    case 3: return group_p<3, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st);
+    case 4: return group_p<4, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st);
+  }
+  return -1;
+}
+template int launch_op3d_group<double>(int, int, int, const OpGroupEntry*, int, const double*,
+                                       double*, long long, double, int, int, hipStream_t);
+template int launch_op3d_group<float>(int, int, int, const OpGroupEntry*, int, const float*,
+                                      float*, long long, float, int, int, hipStream_t);
 
 int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
                  hipStream_t st) {

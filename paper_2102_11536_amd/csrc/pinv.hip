@@ -26,19 +26,17 @@ __device__ __forceinline__ long long col_offset(long long c, long long ncol, lon
   return (c / ncol) * plane_stride + (c % ncol);
 }
 
+// columns c0 .. c0+BN-1 of one right-hand side (inr, outr point at its first entry)
 template <int RA, typename S>
-__global__ void __launch_bounds__(256)
-pinv_strided_k(const S* __restrict__ in, S* __restrict__ out,
-               const S* __restrict__ A, int L, long long row_stride, long long ncol,
-               long long plane_stride, long long ncols_total, long long n_free,
-               const S* __restrict__ si, const S* __restrict__ so) {
+__device__ __forceinline__ void
+strided_body(const S* __restrict__ inr, S* __restrict__ outr,
+             const S* __restrict__ A, int L, long long row_stride, long long ncol,
+             long long plane_stride, long long ncols_total,
+             const S* __restrict__ si, const S* __restrict__ so, long long c0) {
   constexpr int RP = 16 * RA;
   __shared__ S As[BK][RP + 1];
   __shared__ S Bs[BK][BN + 1];
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const long long c0 = (long long)blockIdx.x * BN;
-  const S* inr = in + (size_t)blockIdx.y * n_free;
-  S* outr = out + (size_t)blockIdx.y * n_free;
   // this thread's load slots in the B tile: (k = e / BN, column e % BN), e = tid + 256 l
   long long boff[BK * BN / 256];
   bool bok[BK * BN / 256];
@@ -102,15 +100,26 @@ pinv_strided_k(const S* __restrict__ in, S* __restrict__ out,
 
 template <int RA, typename S>
 __global__ void __launch_bounds__(256)
-pinv_contig_k(const S* __restrict__ in, S* __restrict__ out,
-              const S* __restrict__ A, int L, long long nrows, long long rows_per_rhs,
-              long long n_free, const S* __restrict__ si, const S* __restrict__ so) {
+pinv_strided_k(const S* __restrict__ in, S* __restrict__ out,
+               const S* __restrict__ A, int L, long long row_stride, long long ncol,
+               long long plane_stride, long long ncols_total, long long n_free,
+               const S* __restrict__ si, const S* __restrict__ so) {
+  strided_body<RA, S>(in + (size_t)blockIdx.y * n_free, out + (size_t)blockIdx.y * n_free, A, L,
+                      row_stride, ncol, plane_stride, ncols_total, si, so,
+                      (long long)blockIdx.x * BN);
+}
+
+// rows r0 .. r0+63 of all right-hand sides (row r of rhs r / rows_per_rhs)
+template <int RA, typename S>
+__device__ __forceinline__ void
+contig_body(const S* __restrict__ in, S* __restrict__ out,
+            const S* __restrict__ A, int L, long long nrows, long long rows_per_rhs,
+            long long n_free, const S* __restrict__ si, const S* __restrict__ so, long long r0) {
   constexpr int RP = 16 * RA;
   constexpr int BM = 64;
   __shared__ S Xs[BK][BM + 1];
   __shared__ S As[BK][RP + 1];
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const long long r0 = (long long)blockIdx.x * BM;
   S acc[4][RA];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -163,6 +172,41 @@ pinv_contig_k(const S* __restrict__ in, S* __restrict__ out,
 }
 
 template <int RA, typename S>
+__global__ void __launch_bounds__(256)
+pinv_contig_k(const S* __restrict__ in, S* __restrict__ out,
+              const S* __restrict__ A, int L, long long nrows, long long rows_per_rhs,
+              long long n_free, const S* __restrict__ si, const S* __restrict__ so) {
+  contig_body<RA, S>(in, out, A, L, nrows, rows_per_rhs, n_free, si, so, (long long)blockIdx.x * 64);
+}
+
+// several patches in one launch: workgroup column blockIdx.x belongs to the entry e
+// with blk0 <= blockIdx.x < next blk0; blockIdx.y is the right-hand side
+__device__ __forceinline__ int pinv_entry(const PinvEntry* ents, int nent) {
+  int e = 0;
+  while (e + 1 < nent && (int)blockIdx.x >= ents[e + 1].blk0) ++e;
+  return e;
+}
+
+template <int RA, typename S>
+__global__ void __launch_bounds__(256)
+pinv_strided_group_k(const PinvEntry* __restrict__ ents, int nent, const S* __restrict__ in,
+                     S* __restrict__ out, long long stride) {
+  const PinvEntry& d = ents[pinv_entry(ents, nent)];
+  const size_t o = (size_t)d.off + (size_t)blockIdx.y * stride;
+  strided_body<RA, S>(in + o, out + o, (const S*)d.A, d.L, d.p[0], d.p[1], d.p[2], d.p[3],
+                      (const S*)d.si, (const S*)d.so, (long long)(blockIdx.x - d.blk0) * BN);
+}
+
+template <int RA, typename S>
+__global__ void __launch_bounds__(256)
+pinv_contig_group_k(const PinvEntry* __restrict__ ents, int nent, const S* __restrict__ in,
+                    S* __restrict__ out, long long stride) {
+  const PinvEntry& d = ents[pinv_entry(ents, nent)];
+  contig_body<RA, S>(in + d.off, out + d.off, (const S*)d.A, d.L, d.p[0], d.p[1], stride,
+                     (const S*)d.si, (const S*)d.so, (long long)(blockIdx.x - d.blk0) * 64);
+}
+
+template <int RA, typename S>
 void strided(const S* in, S* out, const S* A, int L, long long row_stride,
              long long ncol, long long plane_stride, int planes_per_rhs, long long n_free, int nr,
              const S* si, const S* so, hipStream_t st) {
@@ -183,6 +227,32 @@ void contig(const S* in, S* out, const S* A, int L, long long nrows,
 }  // namespace
 
 bool pinv_axis_supported(int L) { return L >= 1 && L <= 256; }
+
+int pinv_ra_class(int L) { return L <= 64 ? 0 : (L <= 144 ? 1 : 2); }
+
+template <typename S>
+void launch_pinv_group(int pass, int ra_class, const PinvEntry* ents, int nent, int nblk, int nr,
+                       const S* in, S* out, long long stride, hipStream_t st) {
+  // pass 0 covers every right-hand side through its row index (p[0] = all rows)
+  const dim3 grid((unsigned)nblk, pass == 0 ? 1u : (unsigned)nr);
+#define GA_PG(RA)                                                                             \
+  do {                                                                                        \
+    if (pass == 0)                                                                            \
+      hipLaunchKernelGGL((pinv_contig_group_k<RA, S>), grid, dim3(256), 0, st, ents, nent, in,  \
+                         out, stride);                                                        \
+    else                                                                                      \
+      hipLaunchKernelGGL((pinv_strided_group_k<RA, S>), grid, dim3(256), 0, st, ents, nent, in, \
+                         out, stride);                                                        \
+  } while (0)
+  if (ra_class == 0) GA_PG(4);
+  else if (ra_class == 1) GA_PG(9);
+  else GA_PG(16);
+#undef GA_PG
+}
+template void launch_pinv_group<double>(int, int, const PinvEntry*, int, int, int, const double*,
+                                        double*, long long, hipStream_t);
+template void launch_pinv_group<float>(int, int, const PinvEntry*, int, int, int, const float*,
+                                       float*, long long, hipStream_t);
 
 template <typename S>
 void launch_pinv_strided(const S* in, S* out, const S* A, int L, long long row_stride,

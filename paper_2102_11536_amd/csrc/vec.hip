@@ -296,6 +296,62 @@ __global__ void update_k(int k, double tau, Coefs c, StatePtrs sp, const double*
   }
 }
 
+// ---- segment-aware variants: system s occupies entries seg[2s] .. seg[2s] + seg[2s+1]
+// of each vector (patches of a batch have different lengths)
+
+__global__ void __launch_bounds__(VB)
+dot_partial_seg_k(const double* __restrict__ a, const double* __restrict__ b,
+                  const long long* __restrict__ seg, double* __restrict__ part) {
+  __shared__ double sh[VB / 64];
+  const int r = blockIdx.y;
+  const size_t off = (size_t)seg[2 * r], n = (size_t)seg[2 * r + 1];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB)
+    s += a[off + i] * b[off + i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void cg_fallback_seg_k(double* __restrict__ x, double* __restrict__ r,
+                                  double* __restrict__ z, const double* __restrict__ b,
+                                  const double* __restrict__ zb, const double* __restrict__ scal,
+                                  const long long* __restrict__ seg) {
+  const int rr = blockIdx.y;
+  if (scal[(size_t)rr * NSCAL + S_FALLBACK] == 0.0) return;
+  const size_t off = (size_t)seg[2 * rr], n = (size_t)seg[2 * rr + 1];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    x[off + i] = 0.0;
+    r[off + i] = b[off + i];
+    z[off + i] = zb[off + i];
+  }
+}
+
+__global__ void cg_xr_seg_k(double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ q,
+                            const double* __restrict__ scal, const long long* __restrict__ seg) {
+  const int rr = blockIdx.y;
+  const double a = scal[(size_t)rr * NSCAL + S_ALPHA];
+  if (a == 0.0) return;
+  const size_t off = (size_t)seg[2 * rr], n = (size_t)seg[2 * rr + 1];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    x[off + i] += a * p[off + i];
+    r[off + i] -= a * q[off + i];
+  }
+}
+
+__global__ void cg_p_seg_k(double* __restrict__ p, const double* __restrict__ z,
+                           const double* __restrict__ scal, const long long* __restrict__ seg) {
+  const int rr = blockIdx.y;
+  if (scal[(size_t)rr * NSCAL + S_ACTIVE] == 0.0) return;
+  const double b = scal[(size_t)rr * NSCAL + S_BETA];
+  const size_t off = (size_t)seg[2 * rr], n = (size_t)seg[2 * rr + 1];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[off + i] = z[off + i] + b * p[off + i];
+}
+
 inline unsigned nblocks(size_t n) {
   size_t b = (n + VB - 1) / VB;
   if (b > 8192) b = 8192;
@@ -336,6 +392,26 @@ void launch_scaling(double* s, const double* d, const double* h0, const double* 
 void launch_dot_partial(int nr, const double* a, const double* b, size_t n, double* part,
                         hipStream_t st) {
   hipLaunchKernelGGL(dot_partial_k, dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part);
+}
+void launch_dot_partial_seg(int ns, const double* a, const double* b, const long long* seg,
+                            double* part, hipStream_t st) {
+  hipLaunchKernelGGL(dot_partial_seg_k, dim3(RED_BLOCKS, ns), dim3(VB), 0, st, a, b, seg, part);
+}
+void launch_cg_fallback_seg(int ns, double* x, double* r, double* z, const double* b,
+                            const double* zb, const double* scal, const long long* seg,
+                            size_t maxlen, hipStream_t st) {
+  unsigned bl = nblocks(maxlen) > 2048 ? 2048 : nblocks(maxlen);
+  hipLaunchKernelGGL(cg_fallback_seg_k, dim3(bl, ns), dim3(VB), 0, st, x, r, z, b, zb, scal, seg);
+}
+void launch_cg_xr_seg(int ns, double* x, double* r, const double* p, const double* q,
+                      const double* scal, const long long* seg, size_t maxlen, hipStream_t st) {
+  unsigned bl = nblocks(maxlen) > 2048 ? 2048 : nblocks(maxlen);
+  hipLaunchKernelGGL(cg_xr_seg_k, dim3(bl, ns), dim3(VB), 0, st, x, r, p, q, scal, seg);
+}
+void launch_cg_p_seg(int ns, double* p, const double* z, const double* scal, const long long* seg,
+                     size_t maxlen, hipStream_t st) {
+  unsigned bl = nblocks(maxlen) > 2048 ? 2048 : nblocks(maxlen);
+  hipLaunchKernelGGL(cg_p_seg_k, dim3(bl, ns), dim3(VB), 0, st, p, z, scal, seg);
 }
 void launch_cg_start(int nr, const double* prz, const double* pbn, double* scal, double tol2,
                      hipStream_t st) {

@@ -12,13 +12,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libga.so")
 
 GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EGEOMETRY, GA_ENOCONV, GA_EUNSTABLE = 0, -1, -2, -3, -4, -5, -6
-GA_GUESS_ZERO, GA_GUESS_PREV, GA_GUESS_EXTRAP = 0, 1, 2
+GA_GUESS_ZERO, GA_GUESS_PREV, GA_GUESS_EXTRAP, GA_GUESS_LEARNED = 0, 1, 2, 3
+GA_GNET_NPARAM = 32033
 GA_FP64, GA_FP32 = 0, 1
 
 EXPORTS = ["ga_setup_patch", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
            "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
            "ga_integrator_create", "ga_integrator_destroy", "ga_init_state", "ga_step",
-           "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error"]
+           "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error", "ga_stage_solution",
+           "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
+           "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
+           "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
+           "ga_batch_tune", "ga_batch_init_state", "ga_batch_step"]
 
 
 class GAError(RuntimeError):
@@ -59,6 +64,25 @@ def load_library(path=LIB_PATH):
     lib.ga_profile.argtypes = [i]
     lib.ga_profile_query.argtypes = [i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
     lib.ga_last_error.restype = ctypes.c_char_p
+    ip, fp = ctypes.POINTER(i), ctypes.POINTER(ctypes.c_float)
+    lib.ga_stage_solution.argtypes = [vp, i, i, dp, vp]
+    lib.ga_gnet_create.argtypes = [fp, ctypes.POINTER(vp)]
+    lib.ga_gnet_destroy.argtypes = [vp]
+    lib.ga_gnet_set_params.argtypes = [vp, fp]
+    lib.ga_gnet_get_params.argtypes = [vp, fp]
+    lib.ga_gnet_make_batch.argtypes = [vp, vp, ctypes.POINTER(vp), dp, i, i, ip, dp, dp, vp]
+    lib.ga_gnet_forward.argtypes = [vp, i, i, ip, ip, dp, dp, vp]
+    lib.ga_gnet_loss_grad.argtypes = [vp, i, i, ip, ip, dp, dp, dp, ctypes.POINTER(d), vp]
+    lib.ga_gnet_adam.argtypes = [vp, dp, ctypes.c_float, vp]
+    lib.ga_gnet_infer.argtypes = [vp, vp, ctypes.POINTER(vp), dp, vp]
+    lib.ga_integrator_set_net.argtypes = [vp, i, vp]
+    lp = ctypes.POINTER(ctypes.c_longlong)
+    lib.ga_batch_create.argtypes = [i, ctypes.POINTER(vp), i, d, d, d, i, ctypes.POINTER(vp)]
+    lib.ga_batch_destroy.argtypes = [vp]
+    lib.ga_batch_info.argtypes = [vp, lp, lp, lp]
+    lib.ga_batch_tune.argtypes = [vp, i, ctypes.POINTER(d), vp]
+    lib.ga_batch_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
+    lib.ga_batch_step.argtypes = [vp, ctypes.POINTER(vp), i, i, ctypes.POINTER(i), vp]
     for name in EXPORTS:
         if name not in ("ga_stability_limit", "ga_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -196,7 +220,7 @@ def ga_step(integ, state, nsteps=1, record_iters=True):
     return np.array(its, dtype=np.int64).reshape(nsteps, integ.k) if record_iters else None
 
 
-PROF_MASS, PROF_STIFF, PROF_PINV = 0, 1, 2
+PROF_MASS, PROF_STIFF, PROF_PINV, PROF_GUESS = 0, 1, 2, 3
 
 
 def ga_profile(enable):
@@ -217,3 +241,178 @@ def ga_solve_stats(patch, reset=True):
     _check(_lib.ga_solve_stats(patch.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(m),
                                1 if reset else 0))
     return {"solves": a.value, "guessed": b.value, "fallbacks": c.value, "mean_guess_relres": m.value}
+
+
+def ga_stage_solution(integ, stage, age, out):
+    _check(_lib.ga_stage_solution(integ.h, int(stage), int(age), _ptr(out, integ.patch.n_free), _stream()))
+
+
+# ---- learned initial guess ----
+
+def _fptr(t, n=None):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("net buffers must be contiguous float32 CUDA tensors")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"buffer has {t.numel()} entries, needs {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ints(values):
+    values = [int(v) for v in np.asarray(values).reshape(-1)]
+    return (ctypes.c_int * max(1, len(values)))(*values)
+
+
+def _host_params(params):
+    if params is None:
+        return None
+    a = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    if a.size != GA_GNET_NPARAM:
+        raise ValueError(f"need {GA_GNET_NPARAM} parameters")
+    return a
+
+
+class GNet:
+    """Learned-guess net (ga_gnet_create); params: host array of GA_GNET_NPARAM floats or None."""
+
+    def __init__(self, params=None):
+        lib = load_library()
+        a = _host_params(params)
+        h = ctypes.c_void_p()
+        _check(lib.ga_gnet_create(None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                  ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ga_gnet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ga_gnet_create(params=None):
+    return GNet(params)
+
+
+def ga_gnet_set_params(net, params):
+    a = _host_params(params)
+    _check(_lib.ga_gnet_set_params(net.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+
+def ga_gnet_get_params(net):
+    a = np.zeros(GA_GNET_NPARAM, dtype=np.float32)
+    _check(_lib.ga_gnet_get_params(net.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return a
+
+
+def _hist_array(patch, hist):
+    if len(hist) != 4:
+        raise ValueError("need 4 history vectors (newest first)")
+    return (ctypes.c_void_p * 4)(*[_ptr(h, patch.n_free).value for h in hist])
+
+
+def ga_gnet_make_batch(net, patch, hist, x, origins, S, inp, tgt):
+    nb = len(origins)
+    T = S - 6
+    _check(_lib.ga_gnet_make_batch(net.h, patch.h, _hist_array(patch, hist), _ptr(x, patch.n_free), nb, int(S),
+                                   _ints(origins), _fptr(inp, nb * 4 * S ** 3), _fptr(tgt, nb * T ** 3),
+                                   _stream()))
+
+
+def ga_gnet_forward(net, grid, origins, S, inp, out):
+    nb = len(origins)
+    _check(_lib.ga_gnet_forward(net.h, nb, int(S), _ints(grid), _ints(origins), _fptr(inp, nb * 4 * S ** 3),
+                                _fptr(out, nb * (S - 6) ** 3), _stream()))
+
+
+def ga_gnet_loss_grad(net, grid, origins, S, inp, tgt, grad, want_loss=True):
+    nb = len(origins)
+    loss = ctypes.c_double()
+    _check(_lib.ga_gnet_loss_grad(net.h, nb, int(S), _ints(grid), _ints(origins), _fptr(inp, nb * 4 * S ** 3),
+                                  _fptr(tgt, nb * (S - 6) ** 3), _fptr(grad, GA_GNET_NPARAM),
+                                  ctypes.byref(loss) if want_loss else None, _stream()))
+    return loss.value if want_loss else None
+
+
+def ga_gnet_adam(net, grad, lr):
+    _check(_lib.ga_gnet_adam(net.h, _fptr(grad, GA_GNET_NPARAM), ctypes.c_float(lr), _stream()))
+
+
+def ga_gnet_infer(net, patch, hist, x):
+    _check(_lib.ga_gnet_infer(net.h, patch.h, _hist_array(patch, hist), _ptr(x, patch.n_free), _stream()))
+
+
+def ga_integrator_set_net(integ, stage, net):
+    _check(_lib.ga_integrator_set_net(integ.h, int(stage), None if net is None else net.h))
+    # the integrator holds the net's handle: keep the Python object alive with it
+    integ.__dict__.setdefault("_nets", {})[int(stage)] = net
+
+
+# ---- batched independent patches ----
+
+class Batch:
+    """R independent 3-D patches stepped together (ga_batch_create)."""
+
+    def __init__(self, patches, k, rho, tau, rtol=1e-10, maxit=200):
+        lib = load_library()
+        arr = (ctypes.c_void_p * len(patches))(*[p.h.value for p in patches])
+        h = ctypes.c_void_p()
+        _check(lib.ga_batch_create(len(patches), arr, int(k), float(rho), float(tau), float(rtol), int(maxit),
+                                   ctypes.byref(h)))
+        self.h, self.patches, self.k = h, list(patches), k
+        n = ctypes.c_longlong()
+        offs = (ctypes.c_longlong * len(patches))()
+        _check(lib.ga_batch_info(h, ctypes.byref(n), offs, None))
+        self.n_total, self.offsets = n.value, list(offs)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ga_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ga_batch_create(patches, k, rho, tau, rtol=1e-10, maxit=200):
+    return Batch(patches, k, rho, tau, rtol, maxit)
+
+
+def ga_batch_graph_replays(batch):
+    r = ctypes.c_longlong()
+    _check(_lib.ga_batch_info(batch.h, None, None, ctypes.byref(r)))
+    return r.value
+
+
+def ga_batch_tune(batch, reps=5):
+    ms = ctypes.c_double()
+    _check(_lib.ga_batch_tune(batch.h, int(reps), ctypes.byref(ms), _stream()))
+    return ms.value
+
+
+def _batch_state(batch, state):
+    ns = 3 * batch.k
+    if len(state) != ns:
+        raise ValueError(f"need {ns} state vectors")
+    return (ctypes.c_void_p * ns)(*[_ptr(s, batch.n_total).value for s in state])
+
+
+def ga_batch_init_state(batch, U0, V0, state):
+    n = batch.n_total
+    _check(_lib.ga_batch_init_state(batch.h, _ptr(U0, n), _ptr(V0, n), _batch_state(batch, state), _stream()))
+
+
+def ga_batch_step(batch, state, nsteps=1, use_graph=True):
+    """Advance; returns int array [nsteps, k, npatch] of PCG iterations."""
+    R = len(batch.patches)
+    its = (ctypes.c_int * (nsteps * batch.k * R))()
+    _check(_lib.ga_batch_step(batch.h, _batch_state(batch, state), int(nsteps), 1 if use_graph else 0, its,
+                              _stream()))
+    return np.array(its, dtype=np.int64).reshape(nsteps, batch.k, R)

@@ -17,6 +17,12 @@ stepping); it only builds input arrays.  Recipes:
   RMS 1.
 * The 2-D standing wave u0 = sin(pi x) sin(pi y) is sampled at the Greville
   abscissae of the free coefficients.
+* Batched multi-patch workload: R independent cube patches, each with a
+  seeded element count n_r drawn uniformly from [n_min, n_max], degree p_r
+  from {2, 3, 4} and its own smooth random geometry map (seed base + r),
+  and a GRF initial displacement per patch (seed base + 100 + r).
+* Random parameters of the learned-guess net: normal weights with He scaling
+  sqrt(2 / fan_in) and normal biases of standard deviation 0.05, seeded.
 """
 import numpy as np
 
@@ -138,3 +144,28 @@ def make_initial(dim, n, p, init, seed=0):
     if init == "grf":
         return grf(n, p, seed, dim=dim)
     raise ValueError(init)
+
+
+GNET_LAYERS = ((4, 32), (32, 32), (32, 1))
+
+
+def gnet_random_params(seed, scale=1.0):
+    """Seeded parameters of the learned-guess net (tap-major layout, 32,033
+    values): He-scaled normal weights, small normal biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in GNET_LAYERS:
+        parts.append(rng.standard_normal(27 * ci * co) * scale * np.sqrt(2.0 / (27 * ci)))
+        parts.append(rng.standard_normal(co) * 0.05 * scale)
+    return np.concatenate(parts)
+
+
+def multipatch_specs(R=12, n_min=16, n_max=96, seed=7):
+    """[(n_r, p_r, geometry_seed_r, initial_seed_r)] of the batched workload."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(R):
+        n = int(rng.integers(n_min, n_max + 1))
+        p = int(rng.integers(2, 5))
+        out.append((n, p, seed * 1000 + r, seed * 1000 + 100 + r))
+    return out

@@ -1,0 +1,138 @@
+"""Batched independent patches (one launch per degree / pass / vector op, PCG
+iterations replayed from a captured hipGraph) against the oracle and against
+the same patches stepped one at a time."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2102_11536_amd import ga, workloads
+from tests.helpers import OracleProblem, rel
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ga.load_library()
+
+
+def _setup(specs):
+    pts, U0s = [], []
+    for (n, p, gseed, useed) in specs:
+        pts.append(ga.ga_setup_patch(3, n, p, workloads.smooth_random_ctrl(n, p, gseed)))
+        U0s.append(workloads.grf(n, p, seed=useed))
+    return pts, U0s
+
+
+def _tau(pts, rho=0.5):
+    lam = max(ga.ga_lambda_max(pt, 30) for pt in pts)
+    return 0.5 * np.sqrt(ga.ga_stability_limit(rho) / lam)
+
+
+def _run_batch(pts, U0s, k, tau, nsteps, use_graph=True, tune=False, rtol=1e-12):
+    b = ga.ga_batch_create(pts, k, 0.5, tau, rtol=rtol)
+    if tune:
+        ga.ga_batch_tune(b, reps=2)
+    U = _t(np.concatenate(U0s))
+    state = [torch.zeros(b.n_total, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    ga.ga_batch_init_state(b, U, torch.zeros_like(U), state)
+    hist = [[_np(s) for s in state]]
+    its = []
+    for _ in range(nsteps):
+        its.append(ga.ga_batch_step(b, state, 1, use_graph=use_graph))
+        hist.append([_np(s) for s in state])
+    return b, hist, np.concatenate(its)
+
+
+def _split(b, v):
+    return [v[o:o + pt.n_free] for o, pt in zip(b.offsets, b.patches)]
+
+
+SMALL = [(4, 2, 11, 111), (5, 3, 12, 112), (3, 4, 13, 113), (6, 2, 14, 114)]
+
+
+def test_batch_matches_oracle():
+    _say("batch vs oracle")
+    k = 2
+    pts, U0s = _setup(SMALL)
+    tau = _tau(pts)
+    b, hist, its = _run_batch(pts, U0s, k, tau, 8)
+    assert ga.ga_batch_graph_replays(b) > 0
+    for r, (n, p, gseed, _) in enumerate(SMALL):
+        pr = OracleProblem(3, n, p, geometry="random", seed=gseed)
+        ora = pr.run(U0s[r], 0 * U0s[r], k, 0.5, tau, 8)
+        M = pr.M
+        for step in (1, 4, 8):
+            for s in range(3 * k):
+                g = _split(b, hist[step][s])[r]
+                o = ora[step][s - 2]
+                d = g - o
+                # fields that are exactly zero (e.g. L^3 after one step from V0 = 0) compare absolutely
+                e = np.sqrt(d @ (M @ d)) / max(np.sqrt(o @ (M @ o)), 1e-300)
+                assert e < 1e-10, (r, step, s, e)
+    _say("  iterations per system", its.mean(axis=0).tolist())
+
+
+def test_batch_equals_separate_patches():
+    # uneven batch of the multi-patch recipe at reduced sizes; every patch must
+    # follow the single-patch integrator
+    specs = workloads.multipatch_specs(R=12, n_min=4, n_max=14, seed=3)
+    _say("batch vs separate", specs)
+    k = 2
+    pts, U0s = _setup(specs)
+    tau = _tau(pts)
+    b, hist, _ = _run_batch(pts, U0s, k, tau, 6, tune=True)
+    for r, pt in enumerate(pts):
+        integ = ga.ga_integrator_create(pt, k, 0.5, tau, rtol=1e-12)
+        state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+        U = _t(U0s[r])
+        ga.ga_init_state(integ, U, torch.zeros_like(U), state)
+        ga.ga_step(integ, state, 6)
+        for s in range(3 * k):
+            assert rel(_split(b, hist[-1][s])[r], _np(state[s])) < 1e-10, (r, s)
+
+
+def test_graph_replays_match_eager():
+    # every replay of the captured PCG iteration against the eager launches,
+    # with eager work and synchronisations between replays (each step replays
+    # the graph several times, and steps are compared one by one)
+    _say("graph vs eager")
+    k = 2
+    pts, U0s = _setup(SMALL[:3])
+    tau = _tau(pts)
+    bg, hg, ig = _run_batch(pts, U0s, k, tau, 6, use_graph=True)
+    be, he, ie = _run_batch(pts, U0s, k, tau, 6, use_graph=False)
+    assert ga.ga_batch_graph_replays(bg) >= 6 and ga.ga_batch_graph_replays(be) == 0
+    assert np.array_equal(ig, ie)
+    for step in range(1, 7):
+        for s in range(3 * k):
+            assert rel(hg[step][s], he[step][s]) < 1e-13, (step, s)
+
+
+def test_batch_errors():
+    pt2 = ga.ga_setup_patch(2, 6, 2, workloads.identity_ctrl(6, 2, 2))
+    pt3 = ga.ga_setup_patch(3, 4, 1, workloads.deformed_cube_ctrl(4, 1))
+    for bad in ([pt2], [pt3]):
+        with pytest.raises(ga.GAError):
+            ga.ga_batch_create(bad, 2, 0.5, 1e-3)
+    ok = ga.ga_setup_patch(3, 4, 2, workloads.deformed_cube_ctrl(4, 2))
+    with pytest.raises(ga.GAError):
+        ga.ga_batch_create([ok], 5, 0.5, 1e-3)

@@ -1,0 +1,269 @@
+"""Parity of the learned-guess kernels (FP32 training, BF16 inference) with the
+CPU oracle in oracle/convnet.py, called through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import convnet as cn
+from paper_2102_11536_amd import ga, workloads
+from tests.helpers import OracleProblem, rel
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ga.load_library()
+
+
+def _fields(pt, seed):
+    """Smooth-ish random history and solution on the free grid of a patch."""
+    rng = np.random.default_rng(seed)
+    n = pt.n_free
+    H = [rng.standard_normal(n) * (1.0 + 0.1 * h) for h in range(4)]
+    X = rng.standard_normal(n)
+    return H, X
+
+
+def _grid(pt):
+    mx, my, mz = pt.mf
+    return (mz, my, mx)
+
+
+def _origins(pt, S, nb, seed):
+    rng = np.random.default_rng(seed)
+    T = S - 6
+    out = [(-3, -3, -3), (pt.mf[0] - T - 3, pt.mf[1] - T - 3, pt.mf[2] - T - 3)]
+    while len(out) < nb:
+        out.append(tuple(int(rng.integers(-3, pt.mf[a] - T - 3 + 1)) for a in range(3)))
+    return out
+
+
+PATCHES = [((9, 8, 7), 3), ((12, 10, 8), 2)]
+
+
+@pytest.mark.parametrize("n,p", PATCHES)
+def test_make_batch_matches_oracle(n, p):
+    _say("make_batch", n, p)
+    pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
+    H, X = _fields(pt, 1)
+    S = 10
+    org = _origins(pt, S, 5, 2)
+    net = ga.GNet()
+    inp = torch.zeros(len(org) * 4 * S ** 3, dtype=torch.float32, device=DEV)
+    tgt = torch.zeros(len(org) * (S - 6) ** 3, dtype=torch.float32, device=DEV)
+    ga.ga_gnet_make_batch(net, pt, [_t(h) for h in H], _t(X), org, S, inp, tgt)
+    ri, rt = cn.crops(H, X, _grid(pt), org, S)
+    gi, gt = _np(inp).reshape(ri.shape), _np(tgt).reshape(rt.shape)
+    assert np.max(np.abs(gi - ri)) <= 1e-6 * np.max(np.abs(ri))
+    assert np.max(np.abs(gt - rt)) <= 1e-6 * np.max(np.abs(rt))
+
+
+def _crop_inputs(pt, H, S, org):
+    ri, _ = cn.crops(H, np.zeros_like(H[0]), _grid(pt), org, S)
+    return _t(ri.reshape(-1), torch.float32)
+
+
+@pytest.mark.parametrize("n,p", PATCHES)
+def test_forward_matches_oracle(n, p):
+    _say("forward", n, p)
+    pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
+    H, _ = _fields(pt, 3)
+    S = 11
+    org = _origins(pt, S, 4, 4)
+    params = workloads.gnet_random_params(5)
+    net = ga.GNet(params)
+    out = torch.zeros(len(org) * (S - 6) ** 3, dtype=torch.float32, device=DEV)
+    ga.ga_gnet_forward(net, pt.mf, org, S, _crop_inputs(pt, H, S, org), out)
+    full, _ = cn.net_fields(params, H, _grid(pt))
+    T = S - 6
+    got = _np(out).reshape(len(org), T, T, T)
+    for b, (ox, oy, oz) in enumerate(org):
+        ref = full[oz + 3:oz + 3 + T, oy + 3:oy + 3 + T, ox + 3:ox + 3 + T]
+        assert np.max(np.abs(got[b] - ref)) <= 1e-5 * np.max(np.abs(full)), b
+
+
+@pytest.mark.parametrize("n,p", PATCHES)
+def test_loss_grad_matches_oracle(n, p):
+    _say("loss_grad", n, p)
+    pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
+    H, X = _fields(pt, 6)
+    S = 10
+    org = _origins(pt, S, 3, 7)
+    params = workloads.gnet_random_params(8)
+    net = ga.GNet(params)
+    inp = torch.zeros(len(org) * 4 * S ** 3, dtype=torch.float32, device=DEV)
+    tgt = torch.zeros(len(org) * (S - 6) ** 3, dtype=torch.float32, device=DEV)
+    ga.ga_gnet_make_batch(net, pt, [_t(h) for h in H], _t(X), org, S, inp, tgt)
+    grad = torch.zeros(ga.GA_GNET_NPARAM, dtype=torch.float32, device=DEV)
+    loss = ga.ga_gnet_loss_grad(net, pt.mf, org, S, inp, tgt, grad)
+    rl, rg = cn.crop_loss(params, H, X, _grid(pt), org, S)
+    g = _np(grad)
+    _say("  loss", loss, rl, "grad rel", rel(g, rg))
+    assert abs(loss - rl) <= 1e-5 * rl
+    assert rel(g, rg) <= 1e-4
+    # every layer's block of the gradient, not just the dominant one
+    o = 0
+    for ci, co in cn.LAYERS:
+        for size in (27 * ci * co, co):
+            assert rel(g[o:o + size], rg[o:o + size]) <= 1e-3, (o, size)
+            o += size
+
+
+def test_adam_matches_oracle():
+    _say("adam")
+    params = workloads.gnet_random_params(9)
+    net = ga.GNet(params)
+    rng = np.random.default_rng(10)
+    p, m, v = params.astype(np.float32).astype(np.float64), np.zeros(cn.NPARAM), np.zeros(cn.NPARAM)
+    for k in range(1, 4):
+        g = rng.standard_normal(cn.NPARAM).astype(np.float32)
+        ga.ga_gnet_adam(net, _t(g, torch.float32), 1e-3)
+        p, m, v = cn.adam_step(p, m, v, g.astype(np.float64), k, 1e-3)
+    got = ga.ga_gnet_get_params(net)
+    assert np.max(np.abs(got - p)) <= 2e-6
+
+
+INFER = [((9, 8, 7), 3), ((20, 13, 9), 3), ((16, 6, 7), 2)]
+
+
+@pytest.mark.parametrize("n,p", INFER)
+def test_infer_matches_oracle(n, p):
+    _say("infer", n, p)
+    pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
+    H, _ = _fields(pt, 11)
+    Ht = [_t(h) for h in H]
+    x = torch.zeros(pt.n_free, dtype=torch.float64, device=DEV)
+    # zero net: exactly the extrapolation
+    net0 = ga.GNet()
+    ga.ga_gnet_infer(net0, pt, Ht, x)
+    E = cn.extrapolation(H)
+    assert np.max(np.abs(_np(x) - E)) <= 1e-13 * np.max(np.abs(E))
+    # random net: BF16 weights and activations, FP32 accumulation
+    params = workloads.gnet_random_params(12)
+    net = ga.GNet(params)
+    ga.ga_gnet_infer(net, pt, Ht, x)
+    full, s3 = cn.net_fields(params, H, _grid(pt))
+    got = (_np(x) - E) / s3
+    err = np.max(np.abs(got - full.reshape(-1)))
+    _say("  bf16 max err", err, "max |net|", np.max(np.abs(full)))
+    assert err <= 2e-2 * np.max(np.abs(full))
+    # after a parameter change the packed BF16 weights are rebuilt
+    ga.ga_gnet_set_params(net, np.zeros(cn.NPARAM))
+    ga.ga_gnet_infer(net, pt, Ht, x)
+    assert np.max(np.abs(_np(x) - E)) <= 1e-13 * np.max(np.abs(E))
+
+
+def _run(pt, U0, k, tau, nsteps, guess, nets=None, prec=ga.GA_FP64):
+    integ = ga.ga_integrator_create(pt, k, 0.5, tau, rtol=1e-12, maxit=200, guess=guess, prec=prec)
+    for j, net in enumerate(nets or []):
+        ga.ga_integrator_set_net(integ, j, net)
+    state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    U = _t(U0)
+    ga.ga_init_state(integ, U, torch.zeros_like(U), state)
+    its = ga.ga_step(integ, state, nsteps)
+    return [_np(s) for s in state], its
+
+
+def test_learned_zero_net_equals_extrapolation():
+    _say("learned zero net")
+    pr = OracleProblem(3, 8, 3)
+    tau = pr.tau()
+    U0 = workloads.grf(8, 3, seed=9)
+    pt = ga.ga_setup_patch(3, 8, 3, pr.ctrl)
+    ga.ga_solve_stats(pt)
+    s0, i0 = _run(pt, U0, 2, tau, 12, ga.GA_GUESS_EXTRAP)
+    st0 = ga.ga_solve_stats(pt)
+    s1, i1 = _run(pt, U0, 2, tau, 12, ga.GA_GUESS_LEARNED, [ga.GNet(), ga.GNet()])
+    st1 = ga.ga_solve_stats(pt)
+    assert np.array_equal(i0, i1)
+    assert abs(st0["mean_guess_relres"] - st1["mean_guess_relres"]) <= 1e-9
+    for a, b in zip(s0, s1):
+        assert rel(a, b) <= 1e-12
+
+
+@pytest.mark.parametrize("scale,prec", [(1.0, ga.GA_FP64), (30.0, ga.GA_FP64), (1.0, ga.GA_FP32)])
+def test_learned_guess_matches_oracle(scale, prec):
+    # any net only changes where PCG starts: the trajectory stays the oracle's;
+    # a wild net (scale 30) is rejected by the residual test and falls back to zero
+    _say("learned vs oracle", scale, prec)
+    pr = OracleProblem(3, 6, 3)
+    tau = pr.tau()
+    U0 = workloads.grf(6, 3, seed=13)
+    pt = ga.ga_setup_patch(3, 6, 3, pr.ctrl)
+    nets = [ga.GNet(workloads.gnet_random_params(20 + j, scale)) for j in range(2)]
+    ga.ga_solve_stats(pt)
+    st, its = _run(pt, U0, 2, tau, 10, ga.GA_GUESS_LEARNED, nets, prec)
+    stats = ga.ga_solve_stats(pt)
+    ora = pr.run(U0, 0 * U0, 2, 0.5, tau, 10)[-1]
+    M = pr.M
+    for s in range(6):
+        d = st[s] - ora[s - 2]
+        e = np.sqrt(d @ (M @ d)) / np.sqrt(ora[s - 2] @ (M @ ora[s - 2]))
+        assert e < 1e-10, (s, e)
+    _say("  stats", stats)
+    if scale > 10:
+        assert stats["fallbacks"] >= 2 * 6  # every learned guess (steps 5..10) rejected
+
+
+def test_errors():
+    pr2 = OracleProblem(2, 6, 2)
+    pt2 = ga.ga_setup_patch(2, 6, 2, pr2.ctrl)
+    integ = ga.ga_integrator_create(pt2, 1, 0.5, 1e-3, guess=ga.GA_GUESS_LEARNED)
+    with pytest.raises(ga.GAError):
+        ga.ga_integrator_set_net(integ, 0, ga.GNet())      # 2-D patch
+    pt = ga.ga_setup_patch(3, 6, 2, workloads.deformed_cube_ctrl(6, 2))
+    integ3 = ga.ga_integrator_create(pt, 2, 0.5, 1e-3, guess=ga.GA_GUESS_LEARNED)
+    with pytest.raises(ga.GAError):
+        ga.ga_integrator_set_net(integ3, 2, ga.GNet())     # stage out of range
+    net = ga.GNet()
+    H = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(4)]
+    inp = torch.zeros(4 * 4 * 10 ** 3, dtype=torch.float32, device=DEV)
+    tgt = torch.zeros(4 * 4 ** 3, dtype=torch.float32, device=DEV)
+    with pytest.raises(ga.GAError):   # target box leaves the grid
+        ga.ga_gnet_make_batch(net, pt, H, H[0], [(pt.mf[0] - 3, 0, 0)], 10, inp, tgt)
+    with pytest.raises(ga.GAError):
+        ga.ga_gnet_make_batch(net, pt, H, H[0], [(-4, 0, 0)], 10, inp, tgt)
+    out = torch.zeros(pt.n_free, dtype=torch.float64, device=DEV)
+    with pytest.raises(ga.GAError):
+        ga.ga_stage_solution(integ3, 0, 1, out)           # no history yet
+
+
+def test_trained_net_gain():
+    """What the trained nets (committed weights, trained on 128^3 p = 3 k = 2
+    trajectories) gain over the plain extrapolated guess on a trajectory that
+    was not used in training: the preconditioned residual of the initial guess
+    relative to that of the zero guess, averaged over the stage solves."""
+    import math
+    from paper_2102_11536_amd.train_gnet import DEFAULT_WEIGHTS, evaluate, load_weights
+    params, meta = load_weights(DEFAULT_WEIGHTS)
+    n, p, k = meta["n"], meta["p"], meta["k"]
+    pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
+    tau = 0.5 * math.sqrt(ga.ga_stability_limit(0.5) / ga.ga_lambda_max(pt, 25))
+    nets = [ga.GNet(w) for w in params]
+    res = {}
+    for name, mode in (("extrapolation", ga.GA_GUESS_EXTRAP), ("learned", ga.GA_GUESS_LEARNED),
+                       ("zero", ga.GA_GUESS_ZERO)):
+        res[name] = evaluate(pt, k, 0.5, tau, 1e-10, mode, nets, 20, seed=424242)
+        _say(" ", name, res[name])
+    assert res["learned"]["fallbacks"] == 0
+    assert res["learned"]["mean_guess_relres"] < 0.9 * res["extrapolation"]["mean_guess_relres"]
+    assert res["learned"]["mean_iters"] <= res["extrapolation"]["mean_iters"] <= res["zero"]["mean_iters"]
