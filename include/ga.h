@@ -104,11 +104,19 @@ int ga_apply_MK(ga_patch* patch, char which, int nrhs, double alpha,
 /*
  * ga_apply_Pinv -- z = P^{-1} r for nrhs vectors, with
  * P = D^{1/2} Dhat^{-1/2} Mhat Dhat^{-1/2} D^{1/2} (Sec. 5.4), applied as
- * z = s * (Mz^{-1} x My^{-1} x Mx^{-1})(s * r): a dense contraction along
- * each tensor axis.  r and z may be the same buffer.
+ * z = s * (Mz^{-1} x My^{-1} x Mx^{-1})(s * r), one univariate solve along
+ * each tensor axis: by default forward and backward substitution with the
+ * banded Cholesky factor of Mhat_a (where a z-plane fits the on-chip
+ * staging, 152 KiB), otherwise a product with the dense inverse of Mhat_a.
+ * r and z may be the same buffer.
  */
 int ga_apply_Pinv(ga_patch* patch, int nrhs, const double* r_dev, double* z_dev,
                   void* stream);
+/* Preconditioner algorithm of a patch (both compute the same P^{-1}):
+ * GA_PINV_AUTO (banded solves when they fit, the default) or GA_PINV_DENSE
+ * (dense inverse products always). */
+enum { GA_PINV_AUTO = 0, GA_PINV_DENSE = 1 };
+int ga_patch_set_pinv(ga_patch* patch, int mode);
 
 /*
  * ga_mass_solve -- PCG for M x_j = b_j, j < nrhs (Sec. 5.6; solver settings of

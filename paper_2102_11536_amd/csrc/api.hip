@@ -146,6 +146,13 @@ int pinv_apply(ga_patch* pt, int nr, const double* r, double* z, double* t0, dou
   const size_t n = pt->n_free;
   const int m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
   ProfScope prof(2, st);
+  if (pt->pinv_mode != GA_PINV_DENSE) {
+    const double* cb[3] = {pt->cb[0], pt->cb[1], pt->cb[2]};
+    const int rc = launch_pinv_band<double>(pt->dim, pt->p, pt->mf, nr, r, z, t0, t1, cb, pt->s,
+                                            (long long)n, st);
+    if (rc == 0) return check_launch(0, "preconditioner");
+    if (rc < 0) return check_launch(-1, "preconditioner");
+  }
   const bool fast = pinv_axis_supported(m0) && pinv_axis_supported(m1) &&
                     (pt->dim == 2 || pinv_axis_supported(m2));
   if (fast) {
@@ -275,6 +282,9 @@ int ensure_mixed(ga_patch* pt, hipStream_t st) {
     const size_t mm = (size_t)pt->mf[a] * pt->mf[a];
     if ((rc = dalloc((void**)&pt->Minv32[a], mm * sizeof(float)))) return rc;
     launch_to_f32(pt->Minv32[a], pt->Minv[a], mm, st);
+    const size_t nc = pt->ax[a].chol.size();
+    if ((rc = dalloc((void**)&pt->cb32[a], nc * sizeof(float)))) return rc;
+    launch_to_f32(pt->cb32[a], pt->cb[a], nc, st);
   }
   return check_launch(0, "mixed-precision setup");
 }
@@ -288,6 +298,13 @@ int pinv_apply_f32(ga_patch* pt, int nr, const float* r, float* z, float* t0, fl
     return GA_EINVAL;
   }
   ProfScope prof(2, st);
+  if (pt->pinv_mode != GA_PINV_DENSE) {
+    const float* cb[3] = {pt->cb32[0], pt->cb32[1], pt->cb32[2]};
+    const int rc = launch_pinv_band<float>(3, pt->p, pt->mf, nr, r, z, t0, t1, cb, pt->s32,
+                                           (long long)n, st);
+    if (rc == 0) return check_launch(0, "FP32 preconditioner");
+    if (rc < 0) return check_launch(-1, "FP32 preconditioner");
+  }
   launch_pinv_contig<float>(r, t1, pt->Minv32[0], m0, (long long)nr * m1 * m2,
                             (long long)m1 * m2, (long long)n, pt->s32, nullptr, st);
   launch_pinv_strided<float>(t1, t0, pt->Minv32[1], m1, m0, m0, (long long)m0 * m1, m2,
@@ -521,6 +538,7 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, voi
     for (size_t i = 0; i < ax.w.size(); ++i) w[i] = ax.w[i];
     if ((rc = upload(&pt->tabB[a], B)) || (rc = upload(&pt->tabD[a], D)) ||
         (rc = upload(&pt->tabB2[a], B2)) || (rc = upload(&pt->Minv[a], ax.Minv)) ||
+        (rc = upload(&pt->cb[a], ax.chol)) ||
         (rc = upload(&wdev[a], w))) {
       for (double* d : wdev) if (d) hipFree(d);
       return fail(rc);
@@ -595,6 +613,8 @@ int ga_destroy_patch(ga_patch* pt) {
     if (pt->tabD[a]) hipFree(pt->tabD[a]);
     if (pt->tabB2[a]) hipFree(pt->tabB2[a]);
     if (pt->Minv[a]) hipFree(pt->Minv[a]);
+    if (pt->cb[a]) hipFree(pt->cb[a]);
+    if (pt->cb32[a]) hipFree(pt->cb32[a]);
   }
   if (pt->W) hipFree(pt->W);
   if (pt->G) hipFree(pt->G);
@@ -629,6 +649,13 @@ int ga_patch_info(const ga_patch* pt, long long* n_free, long long* n_quad, int*
   if (n_free) *n_free = pt->n_free;
   if (n_quad) *n_quad = pt->n_quad;
   if (mf) for (int a = 0; a < 3; ++a) mf[a] = a < pt->dim ? pt->mf[a] : 1;
+  return GA_OK;
+}
+
+int ga_patch_set_pinv(ga_patch* pt, int mode) {
+  if (!pt) { set_error("null patch"); return GA_EINVAL; }
+  if (mode != GA_PINV_AUTO && mode != GA_PINV_DENSE) { set_error("bad preconditioner mode"); return GA_EINVAL; }
+  pt->pinv_mode = mode;
   return GA_OK;
 }
 

@@ -18,6 +18,9 @@ struct Axis1D {
   std::vector<double> w;      // [n][q]: Gauss weights (element length included)
   std::vector<double> dhat;   // [mf]: diagonal of the univariate parametric mass (free part)
   std::vector<double> Minv;   // [mf][mf]: its dense inverse, row-major
+  // its banded Cholesky factor L (bandwidth p), [mf + p][p + 1]: entry d = 0 holds
+  // 1 / L(i,i), entry d >= 1 holds L(i, i-d); the p trailing rows are zero
+  std::vector<double> chol;
 };
 
 Axis1D build_axis(int n, int p);
@@ -82,6 +85,7 @@ struct ga_patch {
   int nt[3] = {1, 1, 1};          // element tiles per direction (2-D kernels)
   int ntk[2] = {1, 1}, ntm[2] = {1, 1};  // 3-D xy columns: stiffness and mass layouts
   int ze = 0;                     // element layers per workgroup along z (0: automatic)
+  int pinv_mode = GA_PINV_AUTO;   // preconditioner algorithm (ga_patch_set_pinv)
   long long n_free = 0, n_quad = 0, n_tiles = 0, qp_per_tile = 0;
   ga::Axis1D ax[3];
   // device data
@@ -94,6 +98,8 @@ struct ga_patch {
   float* W32 = nullptr;       // FP32 copy of W (mixed-precision inner solves)
   float* Minv32[3] = {nullptr, nullptr, nullptr};  // FP32 copies of the 1-D inverses
   float* s32 = nullptr;       // FP32 copy of the scaling
+  double* cb[3] = {nullptr, nullptr, nullptr};    // banded Cholesky factors (Axis1D::chol)
+  float* cb32[3] = {nullptr, nullptr, nullptr};
   double* diagM = nullptr;    // [n_free]
   double* s = nullptr;        // [n_free] (Dhat/D)^(1/2)
   double* Minv[3] = {nullptr, nullptr, nullptr};   // [mf][mf]

@@ -79,6 +79,10 @@ struct PinvEntry {
   int blk0;
 };
 int pinv_ra_class(int L);
+// banded-Cholesky preconditioner (0 launched, 1 does not fit the LDS staging, -1 error)
+template <typename S>
+int launch_pinv_band(int dim, int p, const int* mf, int nr, const S* r, S* z, S* t0, S* t1,
+                     const S* const* cb, const S* s, long long n_free, hipStream_t st);
 template <typename S>
 void launch_pinv_group(int pass, int ra_class, const PinvEntry* ents, int nent, int nblk, int nr,
                        const S* in, S* out, long long stride, hipStream_t st);

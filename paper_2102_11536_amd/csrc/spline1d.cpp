@@ -144,6 +144,11 @@ Axis1D build_axis(int n, int p) {
       L[(size_t)i * mf + j] = v / ljj;
     }
   }
+  ax.chol.assign((size_t)(mf + p) * P1, 0.0);
+  for (int i = 0; i < mf; ++i) {
+    ax.chol[(size_t)i * P1] = 1.0 / L[(size_t)i * mf + i];
+    for (int d = 1; d <= p && i - d >= 0; ++d) ax.chol[(size_t)i * P1 + d] = L[(size_t)i * mf + i - d];
+  }
   ax.Minv.assign((size_t)mf * mf, 0.0);
   std::vector<double> y(mf);
   for (int c = 0; c < mf; ++c) {

@@ -15,11 +15,12 @@ GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EGEOMETRY, GA_ENOCONV, GA_EUNSTABLE 
 GA_GUESS_ZERO, GA_GUESS_PREV, GA_GUESS_EXTRAP, GA_GUESS_LEARNED = 0, 1, 2, 3
 GA_GNET_NPARAM = 32033
 GA_FP64, GA_FP32 = 0, 1
+GA_PINV_AUTO, GA_PINV_DENSE = 0, 1
 
 EXPORTS = ["ga_setup_patch", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
            "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
            "ga_integrator_create", "ga_integrator_destroy", "ga_init_state", "ga_step",
-           "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error", "ga_stage_solution",
+           "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error", "ga_stage_solution", "ga_patch_set_pinv",
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
@@ -66,6 +67,7 @@ def load_library(path=LIB_PATH):
     lib.ga_last_error.restype = ctypes.c_char_p
     ip, fp = ctypes.POINTER(i), ctypes.POINTER(ctypes.c_float)
     lib.ga_stage_solution.argtypes = [vp, i, i, dp, vp]
+    lib.ga_patch_set_pinv.argtypes = [vp, i]
     lib.ga_gnet_create.argtypes = [fp, ctypes.POINTER(vp)]
     lib.ga_gnet_destroy.argtypes = [vp]
     lib.ga_gnet_set_params.argtypes = [vp, fp]
@@ -140,6 +142,10 @@ class Patch:
 
 def ga_setup_patch(dim, n_el, p, ctrl):
     return Patch(dim, n_el, p, ctrl)
+
+
+def ga_patch_set_pinv(patch, mode):
+    _check(_lib.ga_patch_set_pinv(patch.h, int(mode)))
 
 
 def ga_diag_M(patch, d):

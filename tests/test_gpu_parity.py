@@ -65,11 +65,15 @@ def test_operators_match_assembled(dim, n, p):
     assert rel(_np(y[: pt.n_free]), -2.5 * (pr.K @ X[0])) < 1e-13
 
 
-@pytest.mark.parametrize("dim,n,p", [(2, 9, 2), (3, 5, 3), (3, (6, 5, 3), 2), (3, 3, 4)])
-def test_preconditioner_matches_oracle(dim, n, p):
-    _say("pinv", dim, n, p)
+@pytest.mark.parametrize("mode", [ga.GA_PINV_AUTO, ga.GA_PINV_DENSE])
+@pytest.mark.parametrize("dim,n,p", [(2, 9, 2), (3, 5, 3), (3, (6, 5, 3), 2), (3, 3, 4), (2, (7, 12), 1),
+                                     (3, (12, 9, 7), 3)])
+def test_preconditioner_matches_oracle(dim, n, p, mode):
+    # banded Cholesky solves (default) and dense inverse products, against the oracle
+    _say("pinv", dim, n, p, mode)
     pr = OracleProblem(dim, n, p)
     pt = ga.ga_setup_patch(dim, n, p, pr.ctrl)
+    ga.ga_patch_set_pinv(pt, mode)
     R = np.random.default_rng(3).standard_normal((2, pt.n_free))
     r = _t(R.ravel())
     z = torch.empty_like(r)
@@ -309,6 +313,19 @@ def test_mixed_step_matches_oracle(k, p, n):
     ora = pr.run(U0, 0 * U0, k, 0.5, tau, 24)
     w = _compare(hist, ora, k, 4, 1e-10, pr.M)
     _say("  worst rel L2 error vs oracle", w)
+
+
+def test_preconditioner_plane_too_large_falls_back():
+    # a z-plane of 149 x 139 FP64 coefficients does not fit the on-chip staging:
+    # the default mode must give the dense path's result
+    n, p = (150, 140, 2), 1
+    pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
+    R = _t(np.random.default_rng(5).standard_normal(pt.n_free))
+    za, zd = torch.empty_like(R), torch.empty_like(R)
+    ga.ga_apply_Pinv(pt, R, za)
+    ga.ga_patch_set_pinv(pt, ga.GA_PINV_DENSE)
+    ga.ga_apply_Pinv(pt, R, zd)
+    assert rel(_np(za), _np(zd)) < 1e-14
 
 
 # ---- initial guesses and the residual fallback ----
