@@ -293,7 +293,7 @@ def main():
                    "learned_guess": learned_note},
         "roofline": {"bound": "hbm", "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": k_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "op3d_kernel<3,1,2> (stiffness apply, k right-hand sides)",
+                     "kernel": "op3d_kernel<3,4,1,2> (stiffness apply, p=3, k right-hand sides)",
                      "avg_launch_ms": k_avg * 1e3, "algorithmic_bytes": k_bytes,
                      "mass_apply": {"achieved": m_gbs, "avg_launch_ms": m_avg * 1e3,
                                     "algorithmic_bytes": m_bytes}},

@@ -231,15 +231,20 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
     GA_TRY_HIP(hipMemcpyAsync(pt->host_scal, pt->scal, sizeof(double) * NSCAL * nr,
                               hipMemcpyDeviceToHost, st));
     GA_TRY_HIP(hipStreamSynchronize(st));
-    bool any = false;
-    for (int r = 0; r < nr; ++r) any |= pt->host_scal[r * NSCAL + S_ACTIVE] != 0.0;
-    if (!any || it >= maxit) break;
-    launch_fill(w.q, 0.0, tot, st);
-    if ((rc = op_apply(pt, 0, nr, 1.0, w.p, w.q, st))) return rc;
+    // right-hand sides a .. b-1 span the active ones; the operator and the
+    // preconditioner skip converged ones outside that range (their step
+    // sizes are zero, so their q and z are never used)
+    int a = nr, b = 0;
+    for (int r = 0; r < nr; ++r)
+      if (pt->host_scal[r * NSCAL + S_ACTIVE] != 0.0) { a = std::min(a, r); b = r + 1; }
+    if (a >= b || it >= maxit) break;
+    const size_t o = (size_t)a * n, cnt = (size_t)(b - a);
+    launch_fill(w.q + o, 0.0, cnt * n, st);
+    if ((rc = op_apply(pt, 0, (int)cnt, 1.0, w.p + o, w.q + o, st))) return rc;
     launch_dot_partial(nr, w.p, w.q, n, partA, st);
     launch_cg_alpha(nr, partA, pt->scal, st);
     launch_cg_xr(nr, x, w.r, w.p, w.q, pt->scal, n, st);
-    if ((rc = pinv_apply(pt, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+    if ((rc = pinv_apply(pt, (int)cnt, w.r + o, w.z + o, w.t0, w.t1, st))) return rc;
     launch_dot_partial(nr, w.r, w.z, n, partA, st);
     launch_cg_beta(nr, partA, pt->scal, st);
     launch_cg_p(nr, w.p, w.z, pt->scal, n, st);

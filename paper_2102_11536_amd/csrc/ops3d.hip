@@ -69,6 +69,15 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned nwg) {
 #ifndef GA_OP3_WAVES_M
 #define GA_OP3_WAVES_M 1
 #endif
+// Gauss layers of quadrature factors prefetched ahead (stiffness: 6 factors per
+// point and much arithmetic per layer; mass: 1 factor and little arithmetic, so a
+// deeper ring is needed to cover the memory latency)
+#ifndef GA_RING_K
+#define GA_RING_K 4
+#endif
+#ifndef GA_RING_M
+#define GA_RING_M 16
+#endif
 
 // MODE: 0 mass, 1 stiffness, 2 diag(M) (tables hold squared values, x unused)
 // One workgroup's share: logical tile `lid` = (xy column, z range) of one patch.
@@ -386,7 +395,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   }
 
   // z sweep over Gauss layers with a ring of D prefetched factor planes
-  constexpr int D = (MODE == 1) ? 2 : 4;
+  constexpr int D = (MODE == 1) ? GA_RING_K : GA_RING_M;
   const int q0 = ez0 * Q, q1 = ez1 * Q;
   S gq[D][NC];
 #pragma unroll
