@@ -174,6 +174,36 @@ int ga_step(ga_integrator* integ, double* const* state_dev, int nsteps,
             int* iters_out, void* stream);
 
 /*
+ * Damping and forcing (eq. ho1 with C and F; initial data of Sec. 3).
+ * Stage j solves  M X_j = F^{(a_j)}(t_n + alpha_fj tau) - C Z_j - K Y_j,
+ * a_j = 3j-3, with Y_j the stiffness argument of ga_step and Z_j its damping
+ * counterpart: the Taylor predictor of L^{a_j-1} at t_{n+1} for j < k, L^{N-1}_n
+ * for j = k (the reading that keeps order 2k; C on L^{a_j-1}_n gives order 1).
+ * alpha_fj = 1 for j < k and 0 for j = k (ga_stage_times).
+ *
+ * ga_integrator_set_damping -- Rayleigh damping C = cM M + cK K (cM, cK >= 0;
+ * both 0 = undamped, the default).  Applies to ga_init_state* and ga_step*.
+ */
+int ga_integrator_set_damping(ga_integrator* integ, double cM, double cK);
+/* ga_stage_times -- t_n + alpha_fj tau for j = 1..k into out[k] (host). */
+int ga_stage_times(const ga_integrator* integ, double t_n, double* out);
+/*
+ * ga_init_state_forced -- as ga_init_state with a load:
+ * L^a = M^{-1}(F^{(a)}(0) - C L^{a-1} - K L^{a-2}), a = 0..3k-3.
+ * F0_dev: 3k-2 device vectors F^{(a)}(0) (the a-th time derivative of the load
+ * vector at t = 0), or NULL for no load.
+ */
+int ga_init_state_forced(ga_integrator* integ, const double* U0_dev, const double* V0_dev,
+                         const double* const* F0_dev, double* const* state_dev, void* stream);
+/*
+ * ga_step_forced -- one step from t_n with the load: forcing_dev[j] (k device
+ * vectors) = F^{(a_j)} at the stage time t_n + alpha_fj tau of ga_stage_times.
+ * iters_out: host [k] or NULL.
+ */
+int ga_step_forced(ga_integrator* integ, double* const* state_dev, const double* const* forcing_dev,
+                   int* iters_out, void* stream);
+
+/*
  * ga_stage_solution -- copy the stage-j solution X_j of `age` steps ago
  * (age 0 = the last step; ages 1..3 need a guess mode other than
  * GA_GUESS_ZERO, which keeps the ring of past solutions) into out_dev

@@ -1,6 +1,6 @@
 """The explicit order-2k generalized-alpha scheme (Sec. 3 for k = 2, Sec. 4 for
 general k: stage equations ho1, updates ho2, definitions ho3; initial data as
-in Sec. 3), written for M U'' + K U = 0 (C = 0, F = 0).
+in Sec. 3), for M U'' + C U' + K U = F.
 
 State: L^a for a = -2 .. N, N = 3k-3, with L^{-2} = U, L^{-1} = V, L^0 = A and
 L^a the a-th time derivative of A.  Block j = 1..k has base index a_j = 3j-3.
@@ -19,8 +19,11 @@ Readings of the paper used here:
   interval shrinks for k >= 2, against the paper's claim that it does not
   depend on k.  gamma_j = 1/2 - alpha_fj + alpha_j (Theorem 2).
 * The factorial printed as "3(k-j) !" is (3(k-j))!.
+* Damping and forcing.  C acts on the predictor one derivative above K's
+  argument: T_{a_j-1} for j < k, L^{N-1}_n for j = k; the load derivative
+  F^{(a_j)} is taken at t_n + alpha_fj tau (t_{n+1} for j < k, t_n for j = k).
 * Initial data for general k (printed for k = 2 only): L^{-2} = U_0,
-  L^{-1} = V_0, L^a = M^{-1}(-K L^{a-2}) for a = 0..N.
+  L^{-1} = V_0, L^a = M^{-1}(F^{(a)}(0) - C L^{a-1} - K L^{a-2}) for a = 0..N.
 """
 from math import factorial
 
@@ -96,21 +99,47 @@ def update(L, T, X, tau, k, rho):
     return new
 
 
-def step(L, tau, k, rho, apply_K, solve_M):
-    """One time step: predictors, the k stage solves M X_j = -K Y_j (eq. ho1
-    with C = F = 0), and the 3k-vector update."""
+def damping_arguments(L, T, k):
+    """Argument Z_j of C in stage equation j, by the reading used for K: the
+    full Taylor predictor T_{a_j-1} for j < k, L^{N-1}_n for j = k."""
+    N = 3 * k - 3
+    return [T[3 * j - 4] if j < k else L[N - 1] for j in range(1, k + 1)]
+
+
+def stage_times(t, tau, k, rho):
+    """Times t_n + alpha_fj tau at which stage j evaluates its forcing."""
+    return [t + af * tau for (_, _, _, af) in block_params(k, rho)]
+
+
+def step(L, tau, k, rho, apply_K, solve_M, apply_C=None, forcing=None, t=0.0):
+    """One time step from t_n = t: predictors, the k stage solves
+    M X_j = F^{(a_j)}(t_n + alpha_fj tau) - C Z_j - K Y_j (eq. ho1), and the
+    3k-vector update.  apply_C (damping) and forcing(a, t) (the a-th time
+    derivative of the load vector) may be None."""
     T = predictors(L, tau, k)
     Y = stage_arguments(L, T, k)
-    X = [solve_M(-apply_K(y)) for y in Y]
+    b = [-apply_K(y) for y in Y]
+    if apply_C is not None:
+        b = [bj - apply_C(z) for bj, z in zip(b, damping_arguments(L, T, k))]
+    if forcing is not None:
+        ts = stage_times(t, tau, k, rho)
+        b = [bj + forcing(3 * j, ts[j]) for j, bj in enumerate(b)]
+    X = [solve_M(bj) for bj in b]
     return update(L, T, X, tau, k, rho)
 
 
-def initial_state(U0, V0, k, apply_K, solve_M):
-    """L^{-2} = U0, L^{-1} = V0, L^a = M^{-1}(-K L^{a-2}), a = 0..N."""
+def initial_state(U0, V0, k, apply_K, solve_M, apply_C=None, forcing=None):
+    """L^{-2} = U0, L^{-1} = V0, L^a = M^{-1}(F^{(a)}(0) - C L^{a-1} - K L^{a-2}),
+    a = 0..N (the initial solves of Sec. 3, continued to general k)."""
     N = 3 * k - 3
     L = {-2: np.asarray(U0, dtype=np.float64), -1: np.asarray(V0, dtype=np.float64)}
     for a in range(0, N + 1):
-        L[a] = solve_M(-apply_K(L[a - 2]))
+        r = -apply_K(L[a - 2])
+        if apply_C is not None:
+            r = r - apply_C(L[a - 1])
+        if forcing is not None:
+            r = r + forcing(a, 0.0)
+        L[a] = solve_M(r)
     return L
 
 

@@ -792,6 +792,7 @@ int ga_integrator_destroy(ga_integrator* it) {
   if (it->Bv) hipFree(it->Bv);
   if (it->X) hipFree(it->X);
   if (it->H) hipFree(it->H);
+  if (it->Z) hipFree(it->Z);
   delete it;
   return GA_OK;
 }
@@ -816,21 +817,53 @@ int ga_stage_solution(ga_integrator* it, int stage, int age, double* out, void* 
   return check_launch(0, "stage solution copy");
 }
 
-int ga_init_state(ga_integrator* it, const double* U0, const double* V0, double* const* state,
-                  void* stream) {
+int ga_integrator_set_damping(ga_integrator* it, double cM, double cK) {
+  if (!it) { set_error("null integrator"); return GA_EINVAL; }
+  if (!(cM >= 0.0) || !(cK >= 0.0) || !std::isfinite(cM) || !std::isfinite(cK)) {
+    set_error("damping coefficients must be finite and non-negative");
+    return GA_EINVAL;
+  }
+  if (cM != 0.0 && !it->Z) {
+    int rc = dalloc((void**)&it->Z, (size_t)it->k * it->patch->n_free * 8);
+    if (rc) return rc;
+  }
+  it->cM = cM;
+  it->cK = cK;
+  return GA_OK;
+}
+
+int ga_stage_times(const ga_integrator* it, double t, double* out) {
+  if (!it || !out) { set_error("null argument"); return GA_EINVAL; }
+  for (int j = 0; j < it->k; ++j) out[j] = j < it->k - 1 ? t + it->tau : t;  // t_n + alpha_fj tau
+  return GA_OK;
+}
+
+int ga_init_state_forced(ga_integrator* it, const double* U0, const double* V0,
+                         const double* const* F0, double* const* state, void* stream) {
   if (!it || !U0 || !V0 || !state) { set_error("null argument"); return GA_EINVAL; }
+  const int N = 3 * it->k - 3;
   for (int s = 0; s < 3 * it->k; ++s)
     if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+  if (F0)
+    for (int a = 0; a <= N; ++a)
+      if (!F0[a]) { set_error("null forcing vector"); return GA_EINVAL; }
   ga_patch* pt = it->patch;
   hipStream_t st = S(stream);
   const size_t n = pt->n_free;
   launch_copy(state[0], U0, n, st);
   launch_copy(state[1], V0, n, st);
-  for (int a = 0; a <= 3 * it->k - 3; ++a) {
-    launch_fill(it->Y, 0.0, n, st);
-    int rc = op_apply(pt, 1, 1, -1.0, state[a], it->Y, st);  // -K L^{a-2}
+  // L^a = M^{-1}(F^{(a)}(0) - C L^{a-1} - K L^{a-2}), C = cM M + cK K
+  for (int a = 0; a <= N; ++a) {
+    double* rhs = it->Bv;
+    double* karg = it->Y;
+    if (it->cK != 0.0) launch_axpby(karg, 1.0, state[a], it->cK, state[a + 1], n, st);
+    else launch_copy(karg, state[a], n, st);
+    if (F0) launch_copy(rhs, F0[a], n, st);
+    else launch_fill(rhs, 0.0, n, st);
+    int rc = op_apply(pt, 1, 1, -1.0, karg, rhs, st);
     if (rc) return rc;
-    rc = solve_any(pt, 1, it->Y, state[a + 2], it->rtol, it->maxit, it->prec, true, nullptr,
+    if (it->cM != 0.0 && (rc = op_apply(pt, 0, 1, -it->cM, state[a + 1], rhs, st))) return rc;
+    rc = solve_any(pt, 1, rhs, state[a + 2], it->rtol, it->maxit, it->prec, true, nullptr,
                    nullptr, st);
     if (rc) return rc;
   }
@@ -840,71 +873,121 @@ int ga_init_state(ga_integrator* it, const double* U0, const double* V0, double*
   return GA_OK;
 }
 
-int ga_step(ga_integrator* it, double* const* state, int nsteps, int* iters_out, void* stream) {
-  if (!it || !state || nsteps < 0) { set_error("bad argument"); return GA_EINVAL; }
-  const int k = it->k, ns = 3 * k;
-  for (int s = 0; s < ns; ++s)
-    if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+int ga_init_state(ga_integrator* it, const double* U0, const double* V0, double* const* state,
+                  void* stream) {
+  return ga_init_state_forced(it, U0, V0, nullptr, state, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// one step: predictors, stage right-hand sides b_j = F_j - C Z_j - K Y_j (eq. ho1;
+// F optional, C = cM M + cK K), the k solves and the update
+int step_once(ga_integrator* it, const StatePtrs& sp, const Coefs& cf, const double* const* F,
+              int* iters, hipStream_t st) {
   ga_patch* pt = it->patch;
-  hipStream_t st = S(stream);
+  const int k = it->k;
   const size_t n = pt->n_free;
-  StatePtrs sp;
-  for (int s = 0; s < 12; ++s) sp.L[s] = s < ns ? state[s] : nullptr;
-  Coefs cf;
-  for (int j = 0; j < 4; ++j) {
-    cf.alpha[j] = j < k ? it->alpha[j] : 1.0;
-    cf.beta[j] = j < k ? it->beta[j] : 0.0;
-    cf.gamma[j] = j < k ? it->gamma[j] : 0.0;
-  }
-  int iters[16];
-  for (int step = 0; step < nsteps; ++step) {
-    launch_predict(k, it->tau, sp, it->Y, n, st);
-    // stage right-hand sides b_j = -K Y_j (eq. ho1 with C = F = 0)
+  const bool damped = it->cM != 0.0 || it->cK != 0.0;
+  if (damped) launch_predict_cz(k, it->tau, it->cK, sp, it->Y, it->cM != 0.0 ? it->Z : nullptr, n, st);
+  else launch_predict(k, it->tau, sp, it->Y, n, st);
+  if (F)
+    for (int j = 0; j < k; ++j) launch_copy(it->Bv + (size_t)j * n, F[j], n, st);
+  else
     launch_fill(it->Bv, 0.0, (size_t)k * n, st);
-    int rc = op_apply(pt, 1, k, -1.0, it->Y, it->Bv, st);
-    if (rc) return rc;
-    // initial guess from the history of stage solutions (newest first)
-    bool zero = true;
-    if (it->guess != GA_GUESS_ZERO && it->nhist > 0) {
-      const int nh = it->guess == GA_GUESS_PREV ? 1 : it->nhist;
-      const double* hp[16] = {nullptr};
-      for (int h = 0; h < nh; ++h)
-        for (int j = 0; j < k; ++j)
-          hp[h * 4 + j] = it->H + ((size_t)((it->head - h + 4) % 4) * k + j) * n;
-      launch_extrap(k, nh, hp, it->X, n, st);
-      if (it->guess == GA_GUESS_LEARNED && it->nhist == 4) {
-        for (int j = 0; j < k; ++j) {
-          if (!it->nets[j]) continue;
-          const double* hj[4] = {hp[j], hp[4 + j], hp[8 + j], hp[12 + j]};
-          ProfScope prof(3, st);
-          rc = gnet_guess(it->nets[j], pt, hj, it->X + (size_t)j * n, st);
-          if (rc) return rc;
-        }
+  int rc = op_apply(pt, 1, k, -1.0, it->Y, it->Bv, st);
+  if (rc) return rc;
+  if (it->cM != 0.0 && (rc = op_apply(pt, 0, k, -it->cM, it->Z, it->Bv, st))) return rc;
+  // initial guess from the history of stage solutions (newest first)
+  bool zero = true;
+  if (it->guess != GA_GUESS_ZERO && it->nhist > 0) {
+    const int nh = it->guess == GA_GUESS_PREV ? 1 : it->nhist;
+    const double* hp[16] = {nullptr};
+    for (int h = 0; h < nh; ++h)
+      for (int j = 0; j < k; ++j)
+        hp[h * 4 + j] = it->H + ((size_t)((it->head - h + 4) % 4) * k + j) * n;
+    launch_extrap(k, nh, hp, it->X, n, st);
+    if (it->guess == GA_GUESS_LEARNED && it->nhist == 4) {
+      for (int j = 0; j < k; ++j) {
+        if (!it->nets[j]) continue;
+        const double* hj[4] = {hp[j], hp[4 + j], hp[8 + j], hp[12 + j]};
+        ProfScope prof(3, st);
+        rc = gnet_guess(it->nets[j], pt, hj, it->X + (size_t)j * n, st);
+        if (rc) return rc;
       }
-      zero = false;
     }
-    rc = solve_any(pt, k, it->Bv, it->X, it->rtol, it->maxit, it->prec, zero, iters, nullptr, st);
-    if (rc) return rc;
-    if (it->guess != GA_GUESS_ZERO) {  // push the solutions into the history ring
-      it->head = (it->head + 1) % 4;
-      launch_copy(it->H + (size_t)it->head * k * n, it->X, (size_t)k * n, st);
-      it->nhist = std::min(it->nhist + 1, 4);
-    }
-    if (iters_out)
-      for (int j = 0; j < k; ++j) iters_out[(size_t)step * k + j] = iters[j];
-    launch_update(k, it->tau, cf, sp, it->X, n, st);
-    if (check_launch(0, "update")) return GA_EDEVICE;
-    it->have_prev = true;
+    zero = false;
   }
-  // finite check of the displacement
+  rc = solve_any(pt, k, it->Bv, it->X, it->rtol, it->maxit, it->prec, zero, iters, nullptr, st);
+  if (rc) return rc;
+  if (it->guess != GA_GUESS_ZERO) {  // push the solutions into the history ring
+    it->head = (it->head + 1) % 4;
+    launch_copy(it->H + (size_t)it->head * k * n, it->X, (size_t)k * n, st);
+    it->nhist = std::min(it->nhist + 1, 4);
+  }
+  launch_update(k, it->tau, cf, sp, it->X, n, st);
+  if (check_launch(0, "update")) return GA_EDEVICE;
+  it->have_prev = true;
+  return GA_OK;
+}
+
+int check_finite(ga_patch* pt, const double* u, hipStream_t st) {
   double* part = pt->red;
-  launch_dot_partial(1, state[0], state[0], n, part, st);
+  launch_dot_partial(1, u, u, pt->n_free, part, st);
   launch_sum_partials(1, part, pt->scal + NSCAL * 63, st);
   double nrm2 = 0.0;
   GA_TRY_HIP(hipMemcpyAsync(&nrm2, pt->scal + NSCAL * 63, 8, hipMemcpyDeviceToHost, st));
   GA_TRY_HIP(hipStreamSynchronize(st));
   if (!std::isfinite(nrm2)) { set_error("displacement became non-finite"); return GA_EUNSTABLE; }
   return GA_OK;
+}
+
+int step_setup(ga_integrator* it, double* const* state, StatePtrs& sp, Coefs& cf) {
+  const int k = it->k, ns = 3 * k;
+  for (int s = 0; s < ns; ++s)
+    if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+  for (int s = 0; s < 12; ++s) sp.L[s] = s < ns ? state[s] : nullptr;
+  for (int j = 0; j < 4; ++j) {
+    cf.alpha[j] = j < k ? it->alpha[j] : 1.0;
+    cf.beta[j] = j < k ? it->beta[j] : 0.0;
+    cf.gamma[j] = j < k ? it->gamma[j] : 0.0;
+  }
+  return GA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ga_step(ga_integrator* it, double* const* state, int nsteps, int* iters_out, void* stream) {
+  if (!it || !state || nsteps < 0) { set_error("bad argument"); return GA_EINVAL; }
+  StatePtrs sp;
+  Coefs cf;
+  int rc = step_setup(it, state, sp, cf);
+  if (rc) return rc;
+  hipStream_t st = S(stream);
+  int iters[16];
+  for (int step = 0; step < nsteps; ++step) {
+    if ((rc = step_once(it, sp, cf, nullptr, iters, st))) return rc;
+    if (iters_out)
+      for (int j = 0; j < it->k; ++j) iters_out[(size_t)step * it->k + j] = iters[j];
+  }
+  return check_finite(it->patch, state[0], st);
+}
+
+int ga_step_forced(ga_integrator* it, double* const* state, const double* const* forcing,
+                   int* iters_out, void* stream) {
+  if (!it || !state || !forcing) { set_error("null argument"); return GA_EINVAL; }
+  for (int j = 0; j < it->k; ++j)
+    if (!forcing[j]) { set_error("null forcing vector"); return GA_EINVAL; }
+  StatePtrs sp;
+  Coefs cf;
+  int rc = step_setup(it, state, sp, cf);
+  if (rc) return rc;
+  hipStream_t st = S(stream);
+  if ((rc = step_once(it, sp, cf, forcing, iters_out, st))) return rc;
+  return check_finite(it->patch, state[0], st);
 }
 
 }  // extern "C"

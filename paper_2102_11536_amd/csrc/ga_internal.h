@@ -125,6 +125,8 @@ struct ga_integrator {
   double* Bv = nullptr;       // [k][n_free] stage right-hand sides -K Y_j
   double* X = nullptr;        // [k][n_free] stage solutions
   double* H = nullptr;        // [4][k][n_free] ring of past stage solutions
+  double* Z = nullptr;        // [k][n_free] damping arguments (Rayleigh mass part)
+  double cM = 0.0, cK = 0.0;  // Rayleigh damping C = cM M + cK K
   int head = -1, nhist = 0;   // newest ring slot, number of valid slots
   bool have_prev = false;
   ga_gnet* nets[4] = {nullptr, nullptr, nullptr, nullptr};  // learned guess per stage (not owned)

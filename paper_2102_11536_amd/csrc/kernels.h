@@ -101,6 +101,8 @@ void launch_cg_xr(int nr, double* x, double* r, const double* p, const double* q
                   const double* scal, size_t n, hipStream_t st);
 void launch_cg_p(int nr, double* p, const double* z, const double* scal, size_t n, hipStream_t st);
 void launch_predict(int k, double tau, StatePtrs sp, double* Y, size_t n, hipStream_t st);
+void launch_predict_cz(int k, double tau, double cK, StatePtrs sp, double* Y, double* Z, size_t n,
+                       hipStream_t st);
 void launch_update(int k, double tau, Coefs c, StatePtrs sp, const double* X, size_t n,
                    hipStream_t st);
 void launch_axpby(double* out, double a, const double* x, double b, const double* y, size_t n,

@@ -276,6 +276,25 @@ __global__ void predict_k(int k, double tau, StatePtrs sp, double* __restrict__ 
   }
 }
 
+// stage arguments with Rayleigh damping C = cM M + cK K: Y_j + cK Z_j (the
+// stiffness argument of the combined K apply) and Z_j (the argument of C:
+// T_{a_j-1} for j < k, L^{N-1} for j = k), Z written only if Zout is given
+__global__ void predict_cz_k(int k, double tau, double cK, StatePtrs sp, double* __restrict__ Y,
+                             double* __restrict__ Zout, size_t n) {
+  const int ns = 3 * k;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double Lv[12];
+    for (int s = 0; s < ns; ++s) Lv[s] = sp.L[s][i];
+    for (int j = 1; j <= k; ++j) {
+      const double y = j < k ? taylor(Lv, 3 * j - 3, ns, tau) : Lv[ns - 3];
+      const double z = j < k ? taylor(Lv, 3 * j - 2, ns, tau) : Lv[ns - 2];
+      Y[(size_t)(j - 1) * n + i] = y + cK * z;
+      if (Zout) Zout[(size_t)(j - 1) * n + i] = z;
+    }
+  }
+}
+
 __global__ void update_k(int k, double tau, Coefs c, StatePtrs sp, const double* __restrict__ X,
                          size_t n) {
   const int ns = 3 * k;
@@ -445,6 +464,10 @@ void launch_cg_p(int nr, double* p, const double* z, const double* scal, size_t 
                  hipStream_t st) {
   unsigned b = nblocks(n) > 2048 ? 2048 : nblocks(n);
   hipLaunchKernelGGL(cg_p_k, dim3(b, nr), dim3(VB), 0, st, p, z, scal, n);
+}
+void launch_predict_cz(int k, double tau, double cK, StatePtrs sp, double* Y, double* Z, size_t n,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(predict_cz_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, cK, sp, Y, Z, n);
 }
 void launch_predict(int k, double tau, StatePtrs sp, double* Y, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(predict_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, sp, Y, n);

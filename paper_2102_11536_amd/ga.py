@@ -21,6 +21,7 @@ EXPORTS = ["ga_setup_patch", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "
            "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
            "ga_integrator_create", "ga_integrator_destroy", "ga_init_state", "ga_step",
            "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error", "ga_stage_solution", "ga_patch_set_pinv",
+           "ga_integrator_set_damping", "ga_stage_times", "ga_init_state_forced", "ga_step_forced",
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
@@ -68,6 +69,10 @@ def load_library(path=LIB_PATH):
     ip, fp = ctypes.POINTER(i), ctypes.POINTER(ctypes.c_float)
     lib.ga_stage_solution.argtypes = [vp, i, i, dp, vp]
     lib.ga_patch_set_pinv.argtypes = [vp, i]
+    lib.ga_integrator_set_damping.argtypes = [vp, d, d]
+    lib.ga_stage_times.argtypes = [vp, d, ctypes.POINTER(d)]
+    lib.ga_init_state_forced.argtypes = [vp, dp, dp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.ga_step_forced.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i), vp]
     lib.ga_gnet_create.argtypes = [fp, ctypes.POINTER(vp)]
     lib.ga_gnet_destroy.argtypes = [vp]
     lib.ga_gnet_set_params.argtypes = [vp, fp]
@@ -217,6 +222,38 @@ def _state_array(integ, state):
 def ga_init_state(integ, U0, V0, state):
     n = integ.patch.n_free
     _check(_lib.ga_init_state(integ.h, _ptr(U0, n), _ptr(V0, n), _state_array(integ, state), _stream()))
+
+
+def ga_integrator_set_damping(integ, cM, cK):
+    _check(_lib.ga_integrator_set_damping(integ.h, float(cM), float(cK)))
+
+
+def ga_stage_times(integ, t):
+    out = (ctypes.c_double * integ.k)()
+    _check(_lib.ga_stage_times(integ.h, float(t), out))
+    return list(out)
+
+
+def _vec_array(integ, vecs, count):
+    if len(vecs) != count:
+        raise ValueError(f"need {count} vectors")
+    return (ctypes.c_void_p * count)(*[_ptr(v, integ.patch.n_free).value for v in vecs])
+
+
+def ga_init_state_forced(integ, U0, V0, F0, state):
+    """F0: list of 3k-2 device vectors F^{(a)}(0), a = 0..3k-3, or None."""
+    n = integ.patch.n_free
+    f = None if F0 is None else _vec_array(integ, F0, 3 * integ.k - 2)
+    _check(_lib.ga_init_state_forced(integ.h, _ptr(U0, n), _ptr(V0, n), f, _state_array(integ, state),
+                                     _stream()))
+
+
+def ga_step_forced(integ, state, forcing):
+    """One step; forcing: k device vectors F^{(a_j)} at the stage times."""
+    its = (ctypes.c_int * integ.k)()
+    _check(_lib.ga_step_forced(integ.h, _state_array(integ, state), _vec_array(integ, forcing, integ.k), its,
+                               _stream()))
+    return list(its)
 
 
 def ga_step(integ, state, nsteps=1, record_iters=True):

@@ -187,3 +187,87 @@ def test_standing_wave_2d():
     Uex = U0 * np.cos(np.sqrt(2) * np.pi * T)
     d = run(2, 400) - Uex
     assert np.sqrt(d @ M @ d) < 1e-6
+
+
+# ---- damping and forcing (stage equations ho1 with C and F) ----------------
+
+def _damped_forced_exact(lam, c, A, Om, x0, v0, t):
+    """x'' + c x' + lam x = A sin(Om t), x(0) = x0, x'(0) = v0 (underdamped)."""
+    D = (lam - Om ** 2) ** 2 + (c * Om) ** 2
+    a, b = A * (lam - Om ** 2) / D, -A * c * Om / D
+    wd = np.sqrt(lam - c * c / 4)
+    C1 = x0 - b
+    C2 = (v0 - a * Om + 0.5 * c * C1) / wd
+    return a * np.sin(Om * t) + b * np.cos(Om * t) + np.exp(-0.5 * c * t) * (C1 * np.cos(wd * t) + C2 * np.sin(wd * t))
+
+
+def _damped_forced_error(k, nst, c=1.3, A=5.0, damping_args=None):
+    lam, Om, T, x0, v0, rho = (2.6 * np.pi) ** 2, 3.1, 0.73, 1.0, -0.4, 0.5
+    tau = T / nst
+    F = (lambda a, t: A * Om ** a * np.sin(Om * t + a * np.pi / 2)) if A else None
+    L = galpha.initial_state(x0, v0, k, lambda y: lam * y, lambda b: b, apply_C=lambda y: c * y, forcing=F)
+    t = 0.0
+    for _ in range(nst):
+        L = galpha.step(L, tau, k, rho, lambda y: lam * y, lambda b: b, apply_C=lambda y: c * y,
+                        forcing=F, t=t)
+        t += tau
+    return abs(L[-2] - _damped_forced_exact(lam, c, A, Om, x0, v0, T))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_damped_forced_sdof_order_2k(k):
+    # order 2k against the closed-form damped, forced oscillator; k = 3 is
+    # still slightly pre-asymptotic (rates approach 6 from above)
+    ns = (200, 400, 800) if k < 3 else (80, 160, 320)
+    e = [_damped_forced_error(k, n) for n in ns]
+    rates = [np.log2(e[i] / e[i + 1]) for i in range(len(e) - 1)]
+    assert all(2 * k - 0.35 < r < 2 * k + 0.9 for r in rates), rates
+    assert rates[-1] <= rates[0] + 0.3 or k < 3
+
+
+def test_literal_damping_argument_is_first_order(monkeypatch):
+    # C acting on L^{a_j-1}_n (the printed stage equations) instead of the
+    # predictor drops the scheme to first order: the reading is what the pin fixes
+    monkeypatch.setattr(galpha, "damping_arguments",
+                        lambda L, T, k: [L[3 * j - 4] for j in range(1, k + 1)])
+    e = [_damped_forced_error(2, n, A=0.0) for n in (200, 400)]
+    assert abs(np.log2(e[0] / e[1]) - 1.0) < 0.2
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_rayleigh_damped_forced_pde_reduces_to_sdof(k):
+    # U0 an eigenvector v of (K, M), C = cM M + cK K, F = g(t) M v: the PDE run is
+    # the scalar run with c = cM + cK lambda and force g(t), times v
+    n, p, rho, cM, cK = 6, 2, 0.5, 0.7, 2e-3
+    _, M, K = _wave2d(n, p)
+    lam, V = sla.eigh(K, M)
+    v, l3 = V[:, 3], lam[3]
+    Mv = M @ v
+    g = lambda a, t: 3.0 * 2.0 ** a * np.cos(2.0 * t + a * np.pi / 2)
+    tau = 0.02
+    ch = solvers.CholeskySolver(M)
+    C = lambda y: cM * (M @ y) + cK * (K @ y)
+    L = galpha.initial_state(v, 0.5 * v, k, lambda y: K @ y, ch.solve, apply_C=C,
+                             forcing=lambda a, t: g(a, t) * Mv)
+    s = galpha.initial_state(1.0, 0.5, k, lambda y: l3 * y, lambda b: b,
+                             apply_C=lambda y: (cM + cK * l3) * y, forcing=g)
+    t = 0.0
+    for _ in range(25):
+        L = galpha.step(L, tau, k, rho, lambda y: K @ y, ch.solve, apply_C=C,
+                        forcing=lambda a, tt: g(a, tt) * Mv, t=t)
+        s = galpha.step(s, tau, k, rho, lambda y: l3 * y, lambda b: b,
+                        apply_C=lambda y: (cM + cK * l3) * y, forcing=g, t=t)
+        t += tau
+    for a in range(-2, 3 * k - 2):
+        assert np.allclose(L[a], s[a] * v, rtol=1e-9, atol=1e-9 * np.abs(s[a]) + 1e-12)
+
+
+def test_no_damping_no_forcing_is_the_plain_step():
+    rng = np.random.default_rng(0)
+    L = {a: rng.standard_normal(5) for a in range(-2, 4)}
+    A = np.diag(rng.uniform(1, 2, 5))
+    a1 = galpha.step(L, 0.01, 2, 0.5, lambda y: A @ y, lambda b: b)
+    a2 = galpha.step(L, 0.01, 2, 0.5, lambda y: A @ y, lambda b: b, apply_C=lambda y: 0 * y,
+                     forcing=lambda a, t: np.zeros(5), t=3.0)
+    for a in a1:
+        assert np.array_equal(a1[a], a2[a])
