@@ -30,12 +30,26 @@ void basis_on_element(int n, int p, int e, double x, double* val, double* der);
 // Element tile of the sum-factorised operator kernels: TE elements per
 // direction, quadrature factors stored tile by tile.
 // 3-D: elements per xy-column edge of the stiffness and the mass kernels
-// (at most 1024 threads = (TE*(p+1))^2 per workgroup)
-constexpr int te3_stiff(int p) { return 4; }
+// (at most 1024 threads = (TE*(p+1))^2 per workgroup); measured on MI355X:
+// 4 x 4 columns for p <= 3, 3 x 3 for p = 4 (225 threads instead of 400)
+#ifndef GA_TES2
+#define GA_TES2 4
+#endif
+#ifndef GA_TES4
+#define GA_TES4 3
+#endif
+constexpr int te3_stiff(int p) { return p == 2 ? GA_TES2 : (p == 4 ? GA_TES4 : 4); }
 #ifndef GA_TE3_MASS
 #define GA_TE3_MASS 4
 #endif
-constexpr int te3_mass(int p) { return (p + 1) * GA_TE3_MASS > 32 ? 32 / (p + 1) : GA_TE3_MASS; }
+#ifndef GA_TEM2
+#define GA_TEM2 GA_TE3_MASS
+#endif
+#ifndef GA_TEM4
+#define GA_TEM4 3
+#endif
+constexpr int te3_mass_raw(int p) { return p == 2 ? GA_TEM2 : (p == 4 ? GA_TEM4 : GA_TE3_MASS); }
+constexpr int te3_mass(int p) { return (p + 1) * te3_mass_raw(p) > 32 ? 32 / (p + 1) : te3_mass_raw(p); }
 constexpr int TE2 = 8;   // 2-D tile: 8 x 8 elements
 
 void set_error(const std::string& msg);

@@ -75,9 +75,15 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned nwg) {
 #ifndef GA_RING_K
 #define GA_RING_K 4
 #endif
-#ifndef GA_RING_M
-#define GA_RING_M 16
+// mass ring by degree and right-hand-side count (measured at 128^3 p = 2, 3 and
+// 96^3 p = 4); GA_RING_M overrides it for every case
+constexpr int mass_ring(int P, int NR) {
+#ifdef GA_RING_M
+  return GA_RING_M;
+#else
+  return P == 3 ? 16 : (P == 2 ? (NR == 1 ? 4 : 16) : (NR == 1 ? 16 : 4));
 #endif
+}
 
 // MODE: 0 mass, 1 stiffness, 2 diag(M) (tables hold squared values, x unused)
 // One workgroup's share: logical tile `lid` = (xy column, z range) of one patch.
@@ -395,7 +401,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   }
 
   // z sweep over Gauss layers with a ring of D prefetched factor planes
-  constexpr int D = (MODE == 1) ? GA_RING_K : GA_RING_M;
+  constexpr int D = (MODE == 1) ? GA_RING_K : mass_ring(P, NR);
   const int q0 = ez0 * Q, q1 = ez1 * Q;
   S gq[D][NC];
 #pragma unroll
