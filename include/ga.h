@@ -34,6 +34,7 @@ typedef struct ga_patch ga_patch;
 typedef struct ga_integrator ga_integrator;
 typedef struct ga_gnet ga_gnet;
 typedef struct ga_batch ga_batch;
+typedef struct ga_mp ga_mp;
 
 enum {
   GA_OK = 0,
@@ -77,6 +78,18 @@ enum { GA_GUESS_ZERO = 0, GA_GUESS_PREV = 1, GA_GUESS_EXTRAP = 2, GA_GUESS_LEARN
  */
 int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host,
                    void* stream, ga_patch** out);
+/*
+ * ga_setup_patch_ex -- as ga_setup_patch with a choice of the faces that carry
+ * the homogeneous Dirichlet data (3-D only): bit 2a of dirichlet_faces is the
+ * face xi_a = 0, bit 2a+1 the face xi_a = 1 (0x3F = all six, ga_setup_patch).
+ * Coefficients on the other faces stay free, as on an interface of a glued
+ * multi-patch domain (Sec. 5.5): along axis a the free coefficients are
+ * lo_a .. m_a - 1 - hi_a with lo_a, hi_a the two face bits, and every vector
+ * of the patch holds them in co-lex order.  M-hat, its factors and the scaling
+ * s are those of that index range.
+ */
+int ga_setup_patch_ex(int dim, const int* n_el, int p, const double* ctrl_host,
+                      unsigned dirichlet_faces, void* stream, ga_patch** out);
 int ga_destroy_patch(ga_patch* patch);
 
 /* Sizes: free coefficients, quadrature points, free coefficients per axis. */
@@ -317,6 +330,38 @@ int ga_batch_init_state(ga_batch* batch, const double* U0_dev, const double* V0_
  */
 int ga_batch_step(ga_batch* batch, double* const* state_dev, int nsteps, int use_graph,
                   int* iters_out, void* stream);
+
+/*
+ * Glued multi-patch domain (Sec. 5.5) with the additive Schwarz mass
+ * preconditioner P_ad^{-1} = sum_r R^(r)T (P^(r))^{-1} R^(r) (Sec. 5.7), P^(r)
+ * the preconditioner of Sec. 5.4 on patch r.  The domain is a brick: the unit
+ * cube's parameter box split into P[0] x P[1] x P[2] boxes, patch r = box
+ * (r % P0, (r / P0) % P1, r / (P0 P1)), each with n_el elements per direction
+ * and degree p (2..4), glued with C^0 continuity: along axis a, coefficient i
+ * (0..n_el+p-1) of box b_a is global coefficient b_a (n_el+p-1) + i, so
+ * neighbouring boxes share the coefficients of their common face (their
+ * control points must match there).  The outer boundary carries homogeneous
+ * Dirichlet data; the unknowns are the interior global coefficients,
+ * mfg_a = P_a (n_el+p-1) - 1 per axis, co-lex (x fastest), N = prod mfg_a.
+ *   ctrl_host[r]  control points of patch r, as for ga_setup_patch.
+ * The library owns the patches it builds.  Time stepping: the order-2k scheme
+ * of ga_step on the global unknowns (C = F = 0), PCG with P_ad, zero guess.
+ */
+int ga_mp_create(const int* P, int n_el, int p, const double* const* ctrl_host, int k, double rho,
+                 double tau, double rtol, int maxit, void* stream, ga_mp** out);
+int ga_mp_destroy(ga_mp* mp);
+/* n_global: N; mfg[3]: unknowns per axis; n_local: sum of the patches' free
+ * coefficients (interface coefficients counted once per patch). */
+int ga_mp_info(const ga_mp* mp, long long* n_global, int* mfg, long long* n_local);
+/* y = M x, K x ('M', 'K') or P_ad^{-1} x ('P') on global vectors, nrhs <= k. */
+int ga_mp_apply(ga_mp* mp, char which, int nrhs, const double* x_dev, double* y_dev, void* stream);
+/* PCG with P_ad for M x_j = b_j, zero guess, the integrator's rtol and maxit. */
+int ga_mp_mass_solve(ga_mp* mp, int nrhs, const double* b_dev, double* x_dev, int* iters_out,
+                     void* stream);
+int ga_mp_init_state(ga_mp* mp, const double* U0_dev, const double* V0_dev,
+                     double* const* state_dev, void* stream);
+/* iters_out: host [nsteps][k] or NULL. */
+int ga_mp_step(ga_mp* mp, double* const* state_dev, int nsteps, int* iters_out, void* stream);
 
 /*
  * Launch timing (instrumentation, not part of the method): with profiling on,

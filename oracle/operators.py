@@ -12,7 +12,9 @@ Definitions followed:
                       = int gradhat B_i^T (|det J| J^{-1} J^{-T}) gradhat B_j d xi.
 * Homogeneous Dirichlet data (second remark of Sec. 2): the unknowns are the
   coefficients of basis functions that vanish on the boundary, i.e. all
-  indices 1 <= i_a <= m_a - 2 (0-based) in every direction.
+  indices 1 <= i_a <= m_a - 2 (0-based) in every direction.  A patch of a
+  glued multi-patch domain (Sec. 5.5) keeps the coefficients of its interface
+  faces: there the range starts at 0 or ends at m_a - 1.
 * Assumption 3 (det DF >= delta > 0) is checked at every quadrature point.
 
 The sums over quadrature points are written as sparse products
@@ -26,16 +28,23 @@ from . import bspline
 
 class Space:
     """Spline space of degree p on n_a uniform elements per direction of the
-    unit square/cube, with the 1-D tables of ``bspline.tables_1d``."""
+    unit square/cube, with the 1-D tables of ``bspline.tables_1d``.
 
-    def __init__(self, n, p, dim=None):
+    ``dirichlet_faces``: bit 2a marks the face xi_a = 0, bit 2a+1 the face
+    xi_a = 1 as carrying the homogeneous Dirichlet data (default: all faces);
+    along axis a the free coefficients are lo[a] .. m[a]-1-hi[a]."""
+
+    def __init__(self, n, p, dim=None, dirichlet_faces=None):
         if np.isscalar(n):
             n = (int(n),) * (dim if dim is not None else 3)
         self.n = tuple(int(v) for v in n)  # (n_x, n_y[, n_z])
         self.dim = len(self.n)
         self.p = int(p)
         self.m = tuple(v + self.p for v in self.n)
-        self.mf = tuple(v - 2 for v in self.m)
+        mask = (1 << (2 * self.dim)) - 1 if dirichlet_faces is None else int(dirichlet_faces)
+        self.lo = tuple((mask >> (2 * a)) & 1 for a in range(self.dim))
+        self.hi = tuple((mask >> (2 * a + 1)) & 1 for a in range(self.dim))
+        self.mf = tuple(self.m[a] - self.lo[a] - self.hi[a] for a in range(self.dim))
         self.tabs = [bspline.tables_1d(v, self.p) for v in self.n]  # per axis x, y, z
 
     @property
@@ -50,7 +59,7 @@ class Space:
         """Flat co-lex indices (full numbering) of the free coefficients, in
         co-lex order of the free grid."""
         idx = np.arange(self.n_dof).reshape(self.m[::-1])
-        sl = tuple(slice(1, v - 1) for v in self.m[::-1])
+        sl = tuple(slice(self.lo[a], self.m[a] - self.hi[a]) for a in reversed(range(self.dim)))
         return idx[sl].ravel()
 
     def to_full(self, x_free):

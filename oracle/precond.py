@@ -20,8 +20,10 @@ class KronPreconditioner:
     def __init__(self, space, diagM):
         """``diagM``: diag(M) on the free coefficients (co-lex)."""
         self.space = space
-        self.Mh = [parametric_mass_1d(space.n[a], space.p)[1:-1, 1:-1]
-                   for a in range(space.dim)]
+        self.Mh = []
+        for a in range(space.dim):
+            r = slice(space.lo[a], space.m[a] - space.hi[a])
+            self.Mh.append(parametric_mass_1d(space.n[a], space.p)[r, r])
         dh = np.diag(self.Mh[0]).copy()
         for a in range(1, space.dim):
             dh = np.kron(np.diag(self.Mh[a]), dh)

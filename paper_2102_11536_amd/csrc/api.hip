@@ -476,14 +476,29 @@ double ga_stability_limit(double rho) {
 
 int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, void* stream,
                    ga_patch** out) {
+  return ga_setup_patch_ex(dim, n_el, p, ctrl_host, dim == 3 ? 0x3Fu : 0xFu, stream, out);
+}
+
+int ga_setup_patch_ex(int dim, const int* n_el, int p, const double* ctrl_host,
+                      unsigned dirichlet_faces, void* stream, ga_patch** out) {
   if (!out || !n_el || !ctrl_host) { set_error("null argument"); return GA_EINVAL; }
   *out = nullptr;
   if (dim != 2 && dim != 3) { set_error("dim must be 2 or 3"); return GA_EINVAL; }
   if (p < 1 || p > 4) { set_error("p must be in 1..4"); return GA_EINVAL; }
+  if (dim == 2 && dirichlet_faces != 0xFu) {
+    set_error("2-D patches carry Dirichlet data on all four sides");
+    return GA_EINVAL;
+  }
+  if (dirichlet_faces >> (2 * dim)) { set_error("bad face mask"); return GA_EINVAL; }
   for (int a = 0; a < dim; ++a)
     if (n_el[a] < 1 || n_el[a] > 4096) { set_error("n_el out of range"); return GA_EINVAL; }
-  for (int a = 0; a < dim; ++a)
-    if (n_el[a] + p - 2 < 1) { set_error("no free coefficients"); return GA_EINVAL; }
+  int lo[3] = {1, 1, 1}, mfa[3] = {1, 1, 1};
+  for (int a = 0; a < dim; ++a) {
+    lo[a] = (dirichlet_faces >> (2 * a)) & 1u ? 1 : 0;
+    const int hi = n_el[a] + p - ((dirichlet_faces >> (2 * a + 1)) & 1u ? 1 : 0);
+    mfa[a] = hi - lo[a];
+    if (mfa[a] < 1) { set_error("no free coefficients"); return GA_EINVAL; }
+  }
   hipStream_t st = S(stream);
   ga_patch* pt = new ga_patch();
   pt->dim = dim;
@@ -494,7 +509,8 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, voi
   for (int a = 0; a < dim; ++a) {
     pt->n[a] = n_el[a];
     pt->m[a] = n_el[a] + p;
-    pt->mf[a] = n_el[a] + p - 2;
+    pt->mf[a] = mfa[a];
+    pt->lo[a] = lo[a];
     ndof *= pt->m[a];
     pt->n_free *= pt->mf[a];
   }
@@ -529,7 +545,7 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host, voi
   // univariate tables, padded to whole tiles with zeros
   std::vector<double*> wdev(3, nullptr);
   for (int a = 0; a < dim; ++a) {
-    pt->ax[a] = build_axis(n_el[a], p);
+    pt->ax[a] = build_axis(n_el[a], p, pt->lo[a], pt->mf[a]);
     const Axis1D& ax = pt->ax[a];
     const size_t per_el = (size_t)ax.q * (p + 1);
     const size_t npad = (size_t)npad_el[a];

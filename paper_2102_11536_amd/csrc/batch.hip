@@ -518,3 +518,272 @@ int ga_batch_step(ga_batch* b, double* const* state, int nsteps, int use_graph, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Glued (C^0) multi-patch domain (Sec. 5.5) with the additive Schwarz mass
+// preconditioner (Sec. 5.7): a brick of P_x x P_y x P_z patches, each n elements
+// and degree p.  The patch work runs through a batch over the patches' local
+// free coefficients (interface faces free, outer faces Dirichlet); the PCG and
+// the time stepping run on the global unknowns:
+//   Op x = sum_r G^(r)T Op^(r) G^(r) x          (gather, batched applies, scatter-add)
+//   P_ad^{-1} r = sum_r R^(r)T (P^(r))^{-1} R^(r) r
+// with G^(r) = R^(r) the map from patch r's free coefficients to global indices.
+
+struct ga_mp {
+  int P[3] = {1, 1, 1}, n = 0, p = 0, k = 1, maxit = 200;
+  double tau = 0.0, rtol = 1e-10;
+  double alpha[4], beta[4], gamma[4];
+  std::vector<ga_patch*> pts;      // owned
+  ga_batch* b = nullptr;           // owned
+  long long Ng = 0, Nl = 0;
+  int mfg[3] = {1, 1, 1};
+  int* map = nullptr;              // [Nl] local free index -> global unknown
+  double *Y = nullptr, *Bv = nullptr, *X = nullptr, *gw = nullptr;  // global vectors
+  double *red = nullptr, *scal = nullptr, *host_scal = nullptr;
+};
+
+namespace {
+
+// y += alpha Op x on global vectors (mode 0 mass, 1 stiffness), nr right-hand sides
+int mp_op(ga_mp* m, int mode, int nr, double alpha, const double* x, double* y, hipStream_t st) {
+  Bufs w = bufs(m->b);
+  launch_gather(nr, x, m->Ng, m->map, m->Nl, w.r, st);
+  launch_fill(w.z, 0.0, (size_t)nr * m->Nl, st);
+  int rc = op_batch(m->b, mode, nr, 1.0, w.r, w.z, st);
+  if (rc) return rc;
+  launch_scatter_add(nr, w.z, m->Nl, m->map, alpha, y, m->Ng, st);
+  return check_launch(0, "multi-patch operator");
+}
+
+// z = P_ad^{-1} r
+int mp_pinv(ga_mp* m, int nr, const double* r, double* z, hipStream_t st) {
+  Bufs w = bufs(m->b);
+  launch_gather(nr, r, m->Ng, m->map, m->Nl, w.r, st);
+  int rc = pinv_batch(m->b, nr, w.r, w.z, w.t0, w.t1, st);
+  if (rc) return rc;
+  launch_fill(z, 0.0, (size_t)nr * m->Ng, st);
+  launch_scatter_add(nr, w.z, m->Nl, m->map, 1.0, z, m->Ng, st);
+  return check_launch(0, "additive Schwarz preconditioner");
+}
+
+// PCG with P_ad for nr systems of Ng unknowns, zero initial guess (stopping rule as
+// for one patch: preconditioned residual relative to that of b)
+int mp_solve(ga_mp* m, int nr, const double* rhs, double* x, int* iters_out, hipStream_t st) {
+  const size_t n = m->Ng, tot = (size_t)nr * n;
+  double* r = m->gw;
+  double* z = r + (size_t)m->k * n;
+  double* pv = z + (size_t)m->k * n;
+  double* q = pv + (size_t)m->k * n;
+  launch_fill(x, 0.0, tot, st);
+  launch_copy(r, rhs, tot, st);
+  int rc = mp_pinv(m, nr, r, z, st);
+  if (rc) return rc;
+  launch_dot_partial(nr, r, z, n, m->red, st);
+  launch_cg_start(nr, m->red, nullptr, m->scal, m->rtol * m->rtol, st);
+  launch_copy(pv, z, tot, st);
+  for (int it = 0;; ++it) {
+    GA_TRY_HIP(hipMemcpyAsync(m->host_scal, m->scal, sizeof(double) * NSCAL * nr,
+                              hipMemcpyDeviceToHost, st));
+    GA_TRY_HIP(hipStreamSynchronize(st));
+    bool any = false;
+    for (int s = 0; s < nr; ++s) any |= m->host_scal[s * NSCAL + S_ACTIVE] != 0.0;
+    if (!any || it >= m->maxit) break;
+    launch_fill(q, 0.0, tot, st);
+    if ((rc = mp_op(m, 0, nr, 1.0, pv, q, st))) return rc;
+    launch_dot_partial(nr, pv, q, n, m->red, st);
+    launch_cg_alpha(nr, m->red, m->scal, st);
+    launch_cg_xr(nr, x, r, pv, q, m->scal, n, st);
+    if ((rc = mp_pinv(m, nr, r, z, st))) return rc;
+    launch_dot_partial(nr, r, z, n, m->red, st);
+    launch_cg_beta(nr, m->red, m->scal, st);
+    launch_cg_p(nr, pv, z, m->scal, n, st);
+    if (check_launch(0, "multi-patch pcg")) return GA_EDEVICE;
+  }
+  bool ok = true;
+  for (int s = 0; s < nr; ++s) {
+    const double* sc = m->host_scal + s * NSCAL;
+    if (iters_out) iters_out[s] = (int)sc[S_ITERS];
+    if (sc[S_ACTIVE] != 0.0 || !std::isfinite(sc[S_RZ])) ok = false;
+  }
+  if (!ok) { set_error("multi-patch PCG did not converge within maxit"); return GA_ENOCONV; }
+  return GA_OK;
+}
+
+void free_mp(ga_mp* m) {
+  if (m->b) ga_batch_destroy(m->b);
+  for (ga_patch* pt : m->pts)
+    if (pt) ga_destroy_patch(pt);
+  for (void* q : {(void*)m->map, (void*)m->Y, (void*)m->Bv, (void*)m->X, (void*)m->gw,
+                  (void*)m->red, (void*)m->scal})
+    if (q) hipFree(q);
+  if (m->host_scal) hipHostFree(m->host_scal);
+  delete m;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ga_mp_create(const int* P, int n_el, int p, const double* const* ctrl_host, int k, double rho,
+                 double tau, double rtol, int maxit, void* stream, ga_mp** out) {
+  if (!P || !ctrl_host || !out) { set_error("null argument"); return GA_EINVAL; }
+  *out = nullptr;
+  const int R = P[0] * P[1] * P[2];
+  if (P[0] < 1 || P[1] < 1 || P[2] < 1 || R > 64) { set_error("brick must have 1..64 patches"); return GA_EINVAL; }
+  if (p < 2 || p > 4 || n_el < 1) { set_error("need p in 2..4 and n_el >= 1"); return GA_EINVAL; }
+  if (k < 1 || k > 4 || !(tau > 0.0) || !(rtol > 0.0) || maxit < 1 || !(rho >= 0.0 && rho < 1.0)) {
+    set_error("bad k/rho/tau/rtol/maxit");
+    return GA_EINVAL;
+  }
+  for (int r = 0; r < R; ++r)
+    if (!ctrl_host[r]) { set_error("null control points"); return GA_EINVAL; }
+  ga_mp* m = new ga_mp();
+  for (int a = 0; a < 3; ++a) m->P[a] = P[a];
+  m->n = n_el;
+  m->p = p;
+  m->k = k;
+  m->tau = tau;
+  m->rtol = rtol;
+  m->maxit = maxit;
+  for (int j = 0; j < k; ++j) {
+    if (j < k - 1) block_j_params(rho, m->alpha[j], m->beta[j], m->gamma[j]);
+    else block_k_params(rho, m->alpha[j], m->beta[j], m->gamma[j]);
+  }
+  const int mm = n_el + p;                       // coefficients per patch and axis
+  long long Ng = 1;
+  for (int a = 0; a < 3; ++a) {
+    m->mfg[a] = P[a] * (mm - 1) - 1;             // global unknowns per axis
+    Ng *= m->mfg[a];
+  }
+  m->Ng = Ng;
+  int rc = GA_OK;
+  std::vector<int> map;
+  const int nn[3] = {n_el, n_el, n_el};
+  for (int r = 0; r < R; ++r) {
+    const int b[3] = {r % P[0], (r / P[0]) % P[1], r / (P[0] * P[1])};
+    unsigned faces = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (b[a] == 0) faces |= 1u << (2 * a);
+      if (b[a] == P[a] - 1) faces |= 1u << (2 * a + 1);
+    }
+    ga_patch* pt = nullptr;
+    if ((rc = ga_setup_patch_ex(3, nn, p, ctrl_host[r], faces, stream, &pt))) { free_mp(m); return rc; }
+    m->pts.push_back(pt);
+    // G^(r): local free (co-lex) -> global unknown: g_a = b_a (m-1) + i_a - 1
+    for (int iz = 0; iz < pt->mf[2]; ++iz)
+      for (int iy = 0; iy < pt->mf[1]; ++iy)
+        for (int ix = 0; ix < pt->mf[0]; ++ix) {
+          const long long gx = (long long)b[0] * (mm - 1) + pt->lo[0] + ix - 1;
+          const long long gy = (long long)b[1] * (mm - 1) + pt->lo[1] + iy - 1;
+          const long long gz = (long long)b[2] * (mm - 1) + pt->lo[2] + iz - 1;
+          map.push_back((int)(gx + (long long)m->mfg[0] * (gy + (long long)m->mfg[1] * gz)));
+        }
+  }
+  if (Ng > (1LL << 31) - 1) { set_error("too many unknowns"); free_mp(m); return GA_EINVAL; }
+  m->Nl = (long long)map.size();
+  if ((rc = ga_batch_create(R, m->pts.data(), k, rho, tau, rtol, maxit, &m->b))) { free_mp(m); return rc; }
+  const size_t kn = (size_t)k * Ng;
+  if ((rc = dalloc((void**)&m->map, map.size() * sizeof(int))) || (rc = dalloc((void**)&m->Y, kn * 8)) ||
+      (rc = dalloc((void**)&m->Bv, kn * 8)) || (rc = dalloc((void**)&m->X, kn * 8)) ||
+      (rc = dalloc((void**)&m->gw, 4 * kn * 8)) ||
+      (rc = dalloc((void**)&m->red, (size_t)k * RED_BLOCKS * 8)) ||
+      (rc = dalloc((void**)&m->scal, (size_t)k * NSCAL * 8))) {
+    free_mp(m);
+    return rc;
+  }
+  if (hipHostMalloc((void**)&m->host_scal, (size_t)k * NSCAL * 8, hipHostMallocDefault) != hipSuccess) {
+    set_error("pinned host allocation failed");
+    free_mp(m);
+    return GA_ENOMEM;
+  }
+  if (hipMemcpy(m->map, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("map upload failed");
+    free_mp(m);
+    return GA_EDEVICE;
+  }
+  *out = m;
+  return GA_OK;
+}
+
+int ga_mp_destroy(ga_mp* m) {
+  if (!m) return GA_OK;
+  hipDeviceSynchronize();
+  free_mp(m);
+  return GA_OK;
+}
+
+int ga_mp_info(const ga_mp* m, long long* n_global, int* mfg, long long* n_local) {
+  if (!m) { set_error("null multi-patch domain"); return GA_EINVAL; }
+  if (n_global) *n_global = m->Ng;
+  if (mfg) for (int a = 0; a < 3; ++a) mfg[a] = m->mfg[a];
+  if (n_local) *n_local = m->Nl;
+  return GA_OK;
+}
+
+int ga_mp_apply(ga_mp* m, char which, int nrhs, const double* x, double* y, void* stream) {
+  if (!m || !x || !y) { set_error("null argument"); return GA_EINVAL; }
+  if (nrhs < 1 || nrhs > m->k) { set_error("nrhs must be in 1..k"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  if (which == 'P') return mp_pinv(m, nrhs, x, y, st);
+  if (which != 'M' && which != 'K') { set_error("which must be 'M', 'K' or 'P'"); return GA_EINVAL; }
+  launch_fill(y, 0.0, (size_t)nrhs * m->Ng, st);
+  return mp_op(m, which == 'K' ? 1 : 0, nrhs, 1.0, x, y, st);
+}
+
+int ga_mp_mass_solve(ga_mp* m, int nrhs, const double* rhs, double* x, int* iters_out,
+                     void* stream) {
+  if (!m || !rhs || !x) { set_error("null argument"); return GA_EINVAL; }
+  if (nrhs < 1 || nrhs > m->k) { set_error("nrhs must be in 1..k"); return GA_EINVAL; }
+  return mp_solve(m, nrhs, rhs, x, iters_out, S(stream));
+}
+
+int ga_mp_init_state(ga_mp* m, const double* U0, const double* V0, double* const* state,
+                     void* stream) {
+  if (!m || !U0 || !V0 || !state) { set_error("null argument"); return GA_EINVAL; }
+  for (int s = 0; s < 3 * m->k; ++s)
+    if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  const size_t n = m->Ng;
+  launch_copy(state[0], U0, n, st);
+  launch_copy(state[1], V0, n, st);
+  for (int a = 0; a <= 3 * m->k - 3; ++a) {
+    launch_fill(m->Bv, 0.0, n, st);
+    int rc = mp_op(m, 1, 1, -1.0, state[a], m->Bv, st);
+    if (rc) return rc;
+    if ((rc = mp_solve(m, 1, m->Bv, state[a + 2], nullptr, st))) return rc;
+  }
+  return GA_OK;
+}
+
+int ga_mp_step(ga_mp* m, double* const* state, int nsteps, int* iters_out, void* stream) {
+  if (!m || !state || nsteps < 0) { set_error("bad argument"); return GA_EINVAL; }
+  const int k = m->k, ns = 3 * k;
+  for (int s = 0; s < ns; ++s)
+    if (!state[s]) { set_error("null state vector"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  const size_t n = m->Ng;
+  StatePtrs sp;
+  for (int s = 0; s < 12; ++s) sp.L[s] = s < ns ? state[s] : nullptr;
+  Coefs cf;
+  for (int j = 0; j < 4; ++j) {
+    cf.alpha[j] = j < k ? m->alpha[j] : 1.0;
+    cf.beta[j] = j < k ? m->beta[j] : 0.0;
+    cf.gamma[j] = j < k ? m->gamma[j] : 0.0;
+  }
+  int its[4];
+  for (int step = 0; step < nsteps; ++step) {
+    launch_predict(k, m->tau, sp, m->Y, n, st);
+    launch_fill(m->Bv, 0.0, (size_t)k * n, st);
+    int rc = mp_op(m, 1, k, -1.0, m->Y, m->Bv, st);
+    if (rc) return rc;
+    if ((rc = mp_solve(m, k, m->Bv, m->X, its, st))) return rc;
+    if (iters_out)
+      for (int j = 0; j < k; ++j) iters_out[(size_t)step * k + j] = its[j];
+    launch_update(k, m->tau, cf, sp, m->X, n, st);
+    if (check_launch(0, "multi-patch update")) return GA_EDEVICE;
+  }
+  GA_TRY_HIP(hipStreamSynchronize(st));
+  return GA_OK;
+}
+
+}  // extern "C"

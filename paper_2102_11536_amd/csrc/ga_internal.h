@@ -13,7 +13,7 @@ namespace ga {
 
 // Univariate data of one tensor axis.
 struct Axis1D {
-  int n = 0, p = 0, q = 0, m = 0, mf = 0;
+  int n = 0, p = 0, q = 0, m = 0, mf = 0, lo = 1;
   std::vector<double> B, D;   // [n][q][p+1]: values / derivatives of basis e+r at Gauss point j of element e
   std::vector<double> w;      // [n][q]: Gauss weights (element length included)
   std::vector<double> dhat;   // [mf]: diagonal of the univariate parametric mass (free part)
@@ -23,7 +23,9 @@ struct Axis1D {
   std::vector<double> chol;
 };
 
-Axis1D build_axis(int n, int p);
+// free coefficients lo .. lo+mf_free-1 of the n+p along the axis (lo = 1, mf_free =
+// n+p-2 when both ends carry homogeneous Dirichlet data)
+Axis1D build_axis(int n, int p, int lo, int mf_free);
 void gauss_legendre01(int nq, std::vector<double>& t, std::vector<double>& w);
 void basis_on_element(int n, int p, int e, double x, double* val, double* der);
 
@@ -96,6 +98,7 @@ int gnet_guess(ga_gnet* net, ga_patch* pt, const double* const* h, double* X, hi
 struct ga_patch {
   int dim = 0, p = 0;
   int n[3] = {1, 1, 1}, m[3] = {1, 1, 1}, mf[3] = {1, 1, 1};
+  int lo[3] = {1, 1, 1};          // first free coefficient per axis (0: that face is free)
   int nt[3] = {1, 1, 1};          // element tiles per direction (2-D kernels)
   int ntk[2] = {1, 1}, ntm[2] = {1, 1};  // 3-D xy columns: stiffness and mass layouts
   int ze = 0;                     // element layers per workgroup along z (0: automatic)

@@ -17,7 +17,7 @@ struct Coefs { double alpha[4], beta[4], gamma[4]; };
 
 // element/tile geometry of one 3-D patch as the operator kernels see it
 struct Geo3 {
-  int n[3], m[3], mf[3], nt[2];
+  int n[3], m[3], mf[3], nt[2], lo[3];
 };
 
 // one patch of a multi-patch operator launch (all patches of one degree)
@@ -121,6 +121,11 @@ void launch_cg_xr_f32(int nr, float* x, float* r, const float* p, const float* q
 void launch_cg_p_f32(int nr, float* p, const float* z, const double* scal, size_t n,
                      hipStream_t st);
 void launch_sum_partials(int nr, const double* part, double* out, hipStream_t st);
+// glued multi-patch: xl[j][i] = xg[j][map[i]]; yg[j][map[i]] += alpha yl[j][i] (atomic)
+void launch_gather(int nr, const double* xg, long long Ng, const int* map, long long Nl, double* xl,
+                   hipStream_t st);
+void launch_scatter_add(int nr, const double* yl, long long Nl, const int* map, double alpha,
+                        double* yg, long long Ng, hipStream_t st);
 // segment-aware CG kernels: system s = entries seg[2s] .. seg[2s] + seg[2s+1] of each vector
 void launch_dot_partial_seg(int ns, const double* a, const double* b, const long long* seg,
                             double* part, hipStream_t st);

@@ -48,7 +48,7 @@ struct Tile3 {
 
 // index of a full-grid coefficient (i0,i1,i2) in the free vector, or -1
 __device__ __forceinline__ long long free_index3(const Geo3& g, int i0, int i1, int i2) {
-  int f0 = i0 - 1, f1 = i1 - 1, f2 = i2 - 1;
+  int f0 = i0 - g.lo[0], f1 = i1 - g.lo[1], f2 = i2 - g.lo[2];
   if (f0 < 0 || f1 < 0 || f2 < 0 || f0 >= g.mf[0] || f1 >= g.mf[1] || f2 >= g.mf[2]) return -1;
   return (long long)f0 + (long long)g.mf[0] * (f1 + (long long)g.mf[1] * f2);
 }
@@ -607,7 +607,7 @@ static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const S* x, S* y,
                          const S* fac, hipStream_t st) {
   constexpr int TK = te3_stiff(P), TM = te3_mass(P);
   Geo3 g;
-  for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; }
+  for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; g.lo[a] = pt->lo[a]; }
   const int* nt = mode == 1 ? pt->ntk : pt->ntm;
   g.nt[0] = nt[0];
   g.nt[1] = nt[1];
@@ -676,7 +676,7 @@ OpGroupEntry op3d_group_entry(int mode, const ga_patch* pt, int ze, long long of
                               bool f32) {
   OpGroupEntry d;
   for (int a = 0; a < 3; ++a) {
-    d.g.n[a] = pt->n[a]; d.g.m[a] = pt->m[a]; d.g.mf[a] = pt->mf[a];
+    d.g.n[a] = pt->n[a]; d.g.m[a] = pt->m[a]; d.g.mf[a] = pt->mf[a]; d.g.lo[a] = pt->lo[a];
     d.tB[a] = pt->tabB[a];
     d.tD[a] = pt->tabD[a];
   }
@@ -732,7 +732,7 @@ template int launch_op3d_group<float>(int, int, int, const OpGroupEntry*, int, c
 int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
                  hipStream_t st) {
   Geo3 g;
-  for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; }
+  for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; g.lo[a] = pt->lo[a]; }
   g.nt[0] = pt->ntk[0];
   g.nt[1] = pt->ntk[1];
   dim3 grid((unsigned)(pt->ntk[0] * pt->ntk[1]), (unsigned)pt->n[2]);

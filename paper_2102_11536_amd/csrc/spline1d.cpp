@@ -91,13 +91,14 @@ void basis_on_element(int n, int p, int e, double x, double* val, double* der) {
   }
 }
 
-Axis1D build_axis(int n, int p) {
+Axis1D build_axis(int n, int p, int lo, int mf_free) {
   Axis1D ax;
   ax.n = n;
   ax.p = p;
   ax.q = p + 1;
   ax.m = n + p;
-  ax.mf = n + p - 2;
+  ax.lo = lo;
+  ax.mf = mf_free;
   std::vector<double> t, w;
   gauss_legendre01(ax.q, t, w);
   const int P1 = p + 1;
@@ -115,7 +116,7 @@ Axis1D build_axis(int n, int p) {
       }
       ax.w[(size_t)e * ax.q + j] = w[j] / n;
     }
-  // univariate parametric mass matrix on the free coefficients (indices 1..m-2)
+  // univariate parametric mass matrix on the free coefficients (indices lo..lo+mf-1)
   const int mf = ax.mf;
   std::vector<double> Mh((size_t)mf * mf, 0.0);
   for (int e = 0; e < n; ++e)
@@ -124,7 +125,7 @@ Axis1D build_axis(int n, int p) {
       double wj = ax.w[(size_t)e * ax.q + j];
       for (int r = 0; r < P1; ++r)
         for (int c = 0; c < P1; ++c) {
-          int i1 = e + r - 1, i2 = e + c - 1;
+          int i1 = e + r - lo, i2 = e + c - lo;
           if (i1 < 0 || i2 < 0 || i1 >= mf || i2 >= mf) continue;
           Mh[(size_t)i1 * mf + i2] += wj * b[r] * b[c];
         }

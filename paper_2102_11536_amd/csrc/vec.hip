@@ -371,6 +371,27 @@ __global__ void cg_p_seg_k(double* __restrict__ p, const double* __restrict__ z,
     p[off + i] = z[off + i] + b * p[off + i];
 }
 
+// glued multi-patch: local (patch-wise free) <-> global unknowns through the map
+// G (local index -> global index), nr right-hand sides
+__global__ void gather_k(int nr, const double* __restrict__ xg, long long Ng,
+                         const int* __restrict__ map, long long Nl, double* __restrict__ xl) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nr * Nl;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long j = e / Nl, i = e % Nl;
+    xl[e] = xg[j * Ng + map[i]];
+  }
+}
+
+__global__ void scatter_add_k(int nr, const double* __restrict__ yl, long long Nl,
+                              const int* __restrict__ map, double alpha, double* __restrict__ yg,
+                              long long Ng) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nr * Nl;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long j = e / Nl, i = e % Nl;
+    unsafeAtomicAdd(&yg[j * Ng + map[i]], alpha * yl[e]);
+  }
+}
+
 inline unsigned nblocks(size_t n) {
   size_t b = (n + VB - 1) / VB;
   if (b > 8192) b = 8192;
@@ -411,6 +432,15 @@ void launch_scaling(double* s, const double* d, const double* h0, const double* 
 void launch_dot_partial(int nr, const double* a, const double* b, size_t n, double* part,
                         hipStream_t st) {
   hipLaunchKernelGGL(dot_partial_k, dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part);
+}
+void launch_gather(int nr, const double* xg, long long Ng, const int* map, long long Nl, double* xl,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(gather_k, dim3(nblocks((size_t)nr * Nl)), dim3(VB), 0, st, nr, xg, Ng, map, Nl, xl);
+}
+void launch_scatter_add(int nr, const double* yl, long long Nl, const int* map, double alpha,
+                        double* yg, long long Ng, hipStream_t st) {
+  hipLaunchKernelGGL(scatter_add_k, dim3(nblocks((size_t)nr * Nl)), dim3(VB), 0, st, nr, yl, Nl, map,
+                     alpha, yg, Ng);
 }
 void launch_dot_partial_seg(int ns, const double* a, const double* b, const long long* seg,
                             double* part, hipStream_t st) {

@@ -17,7 +17,7 @@ GA_GNET_NPARAM = 32033
 GA_FP64, GA_FP32 = 0, 1
 GA_PINV_AUTO, GA_PINV_DENSE = 0, 1
 
-EXPORTS = ["ga_setup_patch", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
+EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
            "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
            "ga_integrator_create", "ga_integrator_destroy", "ga_init_state", "ga_step",
            "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error", "ga_stage_solution", "ga_patch_set_pinv",
@@ -25,7 +25,8 @@ EXPORTS = ["ga_setup_patch", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
-           "ga_batch_tune", "ga_batch_init_state", "ga_batch_step"]
+           "ga_batch_tune", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
+           "ga_mp_info", "ga_mp_apply", "ga_mp_mass_solve", "ga_mp_init_state", "ga_mp_step"]
 
 
 class GAError(RuntimeError):
@@ -47,6 +48,8 @@ def load_library(path=LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, i, d, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
     lib.ga_setup_patch.argtypes = [i, ctypes.POINTER(i), i, ctypes.POINTER(d), vp, ctypes.POINTER(vp)]
+    lib.ga_setup_patch_ex.argtypes = [i, ctypes.POINTER(i), i, ctypes.POINTER(d), ctypes.c_uint, vp,
+                                      ctypes.POINTER(vp)]
     lib.ga_destroy_patch.argtypes = [vp]
     lib.ga_patch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(i)]
@@ -90,6 +93,14 @@ def load_library(path=LIB_PATH):
     lib.ga_batch_tune.argtypes = [vp, i, ctypes.POINTER(d), vp]
     lib.ga_batch_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
     lib.ga_batch_step.argtypes = [vp, ctypes.POINTER(vp), i, i, ctypes.POINTER(i), vp]
+    lib.ga_mp_create.argtypes = [ctypes.POINTER(i), i, i, ctypes.POINTER(vp), i, d, d, d, i, vp,
+                                 ctypes.POINTER(vp)]
+    lib.ga_mp_destroy.argtypes = [vp]
+    lib.ga_mp_info.argtypes = [vp, lp, ctypes.POINTER(i), lp]
+    lib.ga_mp_apply.argtypes = [vp, ctypes.c_char, i, dp, dp, vp]
+    lib.ga_mp_mass_solve.argtypes = [vp, i, dp, dp, ctypes.POINTER(i), vp]
+    lib.ga_mp_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
+    lib.ga_mp_step.argtypes = [vp, ctypes.POINTER(vp), i, ctypes.POINTER(i), vp]
     for name in EXPORTS:
         if name not in ("ga_stability_limit", "ga_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -118,14 +129,18 @@ def _ptr(t, n=None):
 class Patch:
     """One spline patch (ga_setup_patch)."""
 
-    def __init__(self, dim, n_el, p, ctrl):
+    def __init__(self, dim, n_el, p, ctrl, dirichlet_faces=None):
         lib = load_library()
         n_el = [int(v) for v in (n_el if np.ndim(n_el) else [n_el] * dim)]
         ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
         arr = (ctypes.c_int * len(n_el))(*n_el)
         h = ctypes.c_void_p()
-        _check(lib.ga_setup_patch(dim, arr, p, ctrl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                  _stream(), ctypes.byref(h)))
+        cp = ctrl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if dirichlet_faces is None:
+            _check(lib.ga_setup_patch(dim, arr, p, cp, _stream(), ctypes.byref(h)))
+        else:
+            _check(lib.ga_setup_patch_ex(dim, arr, p, cp, ctypes.c_uint(int(dirichlet_faces)), _stream(),
+                                         ctypes.byref(h)))
         self.h = h
         nf, nq = ctypes.c_longlong(), ctypes.c_longlong()
         mf = (ctypes.c_int * 3)()
@@ -147,6 +162,10 @@ class Patch:
 
 def ga_setup_patch(dim, n_el, p, ctrl):
     return Patch(dim, n_el, p, ctrl)
+
+
+def ga_setup_patch_ex(dim, n_el, p, ctrl, dirichlet_faces):
+    return Patch(dim, n_el, p, ctrl, dirichlet_faces)
 
 
 def ga_patch_set_pinv(patch, mode):
@@ -459,3 +478,68 @@ def ga_batch_step(batch, state, nsteps=1, use_graph=True):
     _check(_lib.ga_batch_step(batch.h, _batch_state(batch, state), int(nsteps), 1 if use_graph else 0, its,
                               _stream()))
     return np.array(its, dtype=np.int64).reshape(nsteps, batch.k, R)
+
+
+# ---- glued multi-patch domain ----
+
+class MultiPatch:
+    """Brick of P[0] x P[1] x P[2] C^0-glued patches (ga_mp_create)."""
+
+    def __init__(self, P, n_el, p, ctrls, k, rho, tau, rtol=1e-10, maxit=200):
+        lib = load_library()
+        keep = [np.ascontiguousarray(c, dtype=np.float64) for c in ctrls]
+        arr = (ctypes.c_void_p * len(keep))(*[c.ctypes.data for c in keep])
+        Pa = (ctypes.c_int * 3)(*[int(v) for v in P])
+        h = ctypes.c_void_p()
+        _check(lib.ga_mp_create(Pa, int(n_el), int(p), arr, int(k), float(rho), float(tau), float(rtol),
+                                int(maxit), _stream(), ctypes.byref(h)))
+        self.h, self.k = h, k
+        n, nl = ctypes.c_longlong(), ctypes.c_longlong()
+        mfg = (ctypes.c_int * 3)()
+        _check(lib.ga_mp_info(h, ctypes.byref(n), mfg, ctypes.byref(nl)))
+        self.n_global, self.mfg, self.n_local = n.value, tuple(mfg), nl.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ga_mp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ga_mp_create(P, n_el, p, ctrls, k, rho, tau, rtol=1e-10, maxit=200):
+    return MultiPatch(P, n_el, p, ctrls, k, rho, tau, rtol, maxit)
+
+
+def ga_mp_apply(mp, which, x, y, nrhs=1):
+    n = nrhs * mp.n_global
+    _check(_lib.ga_mp_apply(mp.h, which.encode(), nrhs, _ptr(x, n), _ptr(y, n), _stream()))
+
+
+def ga_mp_mass_solve(mp, b, x, nrhs=1):
+    n = nrhs * mp.n_global
+    its = (ctypes.c_int * nrhs)()
+    _check(_lib.ga_mp_mass_solve(mp.h, nrhs, _ptr(b, n), _ptr(x, n), its, _stream()))
+    return list(its)
+
+
+def _mp_state(mp, state):
+    ns = 3 * mp.k
+    if len(state) != ns:
+        raise ValueError(f"need {ns} state vectors")
+    return (ctypes.c_void_p * ns)(*[_ptr(s, mp.n_global).value for s in state])
+
+
+def ga_mp_init_state(mp, U0, V0, state):
+    n = mp.n_global
+    _check(_lib.ga_mp_init_state(mp.h, _ptr(U0, n), _ptr(V0, n), _mp_state(mp, state), _stream()))
+
+
+def ga_mp_step(mp, state, nsteps=1):
+    its = (ctypes.c_int * (nsteps * mp.k))()
+    _check(_lib.ga_mp_step(mp.h, _mp_state(mp, state), int(nsteps), its, _stream()))
+    return np.array(its, dtype=np.int64).reshape(nsteps, mp.k)

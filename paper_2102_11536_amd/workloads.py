@@ -17,6 +17,11 @@ stepping); it only builds input arrays.  Recipes:
   RMS 1.
 * The 2-D standing wave u0 = sin(pi x) sin(pi y) is sampled at the Greville
   abscissae of the free coefficients.
+* Glued brick of patches: the unit cube split into P_x x P_y x P_z boxes, each a
+  patch with n elements and degree p; the control points of box r are its
+  Greville points mapped affinely into the box and then deformed by the global
+  map x_c + a sin(pi x_{c+1}) sin(pi x_{c+2}) (so the shared faces match); the
+  initial field is a GRF at the global coefficients' Greville-like points.
 * Batched multi-patch workload: R independent cube patches, each with a
   seeded element count n_r drawn uniformly from [n_min, n_max], degree p_r
   from {2, 3, 4} and its own smooth random geometry map (seed base + r),
@@ -88,8 +93,14 @@ def smooth_random_ctrl(n, p, seed, amp=0.06, dim=3):
 def grf(n, p, seed, ell=0.1, dim=3):
     """Seeded GRF on the free coefficient grid, shape [N_free] co-lex."""
     ns = _ns(n, dim)
+    return grf_on_axes([greville(v, p)[1:-1] for v in ns], seed, ell)
+
+
+def grf_on_axes(axes, seed, ell=0.1):
+    """Seeded GRF on the tensor grid of the given per-axis coordinates (x first),
+    co-lex, tapered by prod sin(pi x_a) and scaled to RMS 1."""
+    dim = len(axes)
     rng = np.random.default_rng(seed)
-    axes = [greville(v, p)[1:-1] for v in ns]
     Ls = []
     for x in axes:
         C = np.exp(-0.5 * ((x[:, None] - x[None, :]) / ell) ** 2)
@@ -169,3 +180,27 @@ def multipatch_specs(R=12, n_min=16, n_max=96, seed=7):
         p = int(rng.integers(2, 5))
         out.append((n, p, seed * 1000 + r, seed * 1000 + 100 + r))
     return out
+
+
+def brick_ctrl(P, n, p, r, amp=0.05):
+    """Control points [N_dof][3] of patch r (boxes numbered x fastest) of a brick
+    of P = (P_x, P_y, P_z) boxes over the unit cube."""
+    P = tuple(int(v) for v in P)
+    b = (r % P[0], (r // P[0]) % P[1], r // (P[0] * P[1]))
+    g = _grid([(b[a] + greville(n, p)) / P[a] for a in range(3)])
+    out = g.copy()
+    s_ = np.sin(np.pi * g)
+    for c in range(3):
+        out[:, c] = g[:, c] + amp * s_[:, (c + 1) % 3] * s_[:, (c + 2) % 3]
+    return out
+
+
+def brick_grf(P, n, p, seed, ell=0.1):
+    """GRF on the global unknowns of a glued brick (interior global coefficients,
+    co-lex): per axis the patch Greville points, shared ends merged."""
+    axes = []
+    for a in range(3):
+        gv = greville(n, p)
+        pts = np.concatenate([(b + gv[(1 if b else 0):]) / P[a] for b in range(P[a])])
+        axes.append(pts[1:-1])
+    return grf_on_axes(axes, seed, ell)
