@@ -128,6 +128,63 @@ def bench_multipatch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_glued(args):
+    """C0-glued brick of 2x2x2 patches (48 elements per patch and direction, p=3,
+    deformed by the global map), k=2, FP64 PCG with the additive Schwarz
+    preconditioner to rtol, zero guess; and the PCG iterations of one mass solve
+    for 1, 2, 4 and 8 glued patches at 32 elements per patch (the adjacency trend)."""
+    import torch
+    from paper_2102_11536_amd import ga, workloads
+    k, rho, n, p = args.k, 0.5, 48, args.p
+    dev = "cuda:0"
+    P = (2, 2, 2)
+
+    def domain(P, n, tau=1.0):
+        ctrls = [workloads.brick_ctrl(P, n, p, r) for r in range(P[0] * P[1] * P[2])]
+        return ga.ga_mp_create(P, n, p, ctrls, k, rho, tau, rtol=args.rtol)
+
+    trend = {}
+    for Pt in ((1, 1, 1), (2, 1, 1), (2, 2, 1), (2, 2, 2)):
+        d = domain(Pt, 32)
+        b = torch.as_tensor(workloads.brick_grf(Pt, 32, p, seed=5), device=dev)
+        x = torch.zeros_like(b)
+        trend["x".join(map(str, Pt))] = ga.ga_mp_mass_solve(d, b, x)[0]
+        d.close()
+    log(f"[bench] glued: PCG iterations by layout {trend}")
+    d = domain(P, n)
+    v = torch.as_tensor(workloads.brick_grf(P, n, p, seed=3), device=dev)
+    kv, w = torch.empty_like(v), torch.zeros_like(v)
+    lam = 0.0
+    for _ in range(25):                      # power iteration on M^{-1} K
+        ga.ga_mp_apply(d, "K", v, kv)
+        ga.ga_mp_mass_solve(d, kv, w)
+        lam = float(torch.dot(v, w) / torch.dot(v, v))
+        v = w / torch.linalg.vector_norm(w)
+    tau = 0.5 * np.sqrt(ga.ga_stability_limit(rho) / lam)
+    d.close()
+    d = domain(P, n, tau)
+    U = torch.as_tensor(workloads.brick_grf(P, n, p, seed=2000), device=dev)
+    state = [torch.zeros(d.n_global, dtype=torch.float64, device=dev) for _ in range(3 * k)]
+    ga.ga_mp_init_state(d, U, torch.zeros_like(U), state)
+    ga.ga_mp_step(d, state, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = ga.ga_mp_step(d, state, args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ndof = (P[0] * (n + p - 1) + 1) * (P[1] * (n + p - 1) + 1) * (P[2] * (n + p - 1) + 1)
+    log(f"[bench] glued 2x2x2 x {n}^3 p={p}: {dt / args.steps * 1e3:.3f} ms/step, iters {its.mean():.2f}")
+    out = {"metric": "DOF-steps/s, C0-glued 2x2x2 brick with additive Schwarz PCG (k=2)",
+           "value": ndof * args.steps / dt, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"glued_brick_2x2x2_n{n}_p{p}_k{k}", "n_dof": ndof,
+                      "n_global_unknowns": d.n_global, "n_local": d.n_local, "tau": tau,
+                      "lambda_max": lam, "rtol": args.rtol, "pcg_iters_mean": float(its.mean()),
+                      "pcg_iters_by_layout_n32": trend}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,9 +199,10 @@ def main():
                     help="counter-collection mode: run only these operator applies (e.g. K2,M2), "
                          "three times each, then a 1 GiB device copy used to calibrate "
                          "FETCH_SIZE/WRITE_SIZE, and exit")
-    ap.add_argument("--workload", default="cube", choices=["cube", "multipatch"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "multipatch", "glued"],
                     help="cube: the single-patch headline workload; multipatch: 12 independent "
-                         "patches of uneven size and degree stepped as one batch")
+                         "patches of uneven size and degree stepped as one batch; glued: a 2x2x2 "
+                         "brick of C0-glued patches with the additive Schwarz preconditioner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
@@ -156,6 +214,8 @@ def main():
 
     if args.workload == "multipatch":
         return bench_multipatch(args)
+    if args.workload == "glued":
+        return bench_glued(args)
     n, p, k, rho = args.n, args.p, args.k, 0.5
     dev = "cuda:0"
     log(f"[bench] workload deformed cube p={p} n={n}^3 k={k}: building inputs")
