@@ -82,8 +82,9 @@ def bench_multipatch(args):
     """12 independent patches (n in [16, 96] elements per axis, p in {2, 3, 4},
     seeded smooth random maps, GRF initial data), k = 2, stepped as one batch
     with a common tau (0.5 of the most restrictive patch's stability limit);
-    FP64 PCG to rtol, zero guess; the batched step with and without the
-    captured PCG-iteration graph, after the launch-shape autotuner."""
+    zero guess, mass solves to rtol either in FP64 PCG or as FP32 inner PCG
+    inside FP64 refinement; the batched step with and without the captured
+    PCG-iteration graph, after the launch-shape autotuner."""
     import torch
     from paper_2102_11536_amd import ga, workloads
     k, rho = args.k, 0.5
@@ -97,31 +98,36 @@ def bench_multipatch(args):
     lam = max(ga.ga_lambda_max(pt, 25) for pt in pts)
     tau = 0.5 * np.sqrt(ga.ga_stability_limit(rho) / lam)
     b = ga.ga_batch_create(pts, k, rho, tau, rtol=args.rtol)
+    ga.ga_batch_set_precision(b, ga.GA_FP32)       # builds the FP32 tables, tuned below too
     tuned_ms = ga.ga_batch_tune(b, reps=3)
+    ga.ga_batch_set_precision(b, ga.GA_FP64)
     log(f"[bench] tuned operator launches: {tuned_ms:.3f} ms per (M + K) sweep")
     U = torch.as_tensor(np.concatenate(U0s), device=dev)
     state0 = [torch.zeros(b.n_total, dtype=torch.float64, device=dev) for _ in range(3 * k)]
     ga.ga_batch_init_state(b, U, torch.zeros_like(U), state0)
     ndof = sum((n + p) ** 3 for (n, p, _, _) in specs)
     res = {}
-    for use_graph in (True, False):
-        state = [t.clone() for t in state0]
-        ga.ga_batch_step(b, state, args.warmup, use_graph=use_graph)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its = ga.ga_batch_step(b, state, args.steps, use_graph=use_graph)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res["graph" if use_graph else "eager"] = {"dof_steps_per_s": ndof * args.steps / dt,
-                                                  "ms_per_step": dt / args.steps * 1e3,
-                                                  "pcg_iters_mean": float(its.mean())}
-        log(f"[bench] multipatch {'graph' if use_graph else 'eager'}: {dt / args.steps * 1e3:.3f} ms/step")
+    for prec, pname in ((ga.GA_FP64, "fp64"), (ga.GA_FP32, "mixed")):
+        ga.ga_batch_set_precision(b, prec)
+        for use_graph in (True, False):
+            name = f"{pname}_{'graph' if use_graph else 'eager'}"
+            state = [t.clone() for t in state0]
+            ga.ga_batch_step(b, state, args.warmup, use_graph=use_graph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = ga.ga_batch_step(b, state, args.steps, use_graph=use_graph)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[name] = {"dof_steps_per_s": ndof * args.steps / dt, "ms_per_step": dt / args.steps * 1e3,
+                         "pcg_iters_mean": float(its.mean())}
+            log(f"[bench] multipatch {name}: {dt / args.steps * 1e3:.3f} ms/step, "
+                f"{float(its.mean()):.2f} iterations per system")
     best = max(res, key=lambda x: res[x]["dof_steps_per_s"])
     out = {"metric": "DOF-steps/s, batched multi-patch (12 uneven patches, k=2)",
            "value": res[best]["dof_steps_per_s"], "unit": "DOF-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[best]["ms_per_step"],
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64" if best.startswith("mixed") else "f64", "data": "synthetic",
            "config": {"workload": "multipatch_12", "patches": specs, "n_dof": ndof,
                       "n_free": b.n_total, "k": k, "tau": tau, "rtol": args.rtol,
                       "tuned_op_ms": tuned_ms, "paths": res, "path": best}}

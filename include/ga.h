@@ -306,6 +306,16 @@ int ga_integrator_set_net(ga_integrator* integ, int stage, ga_gnet* net);
 int ga_batch_create(int npatch, ga_patch* const* patches, int k, double rho, double tau,
                     double rtol, int maxit, ga_batch** out);
 int ga_batch_destroy(ga_batch* batch);
+/*
+ * ga_batch_set_precision -- arithmetic of the batch's mass solves (Sec. 6.1):
+ * GA_FP64 (default) or GA_FP32 = FP32 flexible-PCG corrections (FP32 mass
+ * factors, vectors and preconditioner, inner reduction 1e-4) inside an FP64
+ * iterative refinement whose residual and stopping test are FP64.  The first
+ * switch to GA_FP32 builds FP32 copies of every patch's factors (kept with the
+ * patch) and the FP32 launch tables; it synchronizes `stream`.  Iteration
+ * counts reported by ga_batch_step are then inner FP32 iterations.
+ */
+int ga_batch_set_precision(ga_batch* batch, int prec, void* stream);
 /* n_total: N; offsets_out[npatch] (may be NULL); graph_replays: PCG iterations
  * run so far as replays of the captured iteration graph (may be NULL). */
 int ga_batch_info(const ga_batch* batch, long long* n_total, long long* offsets_out,

@@ -449,6 +449,8 @@ int solve_any(ga_patch* pt, int nr, const double* b, double* x, double rtol, int
 
 }  // namespace
 
+int ga::mixed_setup(ga_patch* pt, hipStream_t st) { return ensure_mixed(pt, st); }
+
 extern "C" {
 
 const char* ga_last_error(void) { return g_err.c_str(); }

@@ -36,12 +36,14 @@ struct OpGroup {
   std::vector<long long> offs;
   int ze_override = 0;        // 0: each patch's default
   int nwg = 0;                // 0: one workgroup per tile
+  bool f32 = false;           // FP32 factors (mass only)
   OpGroupEntry* ents = nullptr;
   int nent = 0, total = 0;
 };
 
 struct PGroup {
   int nr = 0, pass = 0, ra = 0;
+  bool f32 = false;
   PinvEntry* ents = nullptr;
   int nent = 0, nblk = 0;
 };
@@ -57,13 +59,15 @@ struct ga_batch {
   long long N = 0, maxlen = 0;
   std::vector<OpGroup> ops[2];   // mass, stiffness
   std::vector<PGroup> pgroups;
+  int prec = GA_FP64;            // arithmetic of the mass solves
+  std::vector<OpGroup> mass32;   // FP32 mass applies of the inner solves (GA_FP32)
   long long* seg = nullptr;      // [k*R][2]
   double *Y = nullptr, *Bv = nullptr, *X = nullptr, *work = nullptr;
   double *red = nullptr, *scal = nullptr, *host_scal = nullptr;
   hipStream_t gs = nullptr;      // stream of the captured iteration
   hipEvent_t ev[2] = {nullptr, nullptr};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr, graph32 = nullptr;
+  hipGraphExec_t exec = nullptr, exec32 = nullptr;
   long long n_iters = 0, n_replays = 0;
 };
 
@@ -75,7 +79,7 @@ int upload_op_group(OpGroup& g) {
   for (size_t i = 0; i < g.pts.size(); ++i) {
     const int ze = g.ze_override > 0 ? std::min(g.ze_override, g.pts[i]->n[2])
                                      : op3d_default_ze(g.mode, g.pts[i]);
-    OpGroupEntry e = op3d_group_entry(g.mode, g.pts[i], ze, g.offs[i], tile, false);
+    OpGroupEntry e = op3d_group_entry(g.mode, g.pts[i], ze, g.offs[i], tile, g.f32);
     tile += e.ntiles;
     h.push_back(e);
   }
@@ -103,9 +107,24 @@ int op_batch(ga_batch* b, int mode, int nr, double alpha, const double* x, doubl
   return GA_OK;
 }
 
+// FP32 mass applies y += M x (inner solves of the mixed-precision path)
+int op_batch32(ga_batch* b, int nr, const float* x, float* y, hipStream_t st) {
+  for (int r0 = 0; r0 < nr; r0 += 3) {
+    const int c = std::min(3, nr - r0);
+    for (OpGroup& g : b->mass32) {
+      const int nwg = g.nwg > 0 ? std::min(g.nwg, g.total) : g.total;
+      if (launch_op3d_group<float>(g.p, 0, c, g.ents, g.nent, x + (size_t)r0 * b->N,
+                                   y + (size_t)r0 * b->N, b->N, 1.0f, g.total, nwg, st))
+        return check_launch(-1, "batched FP32 mass apply");
+    }
+  }
+  return GA_OK;
+}
+
 // entries of one preconditioner pass for nr right-hand sides, grouped by the
-// register-tile class of the axis length
-int build_pgroups(ga_batch* b, int nr) {
+// register-tile class of the axis length (FP32 copies of the 1-D inverses and
+// of the scaling when f32)
+int build_pgroups(ga_batch* b, int nr, bool f32) {
   for (int pass = 0; pass < 3; ++pass) {
     std::vector<PinvEntry> cls[3];
     int blk[3] = {0, 0, 0};
@@ -116,15 +135,19 @@ int build_pgroups(ga_batch* b, int nr) {
       e.off = b->off[r];
       e.si = e.so = nullptr;
       long long nb = 0;
+      const void* sc = f32 ? (const void*)pt->s32 : (const void*)pt->s;
+      const void* A[3] = {pt->Minv[0], pt->Minv[1], pt->Minv[2]};
+      if (f32)
+        for (int a = 0; a < 3; ++a) A[a] = pt->Minv32[a];
       if (pass == 0) {
-        e.A = pt->Minv[0];
+        e.A = A[0];
         e.L = (int)m0;
-        e.si = pt->s;
+        e.si = sc;
         e.p[0] = nr * m1 * m2;
         e.p[1] = m1 * m2;
         nb = (e.p[0] + 63) / 64;
       } else if (pass == 1) {
-        e.A = pt->Minv[1];
+        e.A = A[1];
         e.L = (int)m1;
         e.p[0] = m0;
         e.p[1] = m0;
@@ -132,9 +155,9 @@ int build_pgroups(ga_batch* b, int nr) {
         e.p[3] = m0 * m2;
         nb = (e.p[3] + 63) / 64;
       } else {
-        e.A = pt->Minv[2];
+        e.A = A[2];
         e.L = (int)m2;
-        e.so = pt->s;
+        e.so = sc;
         e.p[0] = m0 * m1;
         e.p[1] = m0 * m1;
         e.p[2] = 0;
@@ -152,6 +175,7 @@ int build_pgroups(ga_batch* b, int nr) {
       g.nr = nr;
       g.pass = pass;
       g.ra = c;
+      g.f32 = f32;
       g.nent = (int)cls[c].size();
       g.nblk = blk[c];
       int rc = dalloc((void**)&g.ents, cls[c].size() * sizeof(PinvEntry));
@@ -171,9 +195,20 @@ int pinv_batch(ga_batch* b, int nr, const double* r, double* z, double* t0, doub
   double* out[3] = {t1, t0, z};
   for (int pass = 0; pass < 3; ++pass)
     for (const PGroup& g : b->pgroups)
-      if (g.nr == nr && g.pass == pass)
+      if (g.nr == nr && g.pass == pass && !g.f32)
         launch_pinv_group<double>(pass, g.ra, g.ents, g.nent, g.nblk, nr, in[pass], out[pass], b->N, st);
   return check_launch(0, "batched preconditioner");
+}
+
+int pinv_batch32(ga_batch* b, int nr, const float* r, float* z, float* t0, float* t1,
+                 hipStream_t st) {
+  const float* in[3] = {r, t1, t0};
+  float* out[3] = {t1, t0, z};
+  for (int pass = 0; pass < 3; ++pass)
+    for (const PGroup& g : b->pgroups)
+      if (g.nr == nr && g.pass == pass && g.f32)
+        launch_pinv_group<float>(pass, g.ra, g.ents, g.nent, g.nblk, nr, in[pass], out[pass], b->N, st);
+  return check_launch(0, "batched FP32 preconditioner");
 }
 
 struct Bufs {
@@ -204,17 +239,59 @@ int pcg_iteration(ga_batch* b, int nr, double* x, hipStream_t st) {
   return check_launch(0, "batched pcg iteration");
 }
 
+// buffers of the mixed-precision solve, carved from the same work area:
+// the FP64 outer residual and seven FP32 vectors of k*N entries
+struct Bufs32 {
+  double* r64;
+  float *r, *z, *p, *q, *d, *t0, *t1;
+};
+
+Bufs32 bufs32(ga_batch* b) {
+  const size_t kn = (size_t)b->k * b->N;
+  float* f = reinterpret_cast<float*>(b->work + kn);
+  Bufs32 w{b->work, f, f + kn, f + 2 * kn, f + 3 * kn, f + 4 * kn, f + 5 * kn, f + 6 * kn};
+  return w;
+}
+
+// one inner FP32 flexible-PCG iteration of every active system for M d = r
+int pcg32_iteration(ga_batch* b, int nr, hipStream_t st) {
+  const int ns = nr * b->R;
+  Bufs32 w = bufs32(b);
+  double* partA = b->red;
+  double* partB = b->red + (size_t)ns * RED_BLOCKS;
+  launch_fill_f32(w.q, (size_t)nr * b->N, st);
+  int rc = op_batch32(b, nr, w.p, w.q, st);
+  if (rc) return rc;
+  launch_dot_ff(ns, w.p, w.q, b->maxlen, partA, st, b->seg);
+  launch_cg_alpha(ns, partA, b->scal, st);
+  launch_cg_xr_f32(ns, w.d, w.r, w.p, w.q, b->scal, b->maxlen, st, b->seg);
+  if ((rc = pinv_batch32(b, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+  launch_dot2_f32(ns, w.r, w.z, w.q, b->maxlen, partA, partB, st, b->seg);
+  launch_cg_beta_flex(ns, partA, partB, b->scal, st);
+  launch_cg_p_f32(ns, w.p, w.z, b->scal, b->maxlen, st, b->seg);
+  return check_launch(0, "batched inner PCG iteration");
+}
+
 void drop_graph(ga_batch* b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+  if (b->exec32) hipGraphExecDestroy(b->exec32);
+  if (b->graph32) hipGraphDestroy(b->graph32);
+  b->exec = b->exec32 = nullptr;
+  b->graph = b->graph32 = nullptr;
 }
 
-int capture_iteration(ga_batch* b) {
-  drop_graph(b);
+// capture one iteration (FP64 PCG, or the FP32 inner PCG when f32) on the
+// batch's stream
+int capture_iteration(ga_batch* b, bool f32) {
+  hipGraph_t& graph = f32 ? b->graph32 : b->graph;
+  hipGraphExec_t& exec = f32 ? b->exec32 : b->exec;
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  exec = nullptr;
+  graph = nullptr;
   GA_TRY_HIP(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
-  int rc = pcg_iteration(b, b->k, b->X, b->gs);
+  int rc = f32 ? pcg32_iteration(b, b->k, b->gs) : pcg_iteration(b, b->k, b->X, b->gs);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->gs, &g);
   if (rc) {
@@ -225,15 +302,15 @@ int capture_iteration(ga_batch* b) {
     set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
     return GA_EDEVICE;
   }
-  b->graph = g;
-  GA_TRY_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  graph = g;
+  GA_TRY_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   return GA_OK;
 }
 
 // batched PCG, zero initial guess, nr right-hand sides per patch: systems
 // s = j*R + r, rhs j of patch r; x and b are [nr][N]
-int solve_batch(ga_batch* b, int nr, const double* rhs, double* x, bool graph, int* iters_out,
-                hipStream_t st) {
+int solve_batch64(ga_batch* b, int nr, const double* rhs, double* x, bool graph, int* iters_out,
+                  hipStream_t st) {
   const int ns = nr * b->R;
   const size_t tot = (size_t)nr * b->N;
   Bufs w = bufs(b);
@@ -247,7 +324,7 @@ int solve_batch(ga_batch* b, int nr, const double* rhs, double* x, bool graph, i
   launch_copy(w.p, w.z, tot, st);
   if (check_launch(0, "batched pcg start")) return GA_EDEVICE;
   const bool use_graph = graph && nr == b->k && x == b->X;
-  if (use_graph && !b->exec && (rc = capture_iteration(b))) return rc;
+  if (use_graph && !b->exec && (rc = capture_iteration(b, false))) return rc;
   for (int it = 0;; ++it) {
     GA_TRY_HIP(hipMemcpyAsync(b->host_scal, b->scal, sizeof(double) * NSCAL * ns,
                               hipMemcpyDeviceToHost, st));
@@ -276,11 +353,119 @@ int solve_batch(ga_batch* b, int nr, const double* rhs, double* x, bool graph, i
   return GA_OK;
 }
 
+int read_batch_scalars(ga_batch* b, int ns, hipStream_t st) {
+  GA_TRY_HIP(hipMemcpyAsync(b->host_scal, b->scal, sizeof(double) * NSCAL * ns,
+                            hipMemcpyDeviceToHost, st));
+  GA_TRY_HIP(hipStreamSynchronize(st));
+  return GA_OK;
+}
+
+// Batched mixed-precision solve, zero initial guess: FP64 iterative refinement
+// (outer residual r = b - M x with the FP64 factors, stop when
+// sqrt(r^T P^{-1} r) <= rtol sqrt(b^T P^{-1} b) per system, dots in FP64) around
+// FP32 flexible PCG corrections M d = r that reduce their residual by 1e-4.  A
+// system that has met its tolerance gets a zero correction (its inner residual
+// is cleared) while the others go on.  x and rhs are [nr][N] in FP64.
+int solve_batch_mixed(ga_batch* b, int nr, const double* rhs, double* x, bool graph,
+                      int* iters_out, hipStream_t st) {
+  const int ns = nr * b->R;
+  const size_t tot = (size_t)nr * b->N;
+  Bufs32 w = bufs32(b);
+  double* partA = b->red;
+  double* partB = b->red + (size_t)ns * RED_BLOCKS;
+  const double inner_tol = 1e-4;
+  const bool use_graph = graph && nr == b->k;
+  int rc;
+  if (use_graph && !b->exec32 && (rc = capture_iteration(b, true))) return rc;
+  launch_fill(x, 0.0, tot, st);
+  launch_to_f32(w.r, rhs, tot, st);
+  if ((rc = pinv_batch32(b, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+  launch_dot_df(ns, rhs, w.z, b->maxlen, partB, st, b->seg);
+  launch_sum_partials(ns, partB, b->scal, st);
+  if ((rc = read_batch_scalars(b, ns, st))) return rc;
+  std::vector<double> bn2(ns), rz(ns);
+  std::vector<int> inner(ns, 0);
+  for (int s = 0; s < ns; ++s) rz[s] = bn2[s] = b->host_scal[s];
+  auto seg_of = [&](int s, size_t& off, size_t& len) {
+    const int j = s / b->R, r = s % b->R;
+    off = (size_t)j * b->N + (size_t)b->off[r];
+    len = (size_t)b->pts[r]->n_free;
+  };
+  bool conv = false;
+  for (int outer = 0; outer < 50; ++outer) {
+    if (outer > 0) {   // preconditioned outer residual
+      launch_to_f32(w.r, w.r64, tot, st);
+      if ((rc = pinv_batch32(b, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+      launch_dot_df(ns, w.r64, w.z, b->maxlen, partA, st, b->seg);
+      launch_sum_partials(ns, partA, b->scal, st);
+      if ((rc = read_batch_scalars(b, ns, st))) return rc;
+      for (int s = 0; s < ns; ++s) rz[s] = b->host_scal[s];
+    }
+    bool all = true;
+    for (int s = 0; s < ns; ++s) {
+      const bool done = !(bn2[s] > 0.0) || rz[s] <= b->rtol * b->rtol * bn2[s];
+      if (!done) {
+        all = false;
+      } else {   // no correction for a converged system
+        size_t off, len;
+        seg_of(s, off, len);
+        launch_fill_f32(w.r + off, len, st);
+        launch_fill_f32(w.z + off, len, st);
+      }
+    }
+    int used = 0;
+    for (int s = 0; s < ns; ++s) used = std::max(used, inner[s]);
+    if (all) { conv = true; break; }
+    if (used >= b->maxit) break;
+    launch_fill_f32(w.d, tot, st);
+    launch_dot_ff(ns, w.r, w.z, b->maxlen, partA, st, b->seg);
+    launch_cg_start(ns, partA, nullptr, b->scal, inner_tol * inner_tol, st);
+    launch_copy_f32(w.p, w.z, tot, st);
+    if (check_launch(0, "batched inner PCG start")) return GA_EDEVICE;
+    for (int it = 0; it < 20; ++it) {
+      if ((rc = read_batch_scalars(b, ns, st))) return rc;
+      bool any = false;
+      for (int s = 0; s < ns; ++s) any |= b->host_scal[s * NSCAL + S_ACTIVE] != 0.0;
+      if (!any) break;
+      if (use_graph) {
+        GA_TRY_HIP(hipGraphLaunch(b->exec32, st));
+        b->n_replays += 1;
+      } else if ((rc = pcg32_iteration(b, nr, st))) {
+        return rc;
+      }
+      b->n_iters += 1;
+    }
+    if ((rc = read_batch_scalars(b, ns, st))) return rc;
+    for (int s = 0; s < ns; ++s) inner[s] += (int)b->host_scal[s * NSCAL + S_ITERS];
+    // x += d; r = b - M x in FP64
+    launch_add_f32(x, w.d, tot, st);
+    launch_copy(w.r64, rhs, tot, st);
+    if ((rc = op_batch(b, 0, nr, -1.0, x, w.r64, st))) return rc;
+  }
+  for (int s = 0; s < ns; ++s) {
+    if (iters_out) iters_out[s] = inner[s];
+    if (!std::isfinite(rz[s])) conv = false;
+  }
+  if (!conv) {
+    set_error("batched mixed-precision solve did not converge within maxit");
+    return GA_ENOCONV;
+  }
+  return GA_OK;
+}
+
+int solve_batch(ga_batch* b, int nr, const double* rhs, double* x, bool graph, int* iters_out,
+                hipStream_t st) {
+  if (b->prec == GA_FP32) return solve_batch_mixed(b, nr, rhs, x, graph, iters_out, st);
+  return solve_batch64(b, nr, rhs, x, graph, iters_out, st);
+}
+
 void free_batch(ga_batch* b) {
   drop_graph(b);
   for (int m = 0; m < 2; ++m)
     for (OpGroup& g : b->ops[m])
       if (g.ents) hipFree(g.ents);
+  for (OpGroup& g : b->mass32)
+    if (g.ents) hipFree(g.ents);
   for (PGroup& g : b->pgroups)
     if (g.ents) hipFree(g.ents);
   for (void* p : {(void*)b->seg, (void*)b->Y, (void*)b->Bv, (void*)b->X, (void*)b->work,
@@ -363,8 +548,8 @@ int ga_batch_create(int npatch, ga_patch* const* patches, int k, double rho, dou
       b->ops[mode].push_back(g);
       if ((rc = upload_op_group(b->ops[mode].back()))) return fail(rc);
     }
-  if ((rc = build_pgroups(b, 1))) return fail(rc);
-  if (k > 1 && (rc = build_pgroups(b, k))) return fail(rc);
+  if ((rc = build_pgroups(b, 1, false))) return fail(rc);
+  if (k > 1 && (rc = build_pgroups(b, k, false))) return fail(rc);
   std::vector<long long> seg;
   for (int j = 0; j < k; ++j)
     for (int r = 0; r < npatch; ++r) {
@@ -376,7 +561,7 @@ int ga_batch_create(int npatch, ga_patch* const* patches, int k, double rho, dou
   if ((rc = dalloc((void**)&b->seg, seg.size() * sizeof(long long))) ||
       (rc = dalloc((void**)&b->Y, kn * 8)) || (rc = dalloc((void**)&b->Bv, kn * 8)) ||
       (rc = dalloc((void**)&b->X, kn * 8)) || (rc = dalloc((void**)&b->work, 6 * kn * 8)) ||
-      (rc = dalloc((void**)&b->red, (size_t)ns * RED_BLOCKS * 8)) ||
+      (rc = dalloc((void**)&b->red, (size_t)2 * ns * RED_BLOCKS * 8)) ||
       (rc = dalloc((void**)&b->scal, (size_t)ns * NSCAL * 8)))
     return fail(rc);
   if (hipHostMalloc((void**)&b->host_scal, (size_t)ns * NSCAL * 8, hipHostMallocDefault) != hipSuccess) {
@@ -393,6 +578,34 @@ int ga_batch_create(int npatch, ga_patch* const* patches, int k, double rho, dou
   }
   *out = b;
   return GA_OK;
+}
+
+int ga_batch_set_precision(ga_batch* b, int prec, void* stream) {
+  if (!b) { set_error("null batch"); return GA_EINVAL; }
+  if (prec != GA_FP64 && prec != GA_FP32) { set_error("prec must be GA_FP64 or GA_FP32"); return GA_EINVAL; }
+  drop_graph(b);
+  b->prec = prec;
+  if (prec == GA_FP64 || !b->mass32.empty()) return GA_OK;
+  hipStream_t st = S(stream);
+  int rc;
+  for (ga_patch* pt : b->pts)
+    if ((rc = mixed_setup(pt, st))) return rc;
+  for (const OpGroup& g64 : b->ops[0]) {
+    OpGroup g;
+    g.p = g64.p;
+    g.mode = 0;
+    g.pts = g64.pts;
+    g.offs = g64.offs;
+    g.ze_override = g64.ze_override;
+    g.nwg = g64.nwg;
+    g.f32 = true;
+    b->mass32.push_back(g);
+    if ((rc = upload_op_group(b->mass32.back()))) return rc;
+  }
+  if ((rc = build_pgroups(b, 1, true))) return rc;
+  if (b->k > 1 && (rc = build_pgroups(b, b->k, true))) return rc;
+  GA_TRY_HIP(hipStreamSynchronize(st));
+  return check_launch(0, "batched mixed-precision setup");
 }
 
 int ga_batch_destroy(ga_batch* b) {
@@ -423,8 +636,9 @@ int ga_batch_tune(ga_batch* b, int reps, double* best_ms, void* stream) {
   const int nr = std::min(b->k, 3);
   launch_fill(w.t0, 0.0, (size_t)b->k * b->N, st);
   launch_fill(w.t1, 0.0, (size_t)b->k * b->N, st);
-  for (int mode = 0; mode < 2 && !rc; ++mode)
-    for (OpGroup& g : b->ops[mode]) {
+  float* t32 = reinterpret_cast<float*>(w.t0);
+  for (int mode = 0; mode < 3 && !rc; ++mode)
+    for (OpGroup& g : mode < 2 ? b->ops[mode] : b->mass32) {
       int best_ze = g.ze_override, best_nwg = g.nwg;
       double best = 1e30;
       std::vector<int> zes = {0, 2, 4, 8, 16, 32};
@@ -436,12 +650,17 @@ int ga_batch_tune(ga_batch* b, int reps, double* best_ms, void* stream) {
           g.nwg = nwgc;
           const int nwg = nwgc > 0 ? nwgc : g.total;
           // warm-up, then timed launches (k right-hand sides, scratch vectors)
-          launch_op3d_group<double>(g.p, mode, nr, g.ents, g.nent, w.t0, w.t1, b->N, 1.0,
-                                    g.total, nwg, st);
+          auto launch = [&]() {
+            if (g.f32)
+              launch_op3d_group<float>(g.p, 0, nr, g.ents, g.nent, t32, t32 + (size_t)nr * b->N,
+                                       b->N, 1.0f, g.total, nwg, st);
+            else
+              launch_op3d_group<double>(g.p, g.mode, nr, g.ents, g.nent, w.t0, w.t1, b->N, 1.0,
+                                        g.total, nwg, st);
+          };
+          launch();
           hipEventRecord(e0, st);
-          for (int i = 0; i < reps; ++i)
-            launch_op3d_group<double>(g.p, mode, nr, g.ents, g.nent, w.t0, w.t1, b->N, 1.0,
-                                      g.total, nwg, st);
+          for (int i = 0; i < reps; ++i) launch();
           hipEventRecord(e1, st);
           if (hipEventSynchronize(e1) != hipSuccess) { rc = check_launch(-1, "tuning"); break; }
           float ms = 0.f;

@@ -90,6 +90,10 @@ inline int check_launch(int rc, const char* what) {
 void block_j_params(double rho, double& a, double& b, double& g);
 void block_k_params(double rho, double& a, double& b, double& g);
 
+// FP32 copies of a 3-D patch's factors, 1-D inverses, band factors and scaling
+// for the mixed-precision solves (built once, kept with the patch)
+int mixed_setup(ga_patch* pt, hipStream_t st);
+
 // whole-grid learned guess of one stage from its four newest solutions h[0..3]
 int gnet_guess(ga_gnet* net, ga_patch* pt, const double* const* h, double* X, hipStream_t st);
 

@@ -107,19 +107,26 @@ void launch_update(int k, double tau, Coefs c, StatePtrs sp, const double* X, si
                    hipStream_t st);
 void launch_axpby(double* out, double a, const double* x, double b, const double* y, size_t n,
                   hipStream_t st);
+// FP32 kernels of the mixed solve; with seg, system r covers entries
+// seg[2r] .. seg[2r] + seg[2r+1] - 1 (n is then the longest system)
 void launch_to_f32(float* o, const double* i, size_t n, hipStream_t st);
 void launch_add_f32(double* x, const float* d, size_t n, hipStream_t st);
 void launch_fill_f32(float* p, size_t n, hipStream_t st);
 void launch_copy_f32(float* d, const float* s, size_t n, hipStream_t st);
-void launch_dot_ff(int nr, const float* a, const float* b, size_t n, double* part, hipStream_t st);
-void launch_dot_df(int nr, const double* a, const float* b, size_t n, double* part, hipStream_t st);
+void launch_dot_ff(int nr, const float* a, const float* b, size_t n, double* part, hipStream_t st,
+               const long long* seg = nullptr);
+void launch_dot_df(int nr, const double* a, const float* b, size_t n, double* part, hipStream_t st,
+               const long long* seg = nullptr);
 void launch_dot2_f32(int nr, const float* r, const float* z, const float* q, size_t n, double* p1,
-                     double* p2, hipStream_t st);
+                     double* p2, hipStream_t st,
+               const long long* seg = nullptr);
 void launch_cg_beta_flex(int nr, const double* p1, const double* p2, double* scal, hipStream_t st);
 void launch_cg_xr_f32(int nr, float* x, float* r, const float* p, const float* q,
-                      const double* scal, size_t n, hipStream_t st);
+                      const double* scal, size_t n, hipStream_t st,
+               const long long* seg = nullptr);
 void launch_cg_p_f32(int nr, float* p, const float* z, const double* scal, size_t n,
-                     hipStream_t st);
+                     hipStream_t st,
+               const long long* seg = nullptr);
 void launch_sum_partials(int nr, const double* part, double* out, hipStream_t st);
 // glued multi-patch: xl[j][i] = xg[j][map[i]]; yg[j][map[i]] += alpha yl[j][i] (atomic)
 void launch_gather(int nr, const double* xg, long long Ng, const int* map, long long Nl, double* xl,

@@ -56,13 +56,28 @@ __global__ void copy_f32_k(float* __restrict__ d, const float* __restrict__ s, s
 }
 
 // part[r][block] = sum a_r * b_r with FP64 accumulation (a, b FP32 or FP64)
+// system r covers entries r*n .. r*n+n-1, or seg[2r] .. seg[2r]+seg[2r+1]-1 when a
+// segment table is given (patches of a batch)
+__device__ __forceinline__ void span(const long long* seg, int r, size_t n, size_t& off, size_t& len) {
+  if (seg) {
+    off = (size_t)seg[2 * r];
+    len = (size_t)seg[2 * r + 1];
+  } else {
+    off = (size_t)r * n;
+    len = n;
+  }
+}
+
 template <typename TA, typename TB>
 __global__ void __launch_bounds__(VB)
-dotm_k(const TA* __restrict__ a, const TB* __restrict__ b, size_t n, double* __restrict__ part) {
+dotm_k(const TA* __restrict__ a, const TB* __restrict__ b, size_t n, double* __restrict__ part,
+       const long long* __restrict__ seg) {
   __shared__ double sh[VB / 64];
   const int r = blockIdx.y;
-  const TA* ar = a + (size_t)r * n;
-  const TB* br = b + (size_t)r * n;
+  size_t off;
+  span(seg, r, n, off, n);
+  const TA* ar = a + off;
+  const TB* br = b + off;
   double s = 0.0;
   for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB)
     s += (double)ar[i] * (double)br[i];
@@ -73,10 +88,11 @@ dotm_k(const TA* __restrict__ a, const TB* __restrict__ b, size_t n, double* __r
 // two dots in one pass: r.z and z.q (FP32 vectors, FP64 accumulation)
 __global__ void __launch_bounds__(VB)
 dot2_k(const float* __restrict__ r, const float* __restrict__ z, const float* __restrict__ q,
-       size_t n, double* __restrict__ p1, double* __restrict__ p2) {
+       size_t n, double* __restrict__ p1, double* __restrict__ p2, const long long* __restrict__ seg) {
   __shared__ double sh[VB / 64];
   const int rr = blockIdx.y;
-  const size_t off = (size_t)rr * n;
+  size_t off;
+  span(seg, rr, n, off, n);
   double s1 = 0.0, s2 = 0.0;
   for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB) {
     const double zv = z[off + i];
@@ -119,11 +135,13 @@ __global__ void __launch_bounds__(VB) cg_beta_flex_k(const double* p1, const dou
 
 __global__ void cg_xr_f32_k(float* __restrict__ x, float* __restrict__ r,
                             const float* __restrict__ p, const float* __restrict__ q,
-                            const double* __restrict__ scal, size_t n) {
+                            const double* __restrict__ scal, size_t n,
+                            const long long* __restrict__ seg) {
   const int rr = blockIdx.y;
   const float a = (float)scal[(size_t)rr * NSCAL + S_ALPHA];
   if (a == 0.0f) return;
-  const size_t off = (size_t)rr * n;
+  size_t off;
+  span(seg, rr, n, off, n);
   for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB) {
     x[off + i] += a * p[off + i];
     r[off + i] -= a * q[off + i];
@@ -131,11 +149,13 @@ __global__ void cg_xr_f32_k(float* __restrict__ x, float* __restrict__ r,
 }
 
 __global__ void cg_p_f32_k(float* __restrict__ p, const float* __restrict__ z,
-                           const double* __restrict__ scal, size_t n) {
+                           const double* __restrict__ scal, size_t n,
+                           const long long* __restrict__ seg) {
   const int rr = blockIdx.y;
   if (scal[(size_t)rr * NSCAL + S_ACTIVE] == 0.0) return;
   const float b = (float)scal[(size_t)rr * NSCAL + S_BETA];
-  const size_t off = (size_t)rr * n;
+  size_t off;
+  span(seg, rr, n, off, n);
   for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB)
     p[off + i] = z[off + i] + b * p[off + i];
 }
@@ -154,28 +174,30 @@ void launch_fill_f32(float* p, size_t n, hipStream_t st) {
 void launch_copy_f32(float* d, const float* s, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(copy_f32_k, dim3(nb(n)), dim3(VB), 0, st, d, s, n);
 }
-void launch_dot_ff(int nr, const float* a, const float* b, size_t n, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((dotm_k<float, float>), dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part);
+void launch_dot_ff(int nr, const float* a, const float* b, size_t n, double* part, hipStream_t st,
+                   const long long* seg) {
+  hipLaunchKernelGGL((dotm_k<float, float>), dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part, seg);
 }
-void launch_dot_df(int nr, const double* a, const float* b, size_t n, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((dotm_k<double, float>), dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part);
+void launch_dot_df(int nr, const double* a, const float* b, size_t n, double* part, hipStream_t st,
+                   const long long* seg) {
+  hipLaunchKernelGGL((dotm_k<double, float>), dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part, seg);
 }
 void launch_dot2_f32(int nr, const float* r, const float* z, const float* q, size_t n, double* p1,
-                     double* p2, hipStream_t st) {
-  hipLaunchKernelGGL(dot2_k, dim3(RED_BLOCKS, nr), dim3(VB), 0, st, r, z, q, n, p1, p2);
+                     double* p2, hipStream_t st, const long long* seg) {
+  hipLaunchKernelGGL(dot2_k, dim3(RED_BLOCKS, nr), dim3(VB), 0, st, r, z, q, n, p1, p2, seg);
 }
 void launch_cg_beta_flex(int nr, const double* p1, const double* p2, double* scal, hipStream_t st) {
   hipLaunchKernelGGL(cg_beta_flex_k, dim3(nr), dim3(VB), 0, st, p1, p2, scal);
 }
 void launch_cg_xr_f32(int nr, float* x, float* r, const float* p, const float* q,
-                      const double* scal, size_t n, hipStream_t st) {
+                      const double* scal, size_t n, hipStream_t st, const long long* seg) {
   unsigned b = nb(n) > 2048 ? 2048 : nb(n);
-  hipLaunchKernelGGL(cg_xr_f32_k, dim3(b, nr), dim3(VB), 0, st, x, r, p, q, scal, n);
+  hipLaunchKernelGGL(cg_xr_f32_k, dim3(b, nr), dim3(VB), 0, st, x, r, p, q, scal, n, seg);
 }
 void launch_cg_p_f32(int nr, float* p, const float* z, const double* scal, size_t n,
-                     hipStream_t st) {
+                     hipStream_t st, const long long* seg) {
   unsigned b = nb(n) > 2048 ? 2048 : nb(n);
-  hipLaunchKernelGGL(cg_p_f32_k, dim3(b, nr), dim3(VB), 0, st, p, z, scal, n);
+  hipLaunchKernelGGL(cg_p_f32_k, dim3(b, nr), dim3(VB), 0, st, p, z, scal, n, seg);
 }
 
 }  // namespace ga

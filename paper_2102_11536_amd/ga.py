@@ -25,7 +25,7 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
-           "ga_batch_tune", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
+           "ga_batch_tune", "ga_batch_set_precision", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
            "ga_mp_info", "ga_mp_apply", "ga_mp_mass_solve", "ga_mp_init_state", "ga_mp_step"]
 
 
@@ -91,6 +91,7 @@ def load_library(path=LIB_PATH):
     lib.ga_batch_destroy.argtypes = [vp]
     lib.ga_batch_info.argtypes = [vp, lp, lp, lp]
     lib.ga_batch_tune.argtypes = [vp, i, ctypes.POINTER(d), vp]
+    lib.ga_batch_set_precision.argtypes = [vp, i, vp]
     lib.ga_batch_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
     lib.ga_batch_step.argtypes = [vp, ctypes.POINTER(vp), i, i, ctypes.POINTER(i), vp]
     lib.ga_mp_create.argtypes = [ctypes.POINTER(i), i, i, ctypes.POINTER(vp), i, d, d, d, i, vp,
@@ -451,6 +452,11 @@ def ga_batch_graph_replays(batch):
     r = ctypes.c_longlong()
     _check(_lib.ga_batch_info(batch.h, None, None, ctypes.byref(r)))
     return r.value
+
+
+def ga_batch_set_precision(batch, prec):
+    """GA_FP64 or GA_FP32 (FP32 inner PCG inside FP64 refinement) mass solves."""
+    _check(_lib.ga_batch_set_precision(batch.h, int(prec), _stream()))
 
 
 def ga_batch_tune(batch, reps=5):

@@ -47,8 +47,10 @@ def _tau(pts, rho=0.5):
     return 0.5 * np.sqrt(ga.ga_stability_limit(rho) / lam)
 
 
-def _run_batch(pts, U0s, k, tau, nsteps, use_graph=True, tune=False, rtol=1e-12):
+def _run_batch(pts, U0s, k, tau, nsteps, use_graph=True, tune=False, rtol=1e-12, prec=ga.GA_FP64):
     b = ga.ga_batch_create(pts, k, 0.5, tau, rtol=rtol)
+    if prec != ga.GA_FP64:
+        ga.ga_batch_set_precision(b, prec)
     if tune:
         ga.ga_batch_tune(b, reps=2)
     U = _t(np.concatenate(U0s))
@@ -125,6 +127,85 @@ def test_graph_replays_match_eager():
     for step in range(1, 7):
         for s in range(3 * k):
             assert rel(hg[step][s], he[step][s]) < 1e-13, (step, s)
+
+
+# ---- FP32 inner PCG inside FP64 refinement, batched (Sec. 6.1) ----
+
+def test_batch_mixed_matches_oracle():
+    _say("mixed batch vs oracle")
+    k = 2
+    pts, U0s = _setup(SMALL)
+    tau = _tau(pts)
+    b, hist, its = _run_batch(pts, U0s, k, tau, 8, prec=ga.GA_FP32)
+    assert ga.ga_batch_graph_replays(b) > 0
+    worst = 0.0
+    for r, (n, p, gseed, _) in enumerate(SMALL):
+        pr = OracleProblem(3, n, p, geometry="random", seed=gseed)
+        ora = pr.run(U0s[r], 0 * U0s[r], k, 0.5, tau, 8)
+        M = pr.M
+        for step in (1, 4, 8):
+            for s in range(3 * k):
+                g = _split(b, hist[step][s])[r]
+                o = ora[step][s - 2]
+                d = g - o
+                e = np.sqrt(d @ (M @ d)) / max(np.sqrt(o @ (M @ o)), 1e-300)
+                worst = max(worst, e)
+                # the refinement reaches the FP64 tolerance; FP32 enters only the corrections
+                assert e < 1e-10, (r, step, s, e)
+    _say("  worst M-norm error", worst, "inner iterations per system", its.mean(axis=0).tolist())
+
+
+def test_batch_mixed_equals_separate_mixed_patches():
+    specs = workloads.multipatch_specs(R=8, n_min=4, n_max=12, seed=5)
+    _say("mixed batch vs separate", specs)
+    k = 2
+    pts, U0s = _setup(specs)
+    tau = _tau(pts)
+    b, hist, _ = _run_batch(pts, U0s, k, tau, 5, tune=True, prec=ga.GA_FP32)
+    for r, pt in enumerate(pts):
+        integ = ga.ga_integrator_create(pt, k, 0.5, tau, rtol=1e-12, prec=ga.GA_FP32)
+        state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+        U = _t(U0s[r])
+        ga.ga_init_state(integ, U, torch.zeros_like(U), state)
+        ga.ga_step(integ, state, 5)
+        for s in range(3 * k):
+            # both stop at relative tolerance 1e-12 by different FP32 paths
+            assert rel(_split(b, hist[-1][s])[r], _np(state[s])) < 1e-10, (r, s)
+
+
+def test_batch_mixed_graph_matches_eager():
+    _say("mixed graph vs eager")
+    k = 2
+    pts, U0s = _setup(SMALL[:3])
+    tau = _tau(pts)
+    bg, hg, ig = _run_batch(pts, U0s, k, tau, 5, use_graph=True, prec=ga.GA_FP32)
+    be, he, ie = _run_batch(pts, U0s, k, tau, 5, use_graph=False, prec=ga.GA_FP32)
+    assert ga.ga_batch_graph_replays(bg) >= 5 and ga.ga_batch_graph_replays(be) == 0
+    assert np.array_equal(ig, ie)
+    for step in range(1, 6):
+        for s in range(3 * k):
+            assert rel(hg[step][s], he[step][s]) < 1e-13, (step, s)
+
+
+def test_batch_precision_switch_back():
+    # FP32 then FP64 again on the same batch: the FP64 solve is the plain one
+    k = 2
+    pts, U0s = _setup(SMALL[:2])
+    tau = _tau(pts)
+    b0, h0, _ = _run_batch(pts, U0s, k, tau, 3)
+    b = ga.ga_batch_create(pts, k, 0.5, tau, rtol=1e-12)
+    ga.ga_batch_set_precision(b, ga.GA_FP32)
+    ga.ga_batch_set_precision(b, ga.GA_FP64)
+    U = _t(np.concatenate(U0s))
+    state = [torch.zeros(b.n_total, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    ga.ga_batch_init_state(b, U, torch.zeros_like(U), state)
+    ga.ga_batch_step(b, state, 3)
+    for s in range(3 * k):
+        # same FP64 launches; shared coefficients are summed by atomics, so the
+        # order of the additions (and the last bits) may differ between runs
+        assert rel(_np(state[s]), h0[-1][s]) < 1e-12
+    with pytest.raises(ga.GAError):
+        ga.ga_batch_set_precision(b, 7)
 
 
 def test_batch_errors():
