@@ -266,17 +266,20 @@ def main():
         nets = [ga.GNet(w) for w in params]
         learned_note = {"weights": os.path.relpath(wfile, ROOT), "trajectories": meta["trajectories"],
                         "heldout": meta.get("heldout")}
-    path_list = [("fp64_zero_guess", ga.GA_FP64, ga.GA_GUESS_ZERO),
-                 ("fp64_prev_guess", ga.GA_FP64, ga.GA_GUESS_PREV),
-                 ("fp64_extrap_guess", ga.GA_FP64, ga.GA_GUESS_EXTRAP),
-                 ("mixed_fp32_zero_guess", ga.GA_FP32, ga.GA_GUESS_ZERO),
-                 ("mixed_fp32_extrap_guess", ga.GA_FP32, ga.GA_GUESS_EXTRAP)]
+    H, D = ga.GA_CG_HOST, ga.GA_CG_DEVICE
+    path_list = [("fp64_zero_guess", ga.GA_FP64, ga.GA_GUESS_ZERO, H),
+                 ("fp64_zero_guess_device_ctl", ga.GA_FP64, ga.GA_GUESS_ZERO, D),
+                 ("fp64_prev_guess", ga.GA_FP64, ga.GA_GUESS_PREV, H),
+                 ("fp64_extrap_guess", ga.GA_FP64, ga.GA_GUESS_EXTRAP, H),
+                 ("mixed_fp32_zero_guess", ga.GA_FP32, ga.GA_GUESS_ZERO, H),
+                 ("mixed_fp32_extrap_guess", ga.GA_FP32, ga.GA_GUESS_EXTRAP, H)]
     if nets:
-        path_list += [("fp64_learned_guess", ga.GA_FP64, ga.GA_GUESS_LEARNED),
-                      ("mixed_fp32_learned_guess", ga.GA_FP32, ga.GA_GUESS_LEARNED)]
+        path_list += [("fp64_learned_guess", ga.GA_FP64, ga.GA_GUESS_LEARNED, H),
+                      ("mixed_fp32_learned_guess", ga.GA_FP32, ga.GA_GUESS_LEARNED, H)]
     paths = {}
     ref_state = None
-    for name, prec, guess in path_list:
+    for name, prec, guess, cg in path_list:
+        ga.ga_patch_set_cg(pt, cg)
         integ = ga.ga_integrator_create(pt, k, rho, tau, rtol=args.rtol, maxit=200, prec=prec,
                                         guess=guess)
         if guess == ga.GA_GUESS_LEARNED:
@@ -298,6 +301,7 @@ def main():
                 for kind in (ga.PROF_MASS, ga.PROF_STIFF, ga.PROF_PINV, ga.PROF_GUESS)}
         sstats = ga.ga_solve_stats(pt)
         ga.ga_profile(False)
+        ga.ga_patch_set_cg(pt, ga.GA_CG_HOST)
         if ref_state is None:
             ref_state = state
             err = 0.0

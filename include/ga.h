@@ -130,6 +130,25 @@ int ga_apply_Pinv(ga_patch* patch, int nrhs, const double* r_dev, double* z_dev,
  * (dense inverse products always). */
 enum { GA_PINV_AUTO = 0, GA_PINV_DENSE = 1 };
 int ga_patch_set_pinv(ga_patch* patch, int mode);
+/*
+ * PCG control of a patch's FP64 solves (Sec. 5.6 PCG; the control is an
+ * implementation choice and gives the same iterates):
+ *   GA_CG_HOST    the host reads the convergence flags after every iteration;
+ *   GA_CG_DEVICE  (default) the convergence test stays on the device: the mass apply,
+ *                 the preconditioner, the fills and dots of every iteration are
+ *                 gated by the per-system flags, so a converged system costs
+ *                 nothing.  The host enqueues as many iterations as the
+ *                 previous solve with the same number of right-hand sides
+ *                 needed (the right-hand sides expected to be active share
+ *                 one operator launch, the others get gated launches of their
+ *                 own), then reads the flags once and continues per iteration
+ *                 only if a system is still active.  3-D patches with the
+ *                 banded preconditioner; otherwise the host control is used.
+ * ga_cg_stats: iterations enqueued ahead so far and host reads of the flags.
+ */
+enum { GA_CG_HOST = 0, GA_CG_DEVICE = 1 };
+int ga_patch_set_cg(ga_patch* patch, int mode);
+int ga_cg_stats(const ga_patch* patch, long long* spec_iters, long long* host_checks);
 
 /*
  * ga_mass_solve -- PCG for M x_j = b_j, j < nrhs (Sec. 5.6; solver settings of

@@ -190,6 +190,51 @@ struct SolveBufs {
   double *r, *z, *p, *q, *t0, *t1;
 };
 
+// One PCG iteration with device-side control: every launch is gated by the
+// per-system flags (a converged system is skipped on the device).  The
+// systems the schedule expects to be active at iteration `it` share one mass
+// apply; every other system gets a gated launch of its own, which returns at
+// once if that system has converged, so the iterates never depend on the
+// schedule.
+int gated_iteration(ga_patch* pt, int nr, int it, double* x, const SolveBufs& w, hipStream_t st) {
+  const size_t n = pt->n_free;
+  const double* gate = pt->scal;
+  double* partA = pt->red;
+  launch_fill_gated(nr, w.q, n, gate, st);
+  int a = nr, b = 0;
+  for (int r = 0; r < nr; ++r)
+    if (pt->hint[r] > it) { a = std::min(a, r); b = r + 1; }
+  if (a >= b) { a = 0; b = nr; }
+  {
+    ProfScope prof(0, st);
+    int rc = 0;
+    for (int r0 = a; r0 < b && !rc; r0 += MAX_NR) {
+      const int c = std::min(MAX_NR, b - r0);
+      rc = launch_op3d(0, c, pt, w.p + (size_t)r0 * n, w.q + (size_t)r0 * n, 1.0, st,
+                       gate + (size_t)r0 * NSCAL);
+    }
+    for (int r = 0; r < nr && !rc; ++r)
+      if (r < a || r >= b)
+        rc = launch_op3d(0, 1, pt, w.p + (size_t)r * n, w.q + (size_t)r * n, 1.0, st,
+                         gate + (size_t)r * NSCAL);
+    if (check_launch(rc, "gated mass apply")) return GA_EDEVICE;
+  }
+  launch_dot_partial(nr, w.p, w.q, n, partA, st, gate);
+  launch_cg_alpha(nr, partA, pt->scal, st);
+  launch_cg_xr(nr, x, w.r, w.p, w.q, pt->scal, n, st);
+  {
+    ProfScope prof(2, st);
+    const double* cb[3] = {pt->cb[0], pt->cb[1], pt->cb[2]};
+    if (launch_pinv_band<double>(pt->dim, pt->p, pt->mf, nr, w.r, w.z, w.t0, w.t1, cb, pt->s,
+                                 (long long)n, st, gate) != 0)
+      return check_launch(-1, "gated preconditioner");
+  }
+  launch_dot_partial(nr, w.r, w.z, n, partA, st, gate);
+  launch_cg_beta(nr, partA, pt->scal, st);
+  launch_cg_p(nr, w.p, w.z, pt->scal, n, st);
+  return check_launch(0, "gated pcg iteration");
+}
+
 // PCG for nr right-hand sides; x holds the guess (zero_guess: ignored and set to 0)
 int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, int maxit,
                bool zero_guess, int* iters_out, double* relres_out, hipStream_t st) {
@@ -227,10 +272,22 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
   launch_copy(w.p, w.z, tot, st);
   if (check_launch(0, "pcg start")) return GA_EDEVICE;
   int it = 0;
+  // device-side control: enqueue the iterations the last solve of nr systems
+  // needed without reading the flags in between
+  const bool dev = pt->cg_ctrl == GA_CG_DEVICE && pt->dim == 3 && pt->pinv_mode != GA_PINV_DENSE &&
+                   nr <= 16 && pt->hint_nr == nr && pinv_band_fits(3, pt->p, pt->mf, sizeof(double));
+  if (dev) {
+    int hmax = 0;
+    for (int r = 0; r < nr; ++r) hmax = std::max(hmax, pt->hint[r]);
+    for (; it < std::min(hmax, maxit); ++it)
+      if ((rc = gated_iteration(pt, nr, it, x, w, st))) return rc;
+    pt->n_spec += it;
+  }
   for (;; ++it) {
     GA_TRY_HIP(hipMemcpyAsync(pt->host_scal, pt->scal, sizeof(double) * NSCAL * nr,
                               hipMemcpyDeviceToHost, st));
     GA_TRY_HIP(hipStreamSynchronize(st));
+    pt->n_checks += 1;
     // right-hand sides a .. b-1 span the active ones; the operator and the
     // preconditioner skip converged ones outside that range (their step
     // sizes are zero, so their q and z are never used)
@@ -263,7 +320,9 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
     if (relres_out) relres_out[r] = s[S_BN2] > 0 ? std::sqrt(std::fabs(s[S_RZ] / s[S_BN2])) : 0.0;
     if (s[S_ACTIVE] != 0.0) ok = false;
     if (!std::isfinite(s[S_RZ])) ok = false;
+    if (r < 16) pt->hint[r] = (int)s[S_ITERS];
   }
+  pt->hint_nr = nr;
   if (!ok) {
     set_error("PCG did not converge within maxit");
     return GA_ENOCONV;
@@ -672,6 +731,20 @@ int ga_patch_info(const ga_patch* pt, long long* n_free, long long* n_quad, int*
   if (n_free) *n_free = pt->n_free;
   if (n_quad) *n_quad = pt->n_quad;
   if (mf) for (int a = 0; a < 3; ++a) mf[a] = a < pt->dim ? pt->mf[a] : 1;
+  return GA_OK;
+}
+
+int ga_patch_set_cg(ga_patch* pt, int mode) {
+  if (!pt) { set_error("null patch"); return GA_EINVAL; }
+  if (mode != GA_CG_HOST && mode != GA_CG_DEVICE) { set_error("bad PCG control mode"); return GA_EINVAL; }
+  pt->cg_ctrl = mode;
+  return GA_OK;
+}
+
+int ga_cg_stats(const ga_patch* pt, long long* spec_iters, long long* host_checks) {
+  if (!pt) { set_error("null patch"); return GA_EINVAL; }
+  if (spec_iters) *spec_iters = pt->n_spec;
+  if (host_checks) *host_checks = pt->n_checks;
   return GA_OK;
 }
 

@@ -107,6 +107,10 @@ struct ga_patch {
   int ntk[2] = {1, 1}, ntm[2] = {1, 1};  // 3-D xy columns: stiffness and mass layouts
   int ze = 0;                     // element layers per workgroup along z (0: automatic)
   int pinv_mode = GA_PINV_AUTO;   // preconditioner algorithm (ga_patch_set_pinv)
+  int cg_ctrl = GA_CG_DEVICE;     // PCG control (ga_patch_set_cg)
+  int hint_nr = 0;                // iterations per right-hand side of the last FP64 solve
+  int hint[16] = {0};             //   of hint_nr right-hand sides (speculative schedule)
+  long long n_spec = 0, n_checks = 0;   // iterations enqueued ahead, host convergence reads
   long long n_free = 0, n_quad = 0, n_tiles = 0, qp_per_tile = 0;
   ga::Axis1D ax[3];
   // device data

@@ -32,7 +32,8 @@ struct OpGroupEntry {
 };
 
 int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
-                hipStream_t st);
+                hipStream_t st,
+                const double* gate = nullptr);
 long long op3d_tiles(int mode, const ga_patch* pt, int ze);
 int op3d_default_ze(int mode, const ga_patch* pt);
 OpGroupEntry op3d_group_entry(int mode, const ga_patch* pt, int ze, long long off, int tile0,
@@ -52,6 +53,10 @@ int launch_geo2d(const ga_patch* pt, const double* ctrl, const double* const* w,
                  hipStream_t st);
 
 void launch_fill(double* p, double v, size_t n, hipStream_t st);
+// device-side control: gate = the CG scalars of right-hand side 0 (NSCAL per
+// right-hand side); right-hand sides whose S_ACTIVE is 0 are left alone
+void launch_fill_gated(int nr, double* y, size_t n, const double* gate, hipStream_t st);
+bool pinv_band_fits(int dim, int p, const int* mf, size_t elem);
 void launch_copy(double* dst, const double* src, size_t n, hipStream_t st);
 void launch_scale_mul(double* out, const double* in, const double* s, int nr, size_t n, hipStream_t st);
 void launch_gemm(int M, int N, int K, const double* X, long long ldx, long long sX,
@@ -82,14 +87,15 @@ int pinv_ra_class(int L);
 // banded-Cholesky preconditioner (0 launched, 1 does not fit the LDS staging, -1 error)
 template <typename S>
 int launch_pinv_band(int dim, int p, const int* mf, int nr, const S* r, S* z, S* t0, S* t1,
-                     const S* const* cb, const S* s, long long n_free, hipStream_t st);
+                     const S* const* cb, const S* s, long long n_free, hipStream_t st,
+                     const double* gate = nullptr);
 template <typename S>
 void launch_pinv_group(int pass, int ra_class, const PinvEntry* ents, int nent, int nblk, int nr,
                        const S* in, S* out, long long stride, hipStream_t st);
 void launch_scaling(double* s, const double* diagM, const double* dh0, const double* dh1,
                     const double* dh2, int mf0, int mf1, int mf2, hipStream_t st);
 void launch_dot_partial(int nr, const double* a, const double* b, size_t n, double* part,
-                        hipStream_t st);
+                        hipStream_t st, const double* gate = nullptr);
 void launch_cg_start(int nr, const double* part_rz, const double* part_bn, double* scal,
                      double tol2, hipStream_t st);
 void launch_cg_fallback(int nr, double* x, double* r, double* z, const double* b, const double* zb,

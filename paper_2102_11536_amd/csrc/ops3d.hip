@@ -489,7 +489,15 @@ op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
             const double* __restrict__ tB0, const double* __restrict__ tB1,
             const double* __restrict__ tB2, const double* __restrict__ tD0,
             const double* __restrict__ tD1, const double* __restrict__ tD2,
-            Geo3 g, int ze, long long n_free, S alpha) {
+            Geo3 g, int ze, long long n_free, S alpha, const double* __restrict__ gate) {
+  // device-side control: with a gate (the CG scalars of the launch's first
+  // right-hand side), the launch does nothing once all its systems have converged
+  if (gate) {
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) any |= gate[r * NSCAL + S_ACTIVE] != 0.0;
+    if (!any) return;
+  }
   op3d_body<P, TE, MODE, NR, S>(x, y, fac, tB0, tB1, tB2, tD0, tD1, tD2, g, ze, n_free, alpha,
                                 xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -604,7 +612,7 @@ static int pick_ze(long long ntxy, int nz, int floor_ze) {
 
 template <int P, typename S>
 static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const S* x, S* y, S alpha,
-                         const S* fac, hipStream_t st) {
+                         const S* fac, hipStream_t st, const double* gate = nullptr) {
   constexpr int TK = te3_stiff(P), TM = te3_mass(P);
   Geo3 g;
   for (int a = 0; a < 3; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; g.lo[a] = pt->lo[a]; }
@@ -619,7 +627,7 @@ static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const S* x, S* y,
 #define GA_OP3(TE, MODE, NRV)                                                               \
   hipLaunchKernelGGL((op3d_kernel<P, TE, MODE, NRV, S>), grid, dim3(Tile3<P, TE>::NT), 0, st, \
                      x, y, fac, B[0], B[1], B[2], pt->tabD[0], pt->tabD[1], pt->tabD[2], g,   \
-                     ze, pt->n_free, alpha)
+                     ze, pt->n_free, alpha, gate)
   if (mode == 0) {
     if (nr == 1) GA_OP3(TM, 0, 1); else if (nr == 2) GA_OP3(TM, 0, 2); else GA_OP3(TM, 0, 3);
   } else if (mode == 1) {
@@ -636,13 +644,13 @@ static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const S* x, S* y,
 }
 
 int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
-                hipStream_t st) {
+                hipStream_t st, const double* gate) {
   const double* fac = (mode == 1) ? pt->G : pt->W;
   switch (pt->p) {
-    case 1: return launch_op3d_p<1, double>(mode, nr, pt, x, y, alpha, fac, st);
-    case 2: return launch_op3d_p<2, double>(mode, nr, pt, x, y, alpha, fac, st);
-    case 3: return launch_op3d_p<3, double>(mode, nr, pt, x, y, alpha, fac, st);
-    case 4: return launch_op3d_p<4, double>(mode, nr, pt, x, y, alpha, fac, st);
+    case 1: return launch_op3d_p<1, double>(mode, nr, pt, x, y, alpha, fac, st, gate);
+    case 2: return launch_op3d_p<2, double>(mode, nr, pt, x, y, alpha, fac, st, gate);
+    case 3: return launch_op3d_p<3, double>(mode, nr, pt, x, y, alpha, fac, st, gate);
+    case 4: return launch_op3d_p<4, double>(mode, nr, pt, x, y, alpha, fac, st, gate);
   }
   return -1;
 }

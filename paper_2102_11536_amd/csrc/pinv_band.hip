@@ -107,7 +107,10 @@ constexpr int NL = 64;   // lines per workgroup (one per sweeping thread)
 template <int P, typename S>
 __global__ void __launch_bounds__(WT)
 band_row_k(const S* __restrict__ in, S* __restrict__ out, const S* __restrict__ cb0, int L0,
-           long long rows, long long n_free, const S* __restrict__ si, const S* __restrict__ so) {
+           long long rows, long long n_free, const S* __restrict__ si, const S* __restrict__ so,
+           const double* __restrict__ gate) {
+  // with a gate, a converged right-hand side (blockIdx.y) is skipped
+  if (gate && gate[(size_t)blockIdx.y * NSCAL + S_ACTIVE] == 0.0) return;
   extern __shared__ unsigned char smem_raw[];
   const int RS = L0 | 1;  // odd row stride
   S* pl = reinterpret_cast<S*>(smem_raw);
@@ -170,7 +173,8 @@ template <int P, typename S>
 __global__ void __launch_bounds__(CT)
 band_col_k(const S* __restrict__ in, S* __restrict__ out, const S* __restrict__ cb,
            long long nlines, long long per_plane, long long plane_stride, long long stride, int L,
-           long long n_free, const S* __restrict__ so) {
+           long long n_free, const S* __restrict__ so, const double* __restrict__ gate) {
+  if (gate && gate[(size_t)blockIdx.y * NSCAL + S_ACTIVE] == 0.0) return;
   extern __shared__ unsigned char smem_raw[];
   S* ct = reinterpret_cast<S*>(smem_raw);       // factor table, (L + P) x (P + 1)
   const int lane = threadIdx.x;
@@ -187,7 +191,7 @@ constexpr size_t LDS_MAX_BYTES = 152 * 1024;
 
 template <int P, typename S>
 int launch_p(int dim, const int* mf, int nr, const S* r, S* z, S* t0, S* t1, const S* const* cb,
-             const S* s, long long n_free, hipStream_t st) {
+             const S* s, long long n_free, hipStream_t st, const double* gate) {
   const long long L0 = mf[0], L1 = mf[1], L2 = dim == 3 ? mf[2] : 1;
   const size_t row_bytes = ((size_t)NL * (L0 | 1) + (size_t)(L0 + P) * (P + 1)) * sizeof(S);
   const long long Lc = std::max(L1, L2);
@@ -204,19 +208,19 @@ int launch_p(int dim, const int* mf, int nr, const S* r, S* z, S* t0, S* t1, con
   const long long rows = L1 * L2;
   // x: r -> t1 (input scaling)
   hipLaunchKernelGGL((band_row_k<P, S>), dim3((unsigned)((rows + NL - 1) / NL), nr), dim3(WT),
-                     row_bytes, st, r, t1, cb[0], (int)L0, rows, n_free, s, (const S*)nullptr);
+                     row_bytes, st, r, t1, cb[0], (int)L0, rows, n_free, s, (const S*)nullptr, gate);
   // y: t1 -> (3-D: t0; 2-D: z with the output scaling)
   const long long ny = L0 * L2;
   hipLaunchKernelGGL((band_col_k<P, S>), dim3((unsigned)((ny + CT - 1) / CT), nr), dim3(CT),
                      (size_t)(L1 + P) * (P + 1) * sizeof(S), st, t1,
                      dim == 3 ? t0 : z, cb[1], ny, L0, L0 * L1, L0, (int)L1, n_free,
-                     dim == 3 ? (const S*)nullptr : s);
+                     dim == 3 ? (const S*)nullptr : s, gate);
   if (dim == 3) {
     // z: t0 -> z (output scaling)
     const long long nz = L0 * L1;
     hipLaunchKernelGGL((band_col_k<P, S>), dim3((unsigned)((nz + CT - 1) / CT), nr), dim3(CT),
                        (size_t)(L2 + P) * (P + 1) * sizeof(S), st, t0, z, cb[2],
-                       nz, nz, 0LL, nz, (int)L2, n_free, s);
+                       nz, nz, 0LL, nz, (int)L2, n_free, s, gate);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -227,21 +231,30 @@ int launch_p(int dim, const int* mf, int nr, const S* r, S* z, S* t0, S* t1, con
 // -1: launch error.  t0, t1: scratch vectors like z.
 template <typename S>
 int launch_pinv_band(int dim, int p, const int* mf, int nr, const S* r, S* z, S* t0, S* t1,
-                     const S* const* cb, const S* s, long long n_free, hipStream_t st) {
+                     const S* const* cb, const S* s, long long n_free, hipStream_t st,
+                     const double* gate) {
   switch (p) {
-    case 1: return launch_p<1, S>(dim, mf, nr, r, z, t0, t1, cb, s, n_free, st);
-    case 2: return launch_p<2, S>(dim, mf, nr, r, z, t0, t1, cb, s, n_free, st);
-    case 3: return launch_p<3, S>(dim, mf, nr, r, z, t0, t1, cb, s, n_free, st);
-    case 4: return launch_p<4, S>(dim, mf, nr, r, z, t0, t1, cb, s, n_free, st);
+    case 1: return launch_p<1, S>(dim, mf, nr, r, z, t0, t1, cb, s, n_free, st, gate);
+    case 2: return launch_p<2, S>(dim, mf, nr, r, z, t0, t1, cb, s, n_free, st, gate);
+    case 3: return launch_p<3, S>(dim, mf, nr, r, z, t0, t1, cb, s, n_free, st, gate);
+    case 4: return launch_p<4, S>(dim, mf, nr, r, z, t0, t1, cb, s, n_free, st, gate);
   }
   return 1;
 }
 
+bool pinv_band_fits(int dim, int p, const int* mf, size_t elem) {
+  if (p < 1 || p > 4) return false;
+  const long long L0 = mf[0], L1 = mf[1], L2 = dim == 3 ? mf[2] : 1;
+  const size_t row_bytes = ((size_t)NL * (L0 | 1) + (size_t)(L0 + p) * (p + 1)) * elem;
+  const size_t col_bytes = (size_t)(std::max(L1, L2) + p) * (p + 1) * elem;
+  return row_bytes <= LDS_MAX_BYTES && col_bytes <= LDS_MAX_BYTES;
+}
+
 template int launch_pinv_band<double>(int, int, const int*, int, const double*, double*, double*,
                                       double*, const double* const*, const double*, long long,
-                                      hipStream_t);
+                                      hipStream_t, const double*);
 template int launch_pinv_band<float>(int, int, const int*, int, const float*, float*, float*,
                                      float*, const float* const*, const float*, long long,
-                                     hipStream_t);
+                                     hipStream_t, const double*);
 
 }  // namespace ga

@@ -36,6 +36,16 @@ __global__ void fill_k(double* p, double v, size_t n) {
     p[i] = v;
 }
 
+// y_r = 0 for the right-hand sides r = blockIdx.y that are still active
+__global__ void fill_gated_k(double* y, size_t n, const double* __restrict__ gate) {
+  const int r = blockIdx.y;
+  if (gate[(size_t)r * NSCAL + S_ACTIVE] == 0.0) return;
+  double* yr = y + (size_t)r * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    yr[i] = 0.0;
+}
+
 __global__ void copy_k(double* __restrict__ d, const double* __restrict__ s, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -126,9 +136,13 @@ __global__ void scaling_k(double* s, const double* __restrict__ d, const double*
 // part[r][block] = partial sum of a_r . b_r
 __global__ void __launch_bounds__(VB)
 dot_partial_k(const double* __restrict__ a, const double* __restrict__ b, size_t n,
-              double* __restrict__ part) {
+              double* __restrict__ part, const double* __restrict__ gate) {
   __shared__ double sh[VB / 64];
   const int r = blockIdx.y;
+  if (gate && gate[(size_t)r * NSCAL + S_ACTIVE] == 0.0) {   // converged: partial unused
+    if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   const double* ar = a + (size_t)r * n;
   const double* br = b + (size_t)r * n;
   double s = 0.0;
@@ -404,6 +418,10 @@ inline unsigned nblocks(size_t n) {
 void launch_fill(double* p, double v, size_t n, hipStream_t st) {
   if (n) hipLaunchKernelGGL(fill_k, dim3(nblocks(n)), dim3(VB), 0, st, p, v, n);
 }
+void launch_fill_gated(int nr, double* y, size_t n, const double* gate, hipStream_t st) {
+  unsigned b = nblocks(n) > 2048 ? 2048 : nblocks(n);
+  if (n) hipLaunchKernelGGL(fill_gated_k, dim3(b, nr), dim3(VB), 0, st, y, n, gate);
+}
 void launch_copy(double* d, const double* s, size_t n, hipStream_t st) {
   if (n) hipLaunchKernelGGL(copy_k, dim3(nblocks(n)), dim3(VB), 0, st, d, s, n);
 }
@@ -430,8 +448,8 @@ void launch_scaling(double* s, const double* d, const double* h0, const double* 
                      mf2);
 }
 void launch_dot_partial(int nr, const double* a, const double* b, size_t n, double* part,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(dot_partial_k, dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part);
+                        hipStream_t st, const double* gate) {
+  hipLaunchKernelGGL(dot_partial_k, dim3(RED_BLOCKS, nr), dim3(VB), 0, st, a, b, n, part, gate);
 }
 void launch_gather(int nr, const double* xg, long long Ng, const int* map, long long Nl, double* xl,
                    hipStream_t st) {

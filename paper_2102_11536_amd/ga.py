@@ -16,6 +16,7 @@ GA_GUESS_ZERO, GA_GUESS_PREV, GA_GUESS_EXTRAP, GA_GUESS_LEARNED = 0, 1, 2, 3
 GA_GNET_NPARAM = 32033
 GA_FP64, GA_FP32 = 0, 1
 GA_PINV_AUTO, GA_PINV_DENSE = 0, 1
+GA_CG_HOST, GA_CG_DEVICE = 0, 1
 
 EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
            "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
@@ -25,7 +26,7 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
-           "ga_batch_tune", "ga_batch_set_precision", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
+           "ga_batch_tune", "ga_batch_set_precision", "ga_patch_set_cg", "ga_cg_stats", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
            "ga_mp_info", "ga_mp_apply", "ga_mp_mass_solve", "ga_mp_init_state", "ga_mp_step"]
 
 
@@ -72,6 +73,8 @@ def load_library(path=LIB_PATH):
     ip, fp = ctypes.POINTER(i), ctypes.POINTER(ctypes.c_float)
     lib.ga_stage_solution.argtypes = [vp, i, i, dp, vp]
     lib.ga_patch_set_pinv.argtypes = [vp, i]
+    lib.ga_patch_set_cg.argtypes = [vp, i]
+    lib.ga_cg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     lib.ga_integrator_set_damping.argtypes = [vp, d, d]
     lib.ga_stage_times.argtypes = [vp, d, ctypes.POINTER(d)]
     lib.ga_init_state_forced.argtypes = [vp, dp, dp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
@@ -171,6 +174,18 @@ def ga_setup_patch_ex(dim, n_el, p, ctrl, dirichlet_faces):
 
 def ga_patch_set_pinv(patch, mode):
     _check(_lib.ga_patch_set_pinv(patch.h, int(mode)))
+
+
+def ga_patch_set_cg(patch, mode):
+    """GA_CG_HOST or GA_CG_DEVICE control of the patch's FP64 PCG solves."""
+    _check(_lib.ga_patch_set_cg(patch.h, int(mode)))
+
+
+def ga_cg_stats(patch):
+    """(iterations enqueued ahead of a convergence read, host reads of the flags)."""
+    a, b = ctypes.c_longlong(), ctypes.c_longlong()
+    _check(_lib.ga_cg_stats(patch.h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def ga_diag_M(patch, d):
