@@ -56,15 +56,19 @@ def printed_type_k(rb, rs):
     return alpha, beta, omega_b, omega_s
 
 
-def block_params(k, rho):
-    """[(alpha_j, beta_j, gamma_j, alpha_fj)] for j = 1..k (readings above)."""
+def block_params(k, rho, rho_s=None):
+    """[(alpha_j, beta_j, gamma_j, alpha_fj)] for j = 1..k (readings above).
+    rho is rho_b; rho_s (default rho_b) gives the two-parameter family
+    rho_s <= rho_b of the Remark in Sec. 3 (type-j formulas at (-rho_b, -rho_s),
+    type-k at (rho_b, rho_s))."""
+    rs = rho if rho_s is None else rho_s
     out = []
     for j in range(1, k + 1):
         if j < k:
-            a, b, _, _ = printed_type_j(-rho, -rho)
+            a, b, _, _ = printed_type_j(-rho, -rs)
             af = 1.0
         else:
-            a, b, _, _ = printed_type_k(rho, rho)
+            a, b, _, _ = printed_type_k(rho, rs)
             af = 0.0
         out.append((a, b, 0.5 - af + a, af))
     return out
@@ -86,11 +90,11 @@ def stage_arguments(L, T, k):
     return [T[3 * j - 5] if j < k else L[N - 2] for j in range(1, k + 1)]
 
 
-def update(L, T, X, tau, k, rho):
+def update(L, T, X, tau, k, rho, rho_s=None):
     """New state from the stage solutions X_j = L^{a_j}(A_n)^{alpha_j}:
     P_{n,j} from ho3 (X_j = T_{a_j} + alpha_j P_{n,j}), then ho2."""
     new = {}
-    for j, (al, be, ga, _) in enumerate(block_params(k, rho), start=1):
+    for j, (al, be, ga, _) in enumerate(block_params(k, rho, rho_s), start=1):
         a = 3 * j - 3
         P = (X[j - 1] - T[a]) / al
         new[a] = T[a] + P
@@ -111,7 +115,7 @@ def stage_times(t, tau, k, rho):
     return [t + af * tau for (_, _, _, af) in block_params(k, rho)]
 
 
-def step(L, tau, k, rho, apply_K, solve_M, apply_C=None, forcing=None, t=0.0):
+def step(L, tau, k, rho, apply_K, solve_M, apply_C=None, forcing=None, t=0.0, rho_s=None):
     """One time step from t_n = t: predictors, the k stage solves
     M X_j = F^{(a_j)}(t_n + alpha_fj tau) - C Z_j - K Y_j (eq. ho1), and the
     3k-vector update.  apply_C (damping) and forcing(a, t) (the a-th time
@@ -125,7 +129,7 @@ def step(L, tau, k, rho, apply_K, solve_M, apply_C=None, forcing=None, t=0.0):
         ts = stage_times(t, tau, k, rho)
         b = [bj + forcing(3 * j, ts[j]) for j, bj in enumerate(b)]
     X = [solve_M(bj) for bj in b]
-    return update(L, T, X, tau, k, rho)
+    return update(L, T, X, tau, k, rho, rho_s)
 
 
 def initial_state(U0, V0, k, apply_K, solve_M, apply_C=None, forcing=None):
@@ -145,7 +149,7 @@ def initial_state(U0, V0, k, apply_K, solve_M, apply_C=None, forcing=None):
 
 # ---- scalar test equation x'' = -lambda x -----------------------------------
 
-def amplification_matrix(k, rho, theta):
+def amplification_matrix(k, rho, theta, rho_s=None):
     """G with U_{n+1} = G U_n for the scaled scalar state
     [U, tau V, tau^2 A, tau^3 L^1, ...] (tau = 1, lambda = Theta), obtained by
     running ``step`` on unit vectors."""
@@ -154,27 +158,27 @@ def amplification_matrix(k, rho, theta):
     G = np.zeros((len(idx), len(idx)))
     for c, a in enumerate(idx):
         L = {b: np.float64(1.0 if b == a else 0.0) for b in idx}
-        new = step(L, 1.0, k, rho, lambda y: theta * y, lambda b: b)
+        new = step(L, 1.0, k, rho, lambda y: theta * y, lambda b: b, rho_s=rho_s)
         for r, b in enumerate(idx):
             G[r, c] = new[b]
     return G
 
 
-def spectral_radius(k, rho, theta):
-    return float(np.max(np.abs(np.linalg.eigvals(amplification_matrix(k, rho, theta)))))
+def spectral_radius(k, rho, theta, rho_s=None):
+    return float(np.max(np.abs(np.linalg.eigvals(amplification_matrix(k, rho, theta, rho_s)))))
 
 
-def stability_limit(k, rho, hi=8.0, tol=1e-10):
+def stability_limit(k, rho, hi=8.0, tol=1e-10, rho_s=None):
     """Largest Theta = tau^2 lambda up to which the spectral radius stays <= 1
     (scan, then bisection on the first crossing)."""
     grid = np.linspace(1e-3, hi, 4001)
     prev = grid[0]
     for th in grid:
-        if spectral_radius(k, rho, th) > 1 + 1e-9:
+        if spectral_radius(k, rho, th, rho_s) > 1 + 1e-9:
             lo, up = prev, th
             while up - lo > tol:
                 mid = 0.5 * (lo + up)
-                if spectral_radius(k, rho, mid) > 1 + 1e-9:
+                if spectral_radius(k, rho, mid, rho_s) > 1 + 1e-9:
                     up = mid
                 else:
                     lo = mid
