@@ -134,6 +134,78 @@ def bench_multipatch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_dispersion(args):
+    """The 1-D dispersion study (Sec. 6.2): u_tt = omega^2 u_xx, omega = 1/j,
+    exact solution sin(j pi x) cos(pi t); N = 400 elements, p = 4 (C^3), T = 5,
+    tau in {0.05, 1e-3}, the order-2 (k = 1) and order-4 (k = 2) schemes for
+    rho in {0, 0.5, 0.9}.  Every stable wavenumber j (tau^2 lambda_max / j^2 <=
+    Theta_s) up to N is one system of a batched 1-D run; the relative L2 error
+    at T and the batched stepping rate are reported."""
+    import torch
+    from paper_2102_11536_amd import ga
+    N, p, T = 400, 4, 5.0
+    dev = "cuda:0"
+    # lambda_max(M^{-1} K) by power iteration on one system
+    w = ga.Wave1D(N, p, [1.0], 1, 0.5, 0.5, 1.0)
+    v = torch.sin(torch.arange(1, w.m + 1, dtype=torch.float64, device=dev) * 0.7) + 1.0
+    kv, mv = torch.empty_like(v), torch.empty_like(v)
+    lam = 0.0
+    for _ in range(400):
+        ga.ga_wave1d_apply(w, "K", v, kv)
+        ga.ga_wave1d_apply(w, "S", kv, mv)
+        lam = float(torch.dot(v, mv) / torch.dot(v, v))
+        v = mv / torch.linalg.norm(mv)
+    w.close()
+    lam *= 1.01                                  # the power iteration approaches lambda_max from below
+    log(f"[bench] dispersion: lambda_max(M^-1 K) ~ {lam:.6e}")
+    results, dof_steps, secs = {}, 0.0, 0.0
+    for tau in (0.05, 1e-3):
+        nsteps = int(round(T / tau))
+        for k in (1, 2):
+            for rho in (0.0, 0.5, 0.9):
+                j0 = max(1, int(np.ceil(np.sqrt(tau ** 2 * lam / ga.ga_stability_limit2(rho, rho)))))
+                js = np.arange(j0, N + 1, dtype=np.float64)
+                w = ga.Wave1D(N, p, 1.0 / js ** 2, k, rho, rho, tau)
+                f = torch.empty(w.n_total, dtype=torch.float64, device=dev)
+                ga.ga_wave1d_load_sine(w, js, f)
+                U0 = torch.empty_like(f)
+                ga.ga_wave1d_apply(w, "S", f, U0)
+                state = [torch.zeros_like(f) for _ in range(3 * k)]
+                ga.ga_wave1d_init_state(w, U0, torch.zeros_like(U0), state)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ga.ga_wave1d_step(w, state, nsteps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                # u = c sin(j pi x), c = cos(pi T); with the L2 projection P u = c U0 and
+                # (P u - u) orthogonal to the spline space:
+                # ||u_h - u||^2 = (U - c U0)^T M (U - c U0) + c^2 (1/2 - U0^T f)
+                c = np.cos(np.pi * T)
+                d = state[0] - c * U0
+                md = torch.empty_like(d)
+                ga.ga_wave1d_apply(w, "M", d, md)
+                e2 = ((d * md).view(len(js), -1).sum(1)
+                      + c * c * (0.5 - (U0 * f).view(len(js), -1).sum(1)).clamp_min(0.0))
+                err = (torch.sqrt(e2) / (abs(c) * np.sqrt(0.5))).cpu().numpy()
+                key = f"tau={tau:g},k={k},rho={rho:g}"
+                pick = [int(j) for j in (j0, 100, 200, 300, 400) if j >= j0]
+                results[key] = {"j_min": int(j0), "systems": len(js), "steps": nsteps,
+                                "ms_per_step": dt / nsteps * 1e3,
+                                "rel_l2_err_at_T": {str(j): float(err[j - j0]) for j in pick},
+                                "median_err": float(np.median(err)), "max_err": float(np.max(err))}
+                dof_steps += len(js) * w.m * nsteps
+                secs += dt
+                log(f"[bench] dispersion {key}: j >= {j0}, {dt / nsteps * 1e3:.4f} ms/step, "
+                    f"errors {results[key]['rel_l2_err_at_T']}")
+                w.close()
+    out = {"metric": "DOF-steps/s, batched 1-D dispersion study (N=400, p=4, all stable j)",
+           "value": dof_steps / secs, "unit": "DOF-steps/s", "n_gpus": 1, "steps": None, "warmup": 0,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "dispersion_1d_N400_p4_T5", "lambda_max": lam, "runs": results}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_glued(args):
     """C0-glued brick of 2x2x2 patches (48 elements per patch and direction, p=3,
     deformed by the global map), k=2, FP64 PCG with the additive Schwarz
@@ -205,10 +277,11 @@ def main():
                     help="counter-collection mode: run only these operator applies (e.g. K2,M2), "
                          "three times each, then a 1 GiB device copy used to calibrate "
                          "FETCH_SIZE/WRITE_SIZE, and exit")
-    ap.add_argument("--workload", default="cube", choices=["cube", "multipatch", "glued"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "multipatch", "glued", "dispersion"],
                     help="cube: the single-patch headline workload; multipatch: 12 independent "
                          "patches of uneven size and degree stepped as one batch; glued: a 2x2x2 "
-                         "brick of C0-glued patches with the additive Schwarz preconditioner")
+                         "brick of C0-glued patches with the additive Schwarz preconditioner; "
+                         "dispersion: the 1-D study of Sec. 6.2, every wavenumber one system")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
@@ -222,6 +295,8 @@ def main():
         return bench_multipatch(args)
     if args.workload == "glued":
         return bench_glued(args)
+    if args.workload == "dispersion":
+        return bench_dispersion(args)
     n, p, k, rho = args.n, args.p, args.k, 0.5
     dev = "cuda:0"
     log(f"[bench] workload deformed cube p={p} n={n}^3 k={k}: building inputs")

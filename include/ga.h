@@ -35,6 +35,7 @@ typedef struct ga_integrator ga_integrator;
 typedef struct ga_gnet ga_gnet;
 typedef struct ga_batch ga_batch;
 typedef struct ga_mp ga_mp;
+typedef struct ga_wave1d ga_wave1d;
 
 enum {
   GA_OK = 0,
@@ -175,6 +176,9 @@ int ga_lambda_max(ga_patch* patch, int iters, double* lambda_out, void* stream);
 
 /* Theta_s(rho): stability limit on tau^2 lambda of the scheme (all k). */
 double ga_stability_limit(double rho);
+/* Theta_s of the two-parameter family rho_s <= rho_b (Remark in Sec. 3): the
+ * lambda = -1 root of the type-k characteristic polynomial, the same for all k. */
+double ga_stability_limit2(double rho_b, double rho_s);
 
 /*
  * ga_integrator_create -- the order-2k scheme of Sec. 4 (k = 1, 2, 3, 4) with
@@ -391,6 +395,41 @@ int ga_mp_init_state(ga_mp* mp, const double* U0_dev, const double* V0_dev,
                      double* const* state_dev, void* stream);
 /* iters_out: host [nsteps][k] or NULL. */
 int ga_mp_step(ga_mp* mp, double* const* state_dev, int nsteps, int* iters_out, void* stream);
+
+/*
+ * ga_integrator_set_rho -- the two-parameter family (Remark in Sec. 3):
+ * 0 <= rho_s <= rho_b < 1; blocks j < k take the printed type-j formulas at
+ * (-rho_b, -rho_s), block k the type-k formulas at (rho_b, rho_s).  rho_s =
+ * rho_b is the one-parameter scheme of ga_integrator_create.
+ */
+int ga_integrator_set_rho(ga_integrator* integ, double rho_b, double rho_s);
+
+/*
+ * Batched 1-D wave problems (the dispersion study of Sec. 6.2): nsys
+ * independent systems M U_r'' + omega_r^2 K U_r = 0 on (0, 1), homogeneous
+ * Dirichlet data, degree p (C^{p-1}) on n_el uniform elements (identity map),
+ * stepped together by the order-2k scheme with (rho_b, rho_s) and one tau.
+ * On the identity map the Kronecker preconditioner of Sec. 5.4 equals M, so
+ * each stage solve is the first (and converged) PCG iterate M^{-1} b.
+ * Vectors: FP64 device, system r at entries r*m .. r*m+m-1, m = n_el + p - 2
+ * (ga_wave1d_info); the state is 3k such vectors (L^{-2} .. L^{3k-3}).
+ * The caller keeps the stability condition tau^2 omega_r^2 lambda_max(M^{-1}K)
+ * <= ga_stability_limit2(rho_b, rho_s); nothing is checked per step.
+ */
+int ga_wave1d_create(int n_el, int p, int nsys, const double* omega2_host, int k, double rho_b,
+                     double rho_s, double tau, ga_wave1d** out);
+int ga_wave1d_destroy(ga_wave1d* w);
+int ga_wave1d_info(const ga_wave1d* w, int* n_free);
+/* f[r][i] = int_0^1 b_i(x) sin(j_r pi x) dx (2p + 8 Gauss points per element),
+ * wavenumbers_host[nsys]; synchronizes the stream. */
+int ga_wave1d_load_sine(ga_wave1d* w, const double* wavenumbers_host, double* f_dev, void* stream);
+/* y[r] = M x[r] ('M'), K x[r] ('K') or M^{-1} x[r] ('S') for every system. */
+int ga_wave1d_apply(ga_wave1d* w, char which, const double* x_dev, double* y_dev, void* stream);
+/* L^{-2} = U0, L^{-1} = V0, L^a = M^{-1}(-omega^2 K L^{a-2}), a = 0 .. 3k-3. */
+int ga_wave1d_init_state(ga_wave1d* w, const double* U0_dev, const double* V0_dev,
+                         double* const* state_dev, void* stream);
+/* nsteps steps of every system; no host synchronization. */
+int ga_wave1d_step(ga_wave1d* w, double* const* state_dev, int nsteps, void* stream);
 
 /*
  * Launch timing (instrumentation, not part of the method): with profiling on,

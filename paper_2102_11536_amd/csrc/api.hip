@@ -25,22 +25,26 @@ namespace ga {
 // Stability limit: the lambda = -1 crossing of the characteristic polynomial
 // of the last diagonal block (printed in Sec. 3), i.e. Theta (8 beta - 4 gamma)
 // = 16 alpha - 8, with the block-k parameters.
-void block_k_params(double rho, double& a, double& b, double& g) {
-  const double rb = rho, rs = rho;
+// block k: the printed type-k formulas at (rho_b, rho_s)
+void block_k_params2(double rho_b, double rho_s, double& a, double& b, double& g) {
+  const double rb = rho_b, rs = rho_s;
   a = (2 + (1 - rb) * rs) / ((1 + rb) * (1 + rs));
   b = (-5 - 3 * rb - 4 * rs + 2 * rb * rs + 2 * rb * rb * rs - rs * rs + rb * rs * rs) /
       ((1 + rb) * (1 + rb) * (-2 - 3 * rs + rb * rs - rs * rs + rb * rs * rs));
   g = 0.5 + a;  // gamma = 1/2 - alpha_f + alpha with alpha_f = 0
 }
 
-// blocks j < k: the printed formulas evaluated at rho_b = rho_s = -rho
-void block_j_params(double rho, double& a, double& b, double& g) {
-  const double rb = -rho, rs = -rho;
+// blocks j < k: the printed type-j formulas evaluated at (-rho_b, -rho_s)
+void block_j_params2(double rho_b, double rho_s, double& a, double& b, double& g) {
+  const double rb = -rho_b, rs = -rho_s;
   a = (2 - (1 + rb) * rs) / ((-1 + rb) * (-1 + rs));
   b = (1 + rb) * (-1 + rb * rs) * (-1 + rb * rs) /
       ((-1 + rb) * (-1 + rb) * (-1 + rs) * (-2 + rs + rb * rs));
   g = 0.5 - 1.0 + a;  // alpha_f = 1
 }
+
+void block_k_params(double rho, double& a, double& b, double& g) { block_k_params2(rho, rho, a, b, g); }
+void block_j_params(double rho, double& a, double& b, double& g) { block_j_params2(rho, rho, a, b, g); }
 
 }  // namespace ga
 
@@ -731,6 +735,20 @@ int ga_patch_info(const ga_patch* pt, long long* n_free, long long* n_quad, int*
   if (n_free) *n_free = pt->n_free;
   if (n_quad) *n_quad = pt->n_quad;
   if (mf) for (int a = 0; a < 3; ++a) mf[a] = a < pt->dim ? pt->mf[a] : 1;
+  return GA_OK;
+}
+
+int ga_integrator_set_rho(ga_integrator* it, double rho_b, double rho_s) {
+  if (!it) { set_error("null integrator"); return GA_EINVAL; }
+  if (!(rho_b >= 0.0 && rho_b < 1.0) || !(rho_s >= 0.0 && rho_s <= rho_b)) {
+    set_error("need 0 <= rho_s <= rho_b < 1");
+    return GA_EINVAL;
+  }
+  for (int j = 0; j < it->k; ++j) {
+    if (j < it->k - 1) block_j_params2(rho_b, rho_s, it->alpha[j], it->beta[j], it->gamma[j]);
+    else block_k_params2(rho_b, rho_s, it->alpha[j], it->beta[j], it->gamma[j]);
+  }
+  it->rho = rho_b;
   return GA_OK;
 }
 

@@ -89,6 +89,10 @@ inline int check_launch(int rc, const char* what) {
 // order-2k scheme with rho_b = rho_s = rho
 void block_j_params(double rho, double& a, double& b, double& g);
 void block_k_params(double rho, double& a, double& b, double& g);
+// the two-parameter family rho_s <= rho_b (type-j formulas at (-rho_b, -rho_s),
+// type-k at (rho_b, rho_s))
+void block_j_params2(double rho_b, double rho_s, double& a, double& b, double& g);
+void block_k_params2(double rho_b, double rho_s, double& a, double& b, double& g);
 
 // FP32 copies of a 3-D patch's factors, 1-D inverses, band factors and scaling
 // for the mixed-precision solves (built once, kept with the patch)

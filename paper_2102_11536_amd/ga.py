@@ -26,7 +26,10 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
-           "ga_batch_tune", "ga_batch_set_precision", "ga_patch_set_cg", "ga_cg_stats", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
+           "ga_batch_tune", "ga_batch_set_precision", "ga_patch_set_cg", "ga_cg_stats",
+           "ga_stability_limit2", "ga_integrator_set_rho", "ga_wave1d_create", "ga_wave1d_destroy",
+           "ga_wave1d_info", "ga_wave1d_load_sine", "ga_wave1d_apply", "ga_wave1d_init_state",
+           "ga_wave1d_step", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
            "ga_mp_info", "ga_mp_apply", "ga_mp_mass_solve", "ga_mp_init_state", "ga_mp_step"]
 
 
@@ -105,8 +108,18 @@ def load_library(path=LIB_PATH):
     lib.ga_mp_mass_solve.argtypes = [vp, i, dp, dp, ctypes.POINTER(i), vp]
     lib.ga_mp_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
     lib.ga_mp_step.argtypes = [vp, ctypes.POINTER(vp), i, ctypes.POINTER(i), vp]
+    lib.ga_stability_limit2.argtypes = [d, d]
+    lib.ga_stability_limit2.restype = d
+    lib.ga_integrator_set_rho.argtypes = [vp, d, d]
+    lib.ga_wave1d_create.argtypes = [i, i, i, ctypes.POINTER(d), i, d, d, d, ctypes.POINTER(vp)]
+    lib.ga_wave1d_destroy.argtypes = [vp]
+    lib.ga_wave1d_info.argtypes = [vp, ctypes.POINTER(i)]
+    lib.ga_wave1d_load_sine.argtypes = [vp, ctypes.POINTER(d), dp, vp]
+    lib.ga_wave1d_apply.argtypes = [vp, ctypes.c_char, dp, dp, vp]
+    lib.ga_wave1d_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
+    lib.ga_wave1d_step.argtypes = [vp, ctypes.POINTER(vp), i, vp]
     for name in EXPORTS:
-        if name not in ("ga_stability_limit", "ga_last_error"):
+        if name not in ("ga_stability_limit", "ga_stability_limit2", "ga_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -222,6 +235,15 @@ def ga_lambda_max(patch, iters=30):
 
 def ga_stability_limit(rho):
     return load_library().ga_stability_limit(float(rho))
+
+
+def ga_stability_limit2(rho_b, rho_s):
+    return load_library().ga_stability_limit2(float(rho_b), float(rho_s))
+
+
+def ga_integrator_set_rho(integ, rho_b, rho_s):
+    """Two-parameter family 0 <= rho_s <= rho_b < 1 for an existing integrator."""
+    _check(_lib.ga_integrator_set_rho(integ.h, float(rho_b), float(rho_s)))
 
 
 class Integrator:
@@ -564,3 +586,59 @@ def ga_mp_step(mp, state, nsteps=1):
     its = (ctypes.c_int * (nsteps * mp.k))()
     _check(_lib.ga_mp_step(mp.h, _mp_state(mp, state), int(nsteps), its, _stream()))
     return np.array(its, dtype=np.int64).reshape(nsteps, mp.k)
+
+
+# ---- batched 1-D wave problems (dispersion study) ----
+
+class Wave1D:
+    """nsys independent 1-D problems M U'' + omega_r^2 K U = 0 (ga_wave1d_create)."""
+
+    def __init__(self, n_el, p, omega2, k, rho_b, rho_s, tau):
+        lib = load_library()
+        w2 = np.ascontiguousarray(np.asarray(omega2, dtype=np.float64))
+        h = ctypes.c_void_p()
+        _check(lib.ga_wave1d_create(int(n_el), int(p), len(w2), w2.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    int(k), float(rho_b), float(rho_s), float(tau), ctypes.byref(h)))
+        self.h, self.k, self.nsys = h, int(k), len(w2)
+        m = ctypes.c_int()
+        _check(lib.ga_wave1d_info(h, ctypes.byref(m)))
+        self.m = m.value
+        self.n_total = self.nsys * self.m
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ga_wave1d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _w1_state(w, state):
+    if len(state) != 3 * w.k:
+        raise ValueError(f"need {3 * w.k} state vectors")
+    return (ctypes.c_void_p * len(state))(*[_ptr(s, w.n_total).value for s in state])
+
+
+def ga_wave1d_load_sine(w, wavenumbers, f):
+    j = np.ascontiguousarray(np.asarray(wavenumbers, dtype=np.float64))
+    if len(j) != w.nsys:
+        raise ValueError("one wavenumber per system")
+    _check(_lib.ga_wave1d_load_sine(w.h, j.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    _ptr(f, w.n_total), _stream()))
+
+
+def ga_wave1d_apply(w, which, x, y):
+    _check(_lib.ga_wave1d_apply(w.h, which.encode()[:1], _ptr(x, w.n_total), _ptr(y, w.n_total), _stream()))
+
+
+def ga_wave1d_init_state(w, U0, V0, state):
+    _check(_lib.ga_wave1d_init_state(w.h, _ptr(U0, w.n_total), _ptr(V0, w.n_total), _w1_state(w, state),
+                                     _stream()))
+
+
+def ga_wave1d_step(w, state, nsteps=1):
+    _check(_lib.ga_wave1d_step(w.h, _w1_state(w, state), int(nsteps), _stream()))

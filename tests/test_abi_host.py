@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2102_11536_amd", "libga.so")
 def declared():
     src = open(os.path.join(ROOT, "include", "ga.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ga_[A-Za-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(ga_[A-Za-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
