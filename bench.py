@@ -134,6 +134,67 @@ def bench_multipatch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c3(args):
+    """Deformed cube p=4 on 128^3 elements, k=3 (sixth order): the FP64 PCG path
+    and the mixed path (FP32 inner PCG with FP32 factors, vectors and
+    preconditioner inside FP64 refinement; K, residuals, dots and the update in
+    FP64), zero guess, rtol 1e-10.  Both rates are timed; then both paths step
+    side by side from the same state and the relative L2(Omega) displacement
+    error of the mixed path against the FP64 path is reported after every step."""
+    import torch
+    from paper_2102_11536_amd import ga, workloads
+    n, p, k, rho = 128, 4, 3, 0.5
+    dev = "cuda:0"
+    log(f"[bench] c3: deformed cube p={p} n={n}^3 k={k}: setup")
+    pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
+    lam = ga.ga_lambda_max(pt, 25)
+    tau = 0.5 * np.sqrt(ga.ga_stability_limit(rho) / lam)
+    u = torch.as_tensor(workloads.grf(n, p, seed=2000), device=dev)
+    init = ga.ga_integrator_create(pt, k, rho, tau, rtol=args.rtol, maxit=200)
+    state0 = [torch.zeros(pt.n_free, dtype=torch.float64, device=dev) for _ in range(3 * k)]
+    ga.ga_init_state(init, u, torch.zeros_like(u), state0)
+    ndof = (n + p) ** 3
+
+    def mnorm(v):
+        w = torch.empty_like(v)
+        ga.ga_apply_MK(pt, "M", v, w)
+        return float(torch.dot(v, w).item()) ** 0.5
+
+    paths, integs = {}, {}
+    for name, prec in (("fp64", ga.GA_FP64), ("mixed_fp32", ga.GA_FP32)):
+        integ = ga.ga_integrator_create(pt, k, rho, tau, rtol=args.rtol, maxit=200, prec=prec)
+        state = [t.clone() for t in state0]
+        ga.ga_step(integ, state, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = ga.ga_step(integ, state, args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        paths[name] = {"dof_steps_per_s": ndof * args.steps / dt, "ms_per_step": dt / args.steps * 1e3,
+                       "pcg_iters_mean": float(np.mean(its))}
+        integs[name] = integ
+        log(f"[bench] c3 {name}: {dt / args.steps * 1e3:.3f} ms/step, iters {np.mean(its):.2f}")
+    sa = [t.clone() for t in state0]
+    sb = [t.clone() for t in state0]
+    errs = []
+    for _ in range(args.steps):
+        ga.ga_step(integs["fp64"], sa, 1)
+        ga.ga_step(integs["mixed_fp32"], sb, 1)
+        errs.append(mnorm(sb[0] - sa[0]) / mnorm(sa[0]))
+    log(f"[bench] c3 mixed vs fp64 displacement error per step: max {max(errs):.2e}")
+    for it in integs.values():
+        it.close()
+    best = max(paths, key=lambda x: paths[x]["dof_steps_per_s"])
+    out = {"metric": "DOF-steps/s, deformed cube p=4 128^3 k=3", "value": paths[best]["dof_steps_per_s"],
+           "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": paths[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if best == "fp64" else "f64+f32", "data": "synthetic",
+           "config": {"workload": "deformed_cube_p4_n128_k3", "n_dof": ndof, "n_free": pt.n_free, "k": k,
+                      "rho": rho, "tau": tau, "rtol": args.rtol, "paths": paths, "path": best,
+                      "mixed_rel_l2_err_vs_fp64_per_step": errs}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_dispersion(args):
     """The 1-D dispersion study (Sec. 6.2): u_tt = omega^2 u_xx, omega = 1/j,
     exact solution sin(j pi x) cos(pi t); N = 400 elements, p = 4 (C^3), T = 5,
@@ -277,11 +338,12 @@ def main():
                     help="counter-collection mode: run only these operator applies (e.g. K2,M2), "
                          "three times each, then a 1 GiB device copy used to calibrate "
                          "FETCH_SIZE/WRITE_SIZE, and exit")
-    ap.add_argument("--workload", default="cube", choices=["cube", "multipatch", "glued", "dispersion"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "multipatch", "glued", "dispersion", "c3"],
                     help="cube: the single-patch headline workload; multipatch: 12 independent "
                          "patches of uneven size and degree stepped as one batch; glued: a 2x2x2 "
                          "brick of C0-glued patches with the additive Schwarz preconditioner; "
-                         "dispersion: the 1-D study of Sec. 6.2, every wavenumber one system")
+                         "dispersion: the 1-D study of Sec. 6.2, every wavenumber one system; "
+                         "c3: deformed cube p=4 128^3 k=3, FP64 and mixed, error per step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
@@ -297,6 +359,8 @@ def main():
         return bench_glued(args)
     if args.workload == "dispersion":
         return bench_dispersion(args)
+    if args.workload == "c3":
+        return bench_c3(args)
     n, p, k, rho = args.n, args.p, args.k, 0.5
     dev = "cuda:0"
     log(f"[bench] workload deformed cube p={p} n={n}^3 k={k}: building inputs")

@@ -129,9 +129,10 @@ constexpr int MAX_NR = 3;  // right-hand sides per kernel pass
 
 int op_apply(ga_patch* pt, int mode, int nr, double alpha, const double* x, double* y,
              hipStream_t st) {
-  // y += alpha * Op x, in chunks of MAX_NR right-hand sides
-  for (int r0 = 0; r0 < nr; r0 += MAX_NR) {
-    int c = nr - r0 < MAX_NR ? nr - r0 : MAX_NR;
+  // y += alpha * Op x, in chunks of at most op3d_max_nr right-hand sides
+  const int cmax = pt->dim == 3 ? op3d_max_nr(pt->p, mode) : MAX_NR;
+  for (int r0 = 0; r0 < nr; r0 += cmax) {
+    int c = nr - r0 < cmax ? nr - r0 : cmax;
     const double* xc = x ? x + (size_t)r0 * pt->n_free : nullptr;
     double* yc = y + (size_t)r0 * pt->n_free;
     ProfScope prof(mode == 1 ? 1 : 0, st);

@@ -95,9 +95,10 @@ int upload_op_group(OpGroup& g) {
 
 int op_batch(ga_batch* b, int mode, int nr, double alpha, const double* x, double* y,
              hipStream_t st) {
-  for (int r0 = 0; r0 < nr; r0 += 3) {   // at most 3 right-hand sides per launch
-    const int c = std::min(3, nr - r0);
-    for (OpGroup& g : b->ops[mode]) {
+  for (OpGroup& g : b->ops[mode]) {
+    const int cmax = op3d_max_nr(g.p, mode);
+    for (int r0 = 0; r0 < nr; r0 += cmax) {
+      const int c = std::min(cmax, nr - r0);
       const int nwg = g.nwg > 0 ? std::min(g.nwg, g.total) : g.total;
       if (launch_op3d_group<double>(g.p, mode, c, g.ents, g.nent, x + (size_t)r0 * b->N,
                                     y + (size_t)r0 * b->N, b->N, alpha, g.total, nwg, st))
@@ -650,12 +651,13 @@ int ga_batch_tune(ga_batch* b, int reps, double* best_ms, void* stream) {
           g.nwg = nwgc;
           const int nwg = nwgc > 0 ? nwgc : g.total;
           // warm-up, then timed launches (k right-hand sides, scratch vectors)
+          const int nrg = std::min(nr, op3d_max_nr(g.p, g.mode));
           auto launch = [&]() {
             if (g.f32)
-              launch_op3d_group<float>(g.p, 0, nr, g.ents, g.nent, t32, t32 + (size_t)nr * b->N,
+              launch_op3d_group<float>(g.p, 0, nrg, g.ents, g.nent, t32, t32 + (size_t)nrg * b->N,
                                        b->N, 1.0f, g.total, nwg, st);
             else
-              launch_op3d_group<double>(g.p, g.mode, nr, g.ents, g.nent, w.t0, w.t1, b->N, 1.0,
+              launch_op3d_group<double>(g.p, g.mode, nrg, g.ents, g.nent, w.t0, w.t1, b->N, 1.0,
                                         g.total, nwg, st);
           };
           launch();

@@ -35,6 +35,10 @@ int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y
                 hipStream_t st,
                 const double* gate = nullptr);
 long long op3d_tiles(int mode, const ga_patch* pt, int ze);
+// right-hand sides per operator launch: 3, except the p = 4 stiffness, whose
+// three-right-hand-side kernel spills registers (measured at 128^3: NR = 3
+// 16.9 ms, NR = 2 + NR = 1 8.3 ms)
+inline int op3d_max_nr(int p, int mode) { return (mode == 1 && p == 4) ? 2 : 3; }
 int op3d_default_ze(int mode, const ga_patch* pt);
 OpGroupEntry op3d_group_entry(int mode, const ga_patch* pt, int ze, long long off, int tile0,
                               bool f32);
