@@ -75,6 +75,9 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned nwg) {
 #ifndef GA_RING_K
 #define GA_RING_K 4
 #endif
+// p = 4 stiffness with two right-hand sides: a ring of 2 keeps the field
+// planes within the register budget of two waves per SIMD
+constexpr int stiff_ring(int P, int NR) { return (P == 4 && NR >= 2) ? 2 : GA_RING_K; }
 // mass ring by degree and right-hand-side count (measured at 128^3 p = 2, 3 and
 // 96^3 p = 4); GA_RING_M overrides it for every case
 constexpr int mass_ring(int P, int NR) {
@@ -401,7 +404,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   }
 
   // z sweep over Gauss layers with a ring of D prefetched factor planes
-  constexpr int D = (MODE == 1) ? GA_RING_K : mass_ring(P, NR);
+  constexpr int D = (MODE == 1) ? stiff_ring(P, NR) : mass_ring(P, NR);
   const int q0 = ez0 * Q, q1 = ez1 * Q;
   S gq[D][NC];
 #pragma unroll
