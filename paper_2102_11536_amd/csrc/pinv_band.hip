@@ -97,8 +97,14 @@ __device__ __forceinline__ void band_solve(const S* src, S* dst, long long strid
   }
 }
 
-constexpr int WT = 256;  // threads per workgroup: all stage and store, NL sweep
-constexpr int NL = 64;   // lines per workgroup (one per sweeping thread)
+#ifndef GA_BAND_WT
+#define GA_BAND_WT 256
+#endif
+#ifndef GA_BAND_NL
+#define GA_BAND_NL 64
+#endif
+constexpr int WT = GA_BAND_WT;  // threads per workgroup: all stage and store, NL sweep
+constexpr int NL = GA_BAND_NL;  // lines per workgroup (one per sweeping thread)
 
 // x axis: a workgroup stages NL consecutive rows (NL * L0 contiguous coefficients of
 // one right-hand side) in LDS with coalesced loads by all WT threads, NL threads
