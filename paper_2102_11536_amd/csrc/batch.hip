@@ -69,6 +69,8 @@ struct ga_batch {
   hipGraph_t graph = nullptr, graph32 = nullptr;
   hipGraphExec_t exec = nullptr, exec32 = nullptr;
   long long n_iters = 0, n_replays = 0;
+  int hint_nr = 0;               // systems of the last FP64 solve and
+  std::vector<int> hint;         //   their iteration counts
 };
 
 namespace {
@@ -326,13 +328,24 @@ int solve_batch64(ga_batch* b, int nr, const double* rhs, double* x, bool graph,
   if (check_launch(0, "batched pcg start")) return GA_EDEVICE;
   const bool use_graph = graph && nr == b->k && x == b->X;
   if (use_graph && !b->exec && (rc = capture_iteration(b, false))) return rc;
+  // iterations run before the first read of the convergence flags: one fewer
+  // than the fewest the previous solve of ns systems needed (an iteration leaves
+  // a converged system unchanged, so no iterate depends on this)
+  int ahead = 0;
+  if (b->hint_nr == ns) {
+    ahead = b->maxit;
+    for (int s = 0; s < ns; ++s) ahead = std::min(ahead, b->hint[s] - 1);
+    ahead = std::max(ahead, 0);
+  }
   for (int it = 0;; ++it) {
-    GA_TRY_HIP(hipMemcpyAsync(b->host_scal, b->scal, sizeof(double) * NSCAL * ns,
-                              hipMemcpyDeviceToHost, st));
-    GA_TRY_HIP(hipStreamSynchronize(st));
-    bool any = false;
-    for (int s = 0; s < ns; ++s) any |= b->host_scal[s * NSCAL + S_ACTIVE] != 0.0;
-    if (!any || it >= b->maxit) break;
+    if (it >= ahead) {
+      GA_TRY_HIP(hipMemcpyAsync(b->host_scal, b->scal, sizeof(double) * NSCAL * ns,
+                                hipMemcpyDeviceToHost, st));
+      GA_TRY_HIP(hipStreamSynchronize(st));
+      bool any = false;
+      for (int s = 0; s < ns; ++s) any |= b->host_scal[s * NSCAL + S_ACTIVE] != 0.0;
+      if (!any || it >= b->maxit) break;
+    }
     if (use_graph) {
       GA_TRY_HIP(hipGraphLaunch(b->exec, st));
       b->n_replays += 1;
@@ -342,9 +355,12 @@ int solve_batch64(ga_batch* b, int nr, const double* rhs, double* x, bool graph,
     b->n_iters += 1;
   }
   bool ok = true;
+  b->hint_nr = ns;
+  b->hint.assign(ns, 0);
   for (int s = 0; s < ns; ++s) {
     const double* sc = b->host_scal + s * NSCAL;
     if (iters_out) iters_out[s] = (int)sc[S_ITERS];
+    b->hint[s] = (int)sc[S_ITERS];
     if (sc[S_ACTIVE] != 0.0 || !std::isfinite(sc[S_RZ])) ok = false;
   }
   if (!ok) {
@@ -761,6 +777,8 @@ struct ga_mp {
   int* map = nullptr;              // [Nl] local free index -> global unknown
   double *Y = nullptr, *Bv = nullptr, *X = nullptr, *gw = nullptr;  // global vectors
   double *red = nullptr, *scal = nullptr, *host_scal = nullptr;
+  int hint_nr = 0;                 // systems of the last solve and
+  std::vector<int> hint;           //   their iteration counts
 };
 
 namespace {
@@ -802,13 +820,25 @@ int mp_solve(ga_mp* m, int nr, const double* rhs, double* x, int* iters_out, hip
   launch_dot_partial(nr, r, z, n, m->red, st);
   launch_cg_start(nr, m->red, nullptr, m->scal, m->rtol * m->rtol, st);
   launch_copy(pv, z, tot, st);
+  // iterations enqueued before the first read of the convergence flags: one
+  // fewer than the fewest the previous solve of nr systems needed.  An
+  // iteration leaves a converged system unchanged (zero step, no new
+  // direction), so this changes no iterate, only when the host looks.
+  int ahead = 0;
+  if (m->hint_nr == nr) {
+    ahead = m->maxit;
+    for (int s = 0; s < nr; ++s) ahead = std::min(ahead, m->hint[s] - 1);
+    ahead = std::max(ahead, 0);
+  }
   for (int it = 0;; ++it) {
-    GA_TRY_HIP(hipMemcpyAsync(m->host_scal, m->scal, sizeof(double) * NSCAL * nr,
-                              hipMemcpyDeviceToHost, st));
-    GA_TRY_HIP(hipStreamSynchronize(st));
-    bool any = false;
-    for (int s = 0; s < nr; ++s) any |= m->host_scal[s * NSCAL + S_ACTIVE] != 0.0;
-    if (!any || it >= m->maxit) break;
+    if (it >= ahead) {
+      GA_TRY_HIP(hipMemcpyAsync(m->host_scal, m->scal, sizeof(double) * NSCAL * nr,
+                                hipMemcpyDeviceToHost, st));
+      GA_TRY_HIP(hipStreamSynchronize(st));
+      bool any = false;
+      for (int s = 0; s < nr; ++s) any |= m->host_scal[s * NSCAL + S_ACTIVE] != 0.0;
+      if (!any || it >= m->maxit) break;
+    }
     launch_fill(q, 0.0, tot, st);
     if ((rc = mp_op(m, 0, nr, 1.0, pv, q, st))) return rc;
     launch_dot_partial(nr, pv, q, n, m->red, st);
@@ -821,9 +851,12 @@ int mp_solve(ga_mp* m, int nr, const double* rhs, double* x, int* iters_out, hip
     if (check_launch(0, "multi-patch pcg")) return GA_EDEVICE;
   }
   bool ok = true;
+  m->hint_nr = nr;
+  m->hint.assign(nr, 0);
   for (int s = 0; s < nr; ++s) {
     const double* sc = m->host_scal + s * NSCAL;
     if (iters_out) iters_out[s] = (int)sc[S_ITERS];
+    m->hint[s] = (int)sc[S_ITERS];
     if (sc[S_ACTIVE] != 0.0 || !std::isfinite(sc[S_RZ])) ok = false;
   }
   if (!ok) { set_error("multi-patch PCG did not converge within maxit"); return GA_ENOCONV; }

@@ -122,6 +122,30 @@ def test_glued_steps_match_oracle(P, n, p, k):
     _say("  iterations", its.mean())
 
 
+def test_glued_solve_iterations_read_ahead():
+    # the iterations enqueued before the first flag read (as many as the last
+    # solve needed, less one) must leave converged systems untouched: a solve
+    # after a harder one, with one zero right-hand side, gives the Cholesky
+    # solution, zero iterations for the zero system and the counts of a fresh solve
+    P, n, p = (2, 1, 1), 4, 3
+    dom, gp = _setup(P, n, p)
+    rng = np.random.default_rng(8)
+    ch = solvers.CholeskySolver(gp.M)
+    B1 = rng.standard_normal((2, dom.n_global))
+    x = torch.zeros(2 * dom.n_global, dtype=torch.float64, device=DEV)
+    its1 = ga.ga_mp_mass_solve(dom, _t(B1.ravel()), x, nrhs=2)
+    B2 = np.stack([rng.standard_normal(dom.n_global), np.zeros(dom.n_global)])
+    its2 = ga.ga_mp_mass_solve(dom, _t(B2.ravel()), x, nrhs=2)
+    got = _np(x).reshape(2, -1)
+    assert rel(got[0], ch.solve(B2[0])) < 1e-10 and np.all(got[1] == 0.0)
+    assert its2[1] == 0 and its2[0] > 0
+    fresh, _ = _setup(P, n, p)
+    x2 = torch.zeros_like(x)
+    its3 = ga.ga_mp_mass_solve(fresh, _t(B2.ravel()), x2, nrhs=2)
+    assert list(its2) == list(its3), (its1, its2, its3)
+    assert rel(_np(x2), _np(x)) < 1e-13
+
+
 def test_mp_errors():
     with pytest.raises(ga.GAError):
         ga.ga_mp_create((2, 1, 1), 3, 1, [workloads.brick_ctrl((2, 1, 1), 3, 1, r) for r in range(2)],
