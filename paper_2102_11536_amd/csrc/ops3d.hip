@@ -27,8 +27,12 @@
 // The stiffness kernel uses 4x4-element columns (6 factors per point, high
 // register use); the mass kernels use wider columns so the fixed per-plane
 // work is spread over more Gauss points.
-// Factor layout: [xy tile][qz over the whole z extent][component][qy][qx].
+// Factor layout: W [xy tile][qz over the whole z extent][qy][qx]; G [xy tile]
+// [qz][component pair][qy][qx][2] (each thread reads its 6 components as three
+// 16-byte pairs).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "ga_internal.h"
 #include "kernels.h"
@@ -158,6 +162,22 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   }
   const int eyq = qy / Q, jyq = qy % Q;
   const S* fcol = fac + (size_t)txy * qz_tot * NC * NT + tid;
+  // factors of Gauss layer q: the stiffness stores its 6 components as 3 pairs
+  // per thread ([layer][pair][thread][2]), read with 16-byte loads
+  auto load_fac = [&](int q, S (&dst)[NC]) {
+    if constexpr (MODE == 1) {
+      using V2 = typename std::conditional<sizeof(S) == 8, double2, float2>::type;
+      const V2* b2 = reinterpret_cast<const V2*>(fac + ((size_t)txy * qz_tot + q) * NC * NT) + tid;
+#pragma unroll
+      for (int h = 0; h < NC / 2; ++h) {
+        const V2 v = b2[(size_t)h * NT];
+        dst[2 * h] = v.x;
+        dst[2 * h + 1] = v.y;
+      }
+    } else {
+      dst[0] = fcol[(size_t)q * NT];
+    }
+  };
 
   S c[NR][NF][P + 1];   // forward fields of the coefficient planes ez..ez+P
   S s[NR][NF][P + 1];   // transposed-z accumulators of the same planes
@@ -408,10 +428,14 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   const int q0 = ez0 * Q, q1 = ez1 * Q;
   S gq[D][NC];
 #pragma unroll
-  for (int d = 0; d < D; ++d)
+  for (int d = 0; d < D; ++d) {
+    if (q0 + d < q1) {
+      load_fac(q0 + d, gq[d]);
+    } else {
 #pragma unroll
-    for (int cc = 0; cc < NC; ++cc)
-      gq[d][cc] = (q0 + d < q1) ? fcol[((size_t)(q0 + d) * NC + cc) * NT] : 0.0;
+      for (int cc = 0; cc < NC; ++cc) gq[d][cc] = 0.0;
+    }
+  }
 
   for (int qb = q0; qb < q1; qb += D) {
 #pragma unroll
@@ -422,10 +446,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
       S cur[NC];
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) cur[cc] = gq[d][cc];
-      if (q + D < q1) {
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) gq[d][cc] = fcol[((size_t)(q + D) * NC + cc) * NT];
-      }
+      if (q + D < q1) load_fac(q + D, gq[d]);
       const double* bzt = tB2 + ((size_t)ez * Q + jz) * (P + 1);
       const double* dzt = tD2 + ((size_t)ez * Q + jz) * (P + 1);
       S bz[P + 1], dz[P + 1];
@@ -558,7 +579,7 @@ geo3d_kernel(const double* __restrict__ ctrl,  // [3][N_dof] full grid, co-lex
   for (int jz = 0; jz < Q; ++jz) {
     const int qz = ez * Q + jz;
     const size_t wi = ((size_t)tm * qz_tot + qz) * TM::NT + lm;
-    const size_t gi = ((size_t)txy * qz_tot + qz) * 6 * NT + tid;
+    const size_t gi = ((size_t)txy * qz_tot + qz) * 6 * NT + 2 * (size_t)tid;
     const double* bx = &tB0[((size_t)ex * Q + jx) * (P + 1)];
     const double* dx = &tD0[((size_t)ex * Q + jx) * (P + 1)];
     const double* by = &tB1[((size_t)ey * Q + jy) * (P + 1)];
@@ -601,7 +622,7 @@ geo3d_kernel(const double* __restrict__ ctrl,  // [3][N_dof] full grid, co-lex
     for (int c = 0; c < 6; ++c) {
       double v = 0.0;
       for (int t = 0; t < 3; ++t) v += A[ia[c]][t] * A[ib[c]][t];
-      G[gi + (size_t)c * NT] = sc * v;
+      G[gi + (size_t)(c / 2) * 2 * NT + (c % 2)] = sc * v;   // components in pairs per thread
     }
   }
 }
