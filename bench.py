@@ -147,6 +147,8 @@ def bench_c3(args):
     dev = "cuda:0"
     log(f"[bench] c3: deformed cube p={p} n={n}^3 k={k}: setup")
     pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
+    ga.ga_patch_tune(pt, nrhs=k, reps=3)
+    log(f"[bench] c3: tuned layers per workgroup (mass, stiffness): {ga.ga_patch_tuned_layers(pt)}")
     lam = ga.ga_lambda_max(pt, 25)
     tau = 0.5 * np.sqrt(ga.ga_stability_limit(rho) / lam)
     u = torch.as_tensor(workloads.grf(n, p, seed=2000), device=dev)
@@ -368,6 +370,9 @@ def main():
     U0 = workloads.grf(n, p, seed=2000)
     log("[bench] setup")
     pt = ga.ga_setup_patch(3, n, p, ctrl)
+    tuned_ms = ga.ga_patch_tune(pt, nrhs=k, reps=3)   # element layers per workgroup (setup)
+    tuned_layers = ga.ga_patch_tuned_layers(pt)
+    log(f"[bench] tuned layers per workgroup (mass, stiffness): {tuned_layers}, {tuned_ms:.3f} ms")
     if args.profile_ops:
         x = torch.as_tensor(np.concatenate([U0] * k), device=dev)
         y = torch.empty_like(x)
@@ -527,6 +532,7 @@ def main():
                    "paths": {k_: {kk: vv for kk, vv in v.items() if kk != "prof"}
                              for k_, v in paths.items()},
                    "accuracy_bar": "rel L2(Omega) displacement error <= 1e-8 vs the FP64 path",
+                   "tuned_layers_mass_stiffness": list(tuned_layers),
                    "learned_guess": learned_note, "other_equations": extra},
         "roofline": {"bound": "hbm", "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": k_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),

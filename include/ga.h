@@ -147,6 +147,18 @@ int ga_patch_set_pinv(ga_patch* patch, int mode);
  *                 banded preconditioner; otherwise the host control is used.
  * ga_cg_stats: iterations enqueued ahead so far and host reads of the flags.
  */
+/*
+ * ga_patch_tune -- autotuner for the operator launches of a 3-D patch: for the
+ * mass and the stiffness apply with nrhs (1..3) right-hand sides, times `reps`
+ * launches for each candidate number of element layers per workgroup along z
+ * (whole columns, then halving down to 4) and keeps the fastest for the patch.
+ * Results do not change (the same sums, in another tiling).  best_ms (may be
+ * NULL): one tuned mass plus one tuned stiffness launch.  Allocates two scratch
+ * vectors for the duration of the call and synchronizes `stream`.
+ * ga_patch_tuned_layers: the layer counts the patch now uses (either may be NULL).
+ */
+int ga_patch_tune(ga_patch* patch, int nrhs, int reps, double* best_ms, void* stream);
+int ga_patch_tuned_layers(const ga_patch* patch, int* ze_mass, int* ze_stiff);
 enum { GA_CG_HOST = 0, GA_CG_DEVICE = 1 };
 int ga_patch_set_cg(ga_patch* patch, int mode);
 int ga_cg_stats(const ga_patch* patch, long long* spec_iters, long long* host_checks);

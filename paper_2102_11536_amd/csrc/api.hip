@@ -753,6 +753,64 @@ int ga_integrator_set_rho(ga_integrator* it, double rho_b, double rho_s) {
   return GA_OK;
 }
 
+int ga_patch_tune(ga_patch* pt, int nrhs, int reps, double* best_ms, void* stream) {
+  if (!pt || nrhs < 1 || nrhs > 3 || reps < 1) { set_error("bad argument"); return GA_EINVAL; }
+  if (pt->dim != 3) { set_error("the operator autotuner is for 3-D patches"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  const size_t n = pt->n_free;
+  double *x = nullptr, *y = nullptr;
+  int rc;
+  if ((rc = dalloc((void**)&x, (size_t)nrhs * n * 8))) return rc;
+  if ((rc = dalloc((void**)&y, (size_t)nrhs * n * 8))) { hipFree(x); return rc; }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double total = 0.0;
+  rc = GA_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_error("event creation failed");
+    rc = GA_EDEVICE;
+  }
+  launch_fill(x, 1.0, (size_t)nrhs * n, st);
+  launch_fill(y, 0.0, (size_t)nrhs * n, st);
+  for (int mode = 0; mode < 2 && rc == GA_OK && pt->ze == 0; ++mode) {
+    const int nr = std::min(nrhs, op3d_max_nr(pt->p, mode));
+    std::vector<int> cand;   // whole columns, then halving down to 4 layers
+    for (int ze = pt->n[2];; ze = (ze + 1) / 2) {
+      cand.push_back(ze);
+      if (ze <= 4) break;
+    }
+    double best = 1e30;
+    int best_ze = 0;
+    for (int ze : cand) {
+      pt->ze_op[mode] = ze;
+      if (launch_op3d(mode, nr, pt, x, y, 1.0, st)) { rc = check_launch(-1, "tuning"); break; }
+      hipEventRecord(e0, st);
+      for (int i = 0; i < reps; ++i) launch_op3d(mode, nr, pt, x, y, 1.0, st);
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = check_launch(-1, "tuning"); break; }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; best_ze = ze; }
+    }
+    pt->ze_op[mode] = best_ze;
+    total += best / reps;
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipStreamSynchronize(st);
+  hipFree(x);
+  hipFree(y);
+  if (rc) return rc;
+  if (best_ms) *best_ms = total;
+  return check_launch(0, "tuning");
+}
+
+int ga_patch_tuned_layers(const ga_patch* pt, int* ze_mass, int* ze_stiff) {
+  if (!pt) { set_error("null patch"); return GA_EINVAL; }
+  if (ze_mass) *ze_mass = op3d_default_ze(0, pt);
+  if (ze_stiff) *ze_stiff = op3d_default_ze(1, pt);
+  return GA_OK;
+}
+
 int ga_patch_set_cg(ga_patch* pt, int mode) {
   if (!pt) { set_error("null patch"); return GA_EINVAL; }
   if (mode != GA_CG_HOST && mode != GA_CG_DEVICE) { set_error("bad PCG control mode"); return GA_EINVAL; }

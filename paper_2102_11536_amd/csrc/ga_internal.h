@@ -110,6 +110,7 @@ struct ga_patch {
   int nt[3] = {1, 1, 1};          // element tiles per direction (2-D kernels)
   int ntk[2] = {1, 1}, ntm[2] = {1, 1};  // 3-D xy columns: stiffness and mass layouts
   int ze = 0;                     // element layers per workgroup along z (0: automatic)
+  int ze_op[2] = {0, 0};          // tuned layers for the mass / stiffness kernels (0: automatic)
   int pinv_mode = GA_PINV_AUTO;   // preconditioner algorithm (ga_patch_set_pinv)
   int cg_ctrl = GA_CG_DEVICE;     // PCG control (ga_patch_set_cg)
   int hint_nr = 0;                // iterations per right-hand side of the last FP64 solve

@@ -26,7 +26,7 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
-           "ga_batch_tune", "ga_batch_set_precision", "ga_patch_set_cg", "ga_cg_stats",
+           "ga_batch_tune", "ga_batch_set_precision", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers",
            "ga_stability_limit2", "ga_integrator_set_rho", "ga_wave1d_create", "ga_wave1d_destroy",
            "ga_wave1d_info", "ga_wave1d_load_sine", "ga_wave1d_apply", "ga_wave1d_init_state",
            "ga_wave1d_step", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
@@ -77,6 +77,8 @@ def load_library(path=LIB_PATH):
     lib.ga_stage_solution.argtypes = [vp, i, i, dp, vp]
     lib.ga_patch_set_pinv.argtypes = [vp, i]
     lib.ga_patch_set_cg.argtypes = [vp, i]
+    lib.ga_patch_tune.argtypes = [vp, i, i, ctypes.POINTER(d), vp]
+    lib.ga_patch_tuned_layers.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
     lib.ga_cg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     lib.ga_integrator_set_damping.argtypes = [vp, d, d]
     lib.ga_stage_times.argtypes = [vp, d, ctypes.POINTER(d)]
@@ -187,6 +189,20 @@ def ga_setup_patch_ex(dim, n_el, p, ctrl, dirichlet_faces):
 
 def ga_patch_set_pinv(patch, mode):
     _check(_lib.ga_patch_set_pinv(patch.h, int(mode)))
+
+
+def ga_patch_tune(patch, nrhs=2, reps=3):
+    """Autotune the element layers per workgroup of the patch's mass and stiffness
+    launches; returns the summed time of one tuned launch of each (ms)."""
+    ms = ctypes.c_double()
+    _check(_lib.ga_patch_tune(patch.h, int(nrhs), int(reps), ctypes.byref(ms), _stream()))
+    return ms.value
+
+
+def ga_patch_tuned_layers(patch):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.ga_patch_tuned_layers(patch.h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def ga_patch_set_cg(patch, mode):

@@ -253,6 +253,30 @@ def test_cube_full_size_sampled_rows(n, p, k, rtol, seed):
     _say("  its", its, "device-controlled PCG: iterations ahead, host reads", ga.ga_cg_stats(pt))
 
 
+@pytest.mark.parametrize("n,p", [((20, 13, 17), 2), (16, 3), (11, 4)])
+def test_patch_tune_keeps_results(n, p):
+    # the autotuner only changes the tiling along z: operators equal the oracle's
+    # before and after, and the tuned layer counts are valid
+    pr = OracleProblem(3, n, p, seed=3)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    X = np.random.default_rng(1).standard_normal((2, pt.n_free))
+    x, y = _t(X.ravel()), torch.empty(2 * pt.n_free, dtype=torch.float64, device=DEV)
+    before = {}
+    for which in ("M", "K"):
+        ga.ga_apply_MK(pt, which, x, y, nrhs=2)
+        before[which] = _np(y).copy()
+    ms = ga.ga_patch_tune(pt, nrhs=2, reps=2)
+    zm, zk = ga.ga_patch_tuned_layers(pt)
+    nz = n if np.isscalar(n) else n[2]
+    assert ms > 0 and 1 <= zm <= nz and 1 <= zk <= nz
+    for which, A in (("M", pr.M), ("K", pr.K)):
+        ga.ga_apply_MK(pt, which, x, y, nrhs=2)
+        got = _np(y)
+        assert rel(got, before[which]) < 1e-13
+        for r in range(2):
+            assert rel(got.reshape(2, -1)[r], A @ X[r]) < 1e-13
+
+
 def test_error_paths():
     ctrl = workloads.identity_ctrl(3, 2, 2)
     bad = ctrl.copy()
