@@ -80,7 +80,7 @@ int upload_op_group(OpGroup& g) {
   int tile = 0;
   for (size_t i = 0; i < g.pts.size(); ++i) {
     const int ze = g.ze_override > 0 ? std::min(g.ze_override, g.pts[i]->n[2])
-                                     : op3d_default_ze(g.mode, g.pts[i]);
+                                     : op3d_default_ze(g.mode, g.pts[i], g.f32);
     OpGroupEntry e = op3d_group_entry(g.mode, g.pts[i], ze, g.offs[i], tile, g.f32);
     tile += e.ntiles;
     h.push_back(e);

@@ -39,7 +39,7 @@ long long op3d_tiles(int mode, const ga_patch* pt, int ze);
 // three-right-hand-side kernel spills registers (measured at 128^3: NR = 3
 // 16.9 ms, NR = 2 + NR = 1 8.3 ms)
 inline int op3d_max_nr(int p, int mode) { return (mode == 1 && p == 4) ? 2 : 3; }
-int op3d_default_ze(int mode, const ga_patch* pt);
+int op3d_default_ze(int mode, const ga_patch* pt, bool f32 = false);
 OpGroupEntry op3d_group_entry(int mode, const ga_patch* pt, int ze, long long off, int tile0,
                               bool f32);
 // y += alpha * Op x over every patch in ents (one degree p), nr right-hand sides

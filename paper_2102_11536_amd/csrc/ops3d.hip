@@ -644,7 +644,7 @@ static int launch_op3d_p(int mode, int nr, const ga_patch* pt, const S* x, S* y,
   g.nt[0] = nt[0];
   g.nt[1] = nt[1];
   const long long ntxy = (long long)nt[0] * nt[1];
-  const int ze = op3d_default_ze(mode, pt);
+  const int ze = op3d_default_ze(mode, pt, sizeof(S) == 4);
   const long long nwg = ntxy * ((pt->n[2] + ze - 1) / ze);
   dim3 grid((unsigned)nwg);
   const double* const* B = (mode == 2) ? pt->tabB2 : pt->tabB;
@@ -699,10 +699,11 @@ long long op3d_tiles(int mode, const ga_patch* pt, int ze) {
   return (long long)nt[0] * nt[1] * ((pt->n[2] + ze - 1) / ze);
 }
 
-int op3d_default_ze(int mode, const ga_patch* pt) {
+int op3d_default_ze(int mode, const ga_patch* pt, bool f32) {
   const int* nt = mode == 1 ? pt->ntk : pt->ntm;
   if (pt->ze > 0) return pt->ze;
-  if (mode <= 1 && pt->ze_op[mode] > 0) return pt->ze_op[mode];
+  // tuned counts hold for the FP64 launches they were measured on
+  if (!f32 && mode <= 1 && pt->ze_op[mode] > 0) return pt->ze_op[mode];
   return pick_ze((long long)nt[0] * nt[1], pt->n[2], mode == 1 ? 8 : 16);
 }
 
