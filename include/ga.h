@@ -351,6 +351,14 @@ int ga_batch_destroy(ga_batch* batch);
  * counts reported by ga_batch_step are then inner FP32 iterations.
  */
 int ga_batch_set_precision(ga_batch* batch, int prec, void* stream);
+/*
+ * ga_batch_set_tau -- per-patch time steps: patch r advances by tau_host[r]
+ * per step (the patches are independent, so each may run at its own stability
+ * limit; a step of the batch is one step of every patch).  tau_host = NULL
+ * returns to the common tau of ga_batch_create.  The scheme's parameters do
+ * not depend on tau.
+ */
+int ga_batch_set_tau(ga_batch* batch, const double* tau_host);
 /* n_total: N; offsets_out[npatch] (may be NULL); graph_replays: PCG iterations
  * run so far as replays of the captured iteration graph (may be NULL). */
 int ga_batch_info(const ga_batch* batch, long long* n_total, long long* offsets_out,

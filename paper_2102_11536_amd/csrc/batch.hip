@@ -71,6 +71,7 @@ struct ga_batch {
   long long n_iters = 0, n_replays = 0;
   int hint_nr = 0;               // systems of the last FP64 solve and
   std::vector<int> hint;         //   their iteration counts
+  std::vector<double> taus;      // per-patch time steps (ga_batch_set_tau); empty: tau for all
 };
 
 namespace {
@@ -625,6 +626,18 @@ int ga_batch_set_precision(ga_batch* b, int prec, void* stream) {
   return check_launch(0, "batched mixed-precision setup");
 }
 
+int ga_batch_set_tau(ga_batch* b, const double* tau_host) {
+  if (!b) { set_error("null batch"); return GA_EINVAL; }
+  if (!tau_host) { b->taus.clear(); return GA_OK; }
+  for (int r = 0; r < b->R; ++r)
+    if (!(tau_host[r] > 0.0) || !std::isfinite(tau_host[r])) {
+      set_error("time steps must be positive and finite");
+      return GA_EINVAL;
+    }
+  b->taus.assign(tau_host, tau_host + b->R);
+  return GA_OK;
+}
+
 int ga_batch_destroy(ga_batch* b) {
   if (!b) return GA_OK;
   hipDeviceSynchronize();
@@ -739,14 +752,30 @@ int ga_batch_step(ga_batch* b, double* const* state, int nsteps, int use_graph, 
     cf.gamma[j] = j < k ? b->gamma[j] : 0.0;
   }
   std::vector<int> its((size_t)k * b->R);
+  // one patch's segment of the batched state (per-patch time steps)
+  auto seg_ptrs = [&](int r) {
+    StatePtrs q;
+    for (int s = 0; s < 12; ++s) q.L[s] = s < ns ? state[s] + b->off[r] : nullptr;
+    return q;
+  };
   for (int step = 0; step < nsteps; ++step) {
-    launch_predict(k, b->tau, sp, b->Y, n, st);
+    if (b->taus.empty()) {
+      launch_predict(k, b->tau, sp, b->Y, n, st);
+    } else {
+      for (int r = 0; r < b->R; ++r)
+        launch_predict_seg(k, b->taus[r], seg_ptrs(r), b->Y + b->off[r], b->pts[r]->n_free, n, st);
+    }
     launch_fill(b->Bv, 0.0, (size_t)k * n, st);
     if ((rc = op_batch(b, 1, k, -1.0, b->Y, b->Bv, st))) return rc;
     if ((rc = solve_batch(b, k, b->Bv, b->X, use_graph != 0, its.data(), st))) return rc;
     if (iters_out)
       for (size_t s = 0; s < its.size(); ++s) iters_out[(size_t)step * its.size() + s] = its[s];
-    launch_update(k, b->tau, cf, sp, b->X, n, st);
+    if (b->taus.empty()) {
+      launch_update(k, b->tau, cf, sp, b->X, n, st);
+    } else {
+      for (int r = 0; r < b->R; ++r)
+        launch_update_seg(k, b->taus[r], cf, seg_ptrs(r), b->X + b->off[r], b->pts[r]->n_free, n, st);
+    }
     if (check_launch(0, "batched update")) return GA_EDEVICE;
   }
   if (use_graph && (rc = join(st, cst, b->ev[1]))) return rc;

@@ -115,6 +115,12 @@ void launch_predict_cz(int k, double tau, double cK, StatePtrs sp, double* Y, do
                        hipStream_t st);
 void launch_update(int k, double tau, Coefs c, StatePtrs sp, const double* X, size_t n,
                    hipStream_t st);
+// one segment of n entries of batched vectors: the state pointers point at the
+// segment, stage vectors are ys (xs) entries apart
+void launch_predict_seg(int k, double tau, StatePtrs sp, double* Y, size_t n, size_t ys,
+                        hipStream_t st);
+void launch_update_seg(int k, double tau, Coefs c, StatePtrs sp, const double* X, size_t n,
+                       size_t xs, hipStream_t st);
 void launch_axpby(double* out, double a, const double* x, double b, const double* y, size_t n,
                   hipStream_t st);
 // FP32 kernels of the mixed solve; with seg, system r covers entries

@@ -279,14 +279,17 @@ __device__ __forceinline__ double taylor(const double* Lv, int s, int ns, double
   return acc;
 }
 
-__global__ void predict_k(int k, double tau, StatePtrs sp, double* __restrict__ Y, size_t n) {
+// Y[(j-1) * ys + i], i < n: the stage arguments (ys = n unless the entries are
+// one segment of longer batched vectors)
+__global__ void predict_k(int k, double tau, StatePtrs sp, double* __restrict__ Y, size_t n,
+                          size_t ys) {
   const int ns = 3 * k;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
     double Lv[12];
     for (int s = 0; s < ns; ++s) Lv[s] = sp.L[s][i];
-    for (int j = 1; j < k; ++j) Y[(size_t)(j - 1) * n + i] = taylor(Lv, 3 * j - 3, ns, tau);
-    Y[(size_t)(k - 1) * n + i] = Lv[ns - 3];  // L^{N-2}
+    for (int j = 1; j < k; ++j) Y[(size_t)(j - 1) * ys + i] = taylor(Lv, 3 * j - 3, ns, tau);
+    Y[(size_t)(k - 1) * ys + i] = Lv[ns - 3];  // L^{N-2}
   }
 }
 
@@ -310,7 +313,7 @@ __global__ void predict_cz_k(int k, double tau, double cK, StatePtrs sp, double*
 }
 
 __global__ void update_k(int k, double tau, Coefs c, StatePtrs sp, const double* __restrict__ X,
-                         size_t n) {
+                         size_t n, size_t xs) {
   const int ns = 3 * k;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -321,7 +324,7 @@ __global__ void update_k(int k, double tau, Coefs c, StatePtrs sp, const double*
       const double Ta = taylor(Lv, sa, ns, tau);
       const double Ta1 = taylor(Lv, sa - 1, ns, tau);
       const double Ta2 = taylor(Lv, sa - 2, ns, tau);
-      const double P = (X[(size_t)(j - 1) * n + i] - Ta) / c.alpha[j - 1];
+      const double P = (X[(size_t)(j - 1) * xs + i] - Ta) / c.alpha[j - 1];
       sp.L[sa][i] = Ta + P;
       sp.L[sa - 1][i] = Ta1 + c.gamma[j - 1] * tau * P;
       sp.L[sa - 2][i] = Ta2 + c.beta[j - 1] * tau * tau * P;
@@ -518,11 +521,19 @@ void launch_predict_cz(int k, double tau, double cK, StatePtrs sp, double* Y, do
   hipLaunchKernelGGL(predict_cz_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, cK, sp, Y, Z, n);
 }
 void launch_predict(int k, double tau, StatePtrs sp, double* Y, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL(predict_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, sp, Y, n);
+  hipLaunchKernelGGL(predict_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, sp, Y, n, n);
 }
 void launch_update(int k, double tau, Coefs c, StatePtrs sp, const double* X, size_t n,
                    hipStream_t st) {
-  hipLaunchKernelGGL(update_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, c, sp, X, n);
+  hipLaunchKernelGGL(update_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, c, sp, X, n, n);
+}
+void launch_predict_seg(int k, double tau, StatePtrs sp, double* Y, size_t n, size_t ys,
+                        hipStream_t st) {
+  if (n) hipLaunchKernelGGL(predict_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, sp, Y, n, ys);
+}
+void launch_update_seg(int k, double tau, Coefs c, StatePtrs sp, const double* X, size_t n,
+                       size_t xs, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(update_k, dim3(nblocks(n)), dim3(VB), 0, st, k, tau, c, sp, X, n, xs);
 }
 
 }  // namespace ga

@@ -26,7 +26,7 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
-           "ga_batch_tune", "ga_batch_set_precision", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers",
+           "ga_batch_tune", "ga_batch_set_precision", "ga_batch_set_tau", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers",
            "ga_stability_limit2", "ga_integrator_set_rho", "ga_wave1d_create", "ga_wave1d_destroy",
            "ga_wave1d_info", "ga_wave1d_load_sine", "ga_wave1d_apply", "ga_wave1d_init_state",
            "ga_wave1d_step", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
@@ -100,6 +100,7 @@ def load_library(path=LIB_PATH):
     lib.ga_batch_info.argtypes = [vp, lp, lp, lp]
     lib.ga_batch_tune.argtypes = [vp, i, ctypes.POINTER(d), vp]
     lib.ga_batch_set_precision.argtypes = [vp, i, vp]
+    lib.ga_batch_set_tau.argtypes = [vp, ctypes.POINTER(d)]
     lib.ga_batch_init_state.argtypes = [vp, dp, dp, ctypes.POINTER(vp), vp]
     lib.ga_batch_step.argtypes = [vp, ctypes.POINTER(vp), i, i, ctypes.POINTER(i), vp]
     lib.ga_mp_create.argtypes = [ctypes.POINTER(i), i, i, ctypes.POINTER(vp), i, d, d, d, i, vp,
@@ -510,6 +511,17 @@ def ga_batch_graph_replays(batch):
 def ga_batch_set_precision(batch, prec):
     """GA_FP64 or GA_FP32 (FP32 inner PCG inside FP64 refinement) mass solves."""
     _check(_lib.ga_batch_set_precision(batch.h, int(prec), _stream()))
+
+
+def ga_batch_set_tau(batch, taus):
+    """Per-patch time steps (None: the common tau of the batch)."""
+    if taus is None:
+        _check(_lib.ga_batch_set_tau(batch.h, None))
+        return
+    t = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+    if len(t) != len(batch.patches):
+        raise ValueError("one time step per patch")
+    _check(_lib.ga_batch_set_tau(batch.h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
 
 def ga_batch_tune(batch, reps=5):

@@ -129,6 +129,33 @@ def test_graph_replays_match_eager():
             assert rel(hg[step][s], he[step][s]) < 1e-13, (step, s)
 
 
+def test_batch_per_patch_time_steps():
+    # every patch at half its own stability limit: the batch equals the single-patch
+    # integrators run with those time steps
+    specs = workloads.multipatch_specs(R=6, n_min=4, n_max=12, seed=9)
+    k = 2
+    pts, U0s = _setup(specs)
+    taus = [0.5 * np.sqrt(ga.ga_stability_limit(0.5) / ga.ga_lambda_max(pt, 30)) for pt in pts]
+    assert max(taus) > 1.2 * min(taus)
+    b = ga.ga_batch_create(pts, k, 0.5, min(taus), rtol=1e-12)
+    ga.ga_batch_set_tau(b, taus)
+    U = _t(np.concatenate(U0s))
+    state = [torch.zeros(b.n_total, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    ga.ga_batch_init_state(b, U, torch.zeros_like(U), state)
+    ga.ga_batch_step(b, state, 5)
+    got = [_np(s) for s in state]
+    for r, pt in enumerate(pts):
+        integ = ga.ga_integrator_create(pt, k, 0.5, taus[r], rtol=1e-12)
+        st = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+        u = _t(U0s[r])
+        ga.ga_init_state(integ, u, torch.zeros_like(u), st)
+        ga.ga_step(integ, st, 5)
+        for s in range(3 * k):
+            assert rel(_split(b, got[s])[r], _np(st[s])) < 1e-10, (r, s)
+    with pytest.raises(ga.GAError):
+        ga.ga_batch_set_tau(b, [1.0] * (len(pts) - 1) + [-1.0])
+
+
 # ---- FP32 inner PCG inside FP64 refinement, batched (Sec. 6.1) ----
 
 def test_batch_mixed_matches_oracle():
