@@ -298,6 +298,48 @@ def test_error_paths():
         ga.ga_integrator_create(pt, 2, 1.0, 1e-3)
 
 
+def test_degenerate_inputs():
+    # a patch with no free coefficients is refused; zero right-hand sides give zero
+    # solutions in zero iterations (FP64, mixed, device-controlled); a zero initial
+    # state stays zero; a one-unknown patch steps like the scalar oracle
+    with pytest.raises(ga.GAError) as e:
+        ga.ga_setup_patch(3, 1, 1, workloads.deformed_cube_ctrl(1, 1))
+    assert e.value.code == ga.GA_EINVAL
+    pr = OracleProblem(3, 5, 3, seed=2)
+    pt = ga.ga_setup_patch(3, 5, 3, pr.ctrl)
+    B = np.stack([np.zeros(pt.n_free), np.random.default_rng(3).standard_normal(pt.n_free)])
+    for prec, cg in ((ga.GA_FP64, ga.GA_CG_HOST), (ga.GA_FP64, ga.GA_CG_DEVICE), (ga.GA_FP32, ga.GA_CG_DEVICE)):
+        ga.ga_patch_set_cg(pt, cg)
+        for _ in range(2):   # the second solve runs with the first one's schedule
+            x = torch.full((2 * pt.n_free,), 7.0, dtype=torch.float64, device=DEV)
+            its, relres, _ = ga.ga_mass_solve(pt, _t(B.ravel()), x, nrhs=2, rtol=1e-12, prec=prec)
+            got = _np(x).reshape(2, -1)
+            assert its[0] == 0 and np.all(got[0] == 0.0), (prec, cg, its)
+            assert rel(got[1], pr.chol.solve(B[1])) < 1e-10
+    integ = ga.ga_integrator_create(pt, 2, 0.5, 1e-3, rtol=1e-12)
+    state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(6)]
+    z = torch.zeros(pt.n_free, dtype=torch.float64, device=DEV)
+    ga.ga_init_state(integ, z, z, state)
+    its = ga.ga_step(integ, state, 3)
+    assert np.all(its == 0) and all(float(torch.abs(s_).max()) == 0.0 for s_ in state)
+    # n = 2, p = 1: a single free coefficient per patch, M and K are 1 x 1
+    pr1 = OracleProblem(3, 2, 1, seed=4)
+    pt1 = ga.ga_setup_patch(3, 2, 1, pr1.ctrl)
+    assert pt1.n_free == 1
+    m, k_ = float(pr1.M.toarray()[0, 0]), float(pr1.K.toarray()[0, 0])
+    tau = 0.5 * np.sqrt(ga.ga_stability_limit(0.5) * m / k_)
+    integ1 = ga.ga_integrator_create(pt1, 2, 0.5, tau, rtol=1e-14)
+    st1 = [torch.zeros(1, dtype=torch.float64, device=DEV) for _ in range(6)]
+    ga.ga_init_state(integ1, _t(np.array([1.0])), _t(np.array([0.0])), st1)
+    ga.ga_step(integ1, st1, 10)
+    L = galpha.initial_state(np.array([1.0]), np.array([0.0]), 2, lambda y: k_ * y, lambda b: b / m)
+    for _ in range(10):
+        L = galpha.step(L, tau, 2, 0.5, lambda y: k_ * y, lambda b: b / m)
+    for s_ in range(6):
+        o = L[s_ - 2][0]
+        assert abs(_np(st1[s_])[0] - o) <= 1e-11 * abs(o) + 1e-300, (s_, _np(st1[s_])[0], o)
+
+
 def test_unstable_step_detected():
     # tau far above the stability limit: the state grows until it is non-finite
     pr = OracleProblem(2, 8, 2, geometry="identity")
