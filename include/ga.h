@@ -452,16 +452,19 @@ int ga_wave1d_init_state(ga_wave1d* w, const double* U0_dev, const double* V0_de
 int ga_wave1d_step(ga_wave1d* w, double* const* state_dev, int nsteps, void* stream);
 
 /*
- * Launch timing (instrumentation, not part of the method): with profiling on,
- * every operator launch (kind 0 = mass apply, 1 = stiffness apply), every
- * preconditioner application (kind 2) and every learned-guess inference in
- * ga_step (kind 3) is bracketed by HIP events on the
- * stream it runs on.  ga_profile(enable) clears the totals;
- * ga_profile_query waits for the recorded events and returns the summed
- * duration in ms and the number of launches of one kind.  Host-global state,
- * not thread safe.
+ * Launch timing (instrumentation, not part of the method): launches of the
+ * timed kinds are bracketed by HIP events on the stream they run on.  Kinds:
+ * 0 = mass apply (operator launch), 1 = stiffness apply, 2 = preconditioner
+ * application, 3 = learned-guess inference in ga_step.  ga_profile(kinds)
+ * clears the totals and times the kinds whose bit (1 << kind) is set in
+ * `kinds` (0 turns timing off, GA_PROF_ALL times every kind; outside [0, 15]:
+ * GA_EINVAL).  Each event pair costs the stream a few microseconds, so time
+ * only the kinds that are needed.  ga_profile_query waits for the recorded
+ * events and returns the summed duration in ms and the number of launches of
+ * one kind.  Host-global state, not thread safe.
  */
-int ga_profile(int enable);
+#define GA_PROF_ALL 15
+int ga_profile(int kinds);
 int ga_profile_query(int kind, double* total_ms, long long* launches);
 
 /* Message for the last non-GA_OK status returned on this thread. */

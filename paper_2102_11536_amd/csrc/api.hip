@@ -61,7 +61,7 @@ int upload(T** dst, const std::vector<T>& v) {
 
 // ---- optional HIP-event timing of the operator and preconditioner launches ----
 struct ProfState {
-  bool on = false;
+  unsigned kinds = 0;  // bit k set: launches of kind k are timed
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];
   double total_ms[4] = {0, 0, 0, 0};
@@ -99,14 +99,14 @@ struct ProfScope {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(int k, hipStream_t s) : kind(k), st(s) {
-    if (!g_prof.on) return;
+    if (!((g_prof.kinds >> kind) & 1u)) return;
     if (g_prof.pending[kind].size() > 4096) prof_drain(kind);
     a = prof_event();
     b = prof_event();
     if (a && b) hipEventRecord(a, st);
   }
   ~ProfScope() {
-    if (!g_prof.on || !a || !b) return;
+    if (!a || !b) return;
     hipEventRecord(b, st);
     g_prof.pending[kind].push_back({a, b});
   }
@@ -519,10 +519,11 @@ extern "C" {
 
 const char* ga_last_error(void) { return g_err.c_str(); }
 
-int ga_profile(int enable) {
+int ga_profile(int kinds) {
+  if (kinds < 0 || kinds > GA_PROF_ALL) { set_error("ga_profile: kinds must be a mask in [0, 15]"); return GA_EINVAL; }
   for (int k = 0; k < 4; ++k) prof_drain(k);
   for (int k = 0; k < 4; ++k) { g_prof.total_ms[k] = 0.0; g_prof.count[k] = 0; }
-  g_prof.on = enable != 0;
+  g_prof.kinds = (unsigned)kinds;
   return GA_OK;
 }
 

@@ -338,10 +338,15 @@ def ga_step(integ, state, nsteps=1, record_iters=True):
 
 
 PROF_MASS, PROF_STIFF, PROF_PINV, PROF_GUESS = 0, 1, 2, 3
+GA_PROF_ALL = 15
 
 
-def ga_profile(enable):
-    _check(load_library().ga_profile(1 if enable else 0))
+def ga_profile(enable, kinds=None):
+    """Time launches of `kinds` (PROF_* values; all four when None) while enabled."""
+    mask = 0
+    if enable:
+        mask = GA_PROF_ALL if kinds is None else sum(1 << int(kd) for kd in set(kinds))
+    _check(load_library().ga_profile(mask))
 
 
 def ga_profile_query(kind):

@@ -57,3 +57,12 @@ def test_code_object_targets_gfx950():
     # the fat binary of the library (built here from source) names its target
     data = open(LIB, "rb").read()
     assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def test_profile_mask_host_checks():
+    # host-only: the kinds mask is range-checked before any event is touched
+    from paper_2102_11536_amd import ga
+    lib = ga.load_library()
+    assert lib.ga_profile(16) == -1
+    assert lib.ga_profile(-1) == -1
+    assert lib.ga_profile(0) == 0
