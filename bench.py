@@ -409,7 +409,7 @@ def main():
                          "c3: deformed cube p=4 128^3 k=3, FP64 and mixed, error per step")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
+        print(f"bench.py: the library runs on exactly one GPU (asked for {args.gpus}); the "
               "multi-GPU decomposition is a design only", file=sys.stderr)
         sys.exit(2)
 
