@@ -50,32 +50,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n=16, p=3, k=2, rho=0.5, budget_s=10.0):
+def cpu_baseline(n=16, p=3, k=2, rho=0.5, budget_s=10.0, dim=3, tau=1e-3, max_steps=None):
     """The oracle (assembled CSR M and K, Kronecker-preconditioned PCG to 1e-10,
-    single thread) stepping the same recipe on a reduced mesh; setup excluded."""
+    single thread) stepping the same recipe, on a reduced mesh for the 3-D cube
+    (deformed map, random-field u0) or on the full 2-D standing-wave problem
+    (identity map, u0 = sin(pi x) sin(pi y)); setup excluded."""
     from threadpoolctl import threadpool_limits
 
     from oracle import galpha, operators, precond, solvers
     from paper_2102_11536_amd import workloads
     with threadpool_limits(1):
-        sp_ = operators.Space(n, p, 3)
-        ctrl = workloads.deformed_cube_ctrl(n, p)
+        sp_ = operators.Space(n, p, dim)
+        if dim == 3:
+            ctrl, U0 = workloads.deformed_cube_ctrl(n, p), workloads.grf(n, p, seed=2000)
+        else:
+            ctrl, U0 = workloads.identity_ctrl(n, p, 2), workloads.standing_wave_u0(n, p)
         M, K = operators.free_operators(sp_, ctrl)
         P = precond.KronPreconditioner(sp_, M.diagonal())
         solve = lambda b: solvers.pcg(lambda v: M @ v, b, P.apply, tol=1e-10)[0]
-        U0 = workloads.grf(n, p, seed=2000)
         L = galpha.initial_state(U0, 0 * U0, k, lambda y: K @ y, solve)
-        tau = 1e-3
         steps, t0 = 0, time.perf_counter()
-        while time.perf_counter() - t0 < budget_s or steps < 2:
+        while (time.perf_counter() - t0 < budget_s or steps < 2) and (max_steps is None or steps < max_steps):
             L = galpha.step(L, tau, k, rho, lambda y: K @ y, solve)
             steps += 1
         dt = time.perf_counter() - t0
-    ndof = (n + p) ** 3
+    ndof = (n + p) ** dim
+    what = (f"deformed cube p={p} k={k} at {n}^3 elements" if dim == 3 else
+            f"2-D standing wave (identity map) p={p} k={k} at {n}^2 elements")
     return {"value": ndof * steps / dt, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle PCG tier (CSR M, K; Kronecker PCG rtol 1e-10), deformed cube p={p} "
-                      f"k={k} at {n}^3 elements ({ndof} DOFs), {steps} steps in {dt:.1f} s, "
-                      f"assembly excluded, 1 thread"}
+            "sample": f"oracle PCG tier (CSR M, K; Kronecker PCG rtol 1e-10), {what} ({ndof} DOFs), "
+                      f"{steps} steps in {dt:.1f} s, assembly excluded, 1 thread"}
 
 
 def bench_multipatch(args):
@@ -193,6 +197,49 @@ def equal_accuracy(args, pt, k, rho, tau, state0, nets, mnorm):
     ga.ga_patch_set_cg(pt, ga.GA_CG_HOST)
     return {"reference": "FP64 PCG at rtol 1e-12", "bar": "E <= 1e-8 over warmup + timed steps",
             "rtols_tried": [1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10], "variants": out}
+
+
+def bench_wave2d(args):
+    """2-D scalar wave on the unit square (identity geometry map), p=2 on 32x32
+    elements (34x34 = 1156 DOFs), k=1, rho_inf=0.5, tau half the stability limit,
+    u0 = sin(pi x) sin(pi y), v0 = 0, PCG rtol 1e-10: the whole 200-step
+    trajectory is timed.  A step here is a handful of tiny launches, so the rate
+    is bound by launch latency, not by HBM."""
+    import torch
+    from paper_2102_11536_amd import ga, workloads
+    n, p, k, rho, nsteps = 32, 2, 1, 0.5, 200
+    dev = "cuda:0"
+    pt = ga.ga_setup_patch(2, n, p, workloads.identity_ctrl(n, p, 2))
+    lam = ga.ga_lambda_max(pt, 50)
+    tau = 0.5 * np.sqrt(ga.ga_stability_limit(rho) / lam)
+    u = torch.as_tensor(workloads.standing_wave_u0(n, p), device=dev)
+    integ = ga.ga_integrator_create(pt, k, rho, tau, rtol=args.rtol, maxit=200)
+    state0 = [torch.zeros(pt.n_free, dtype=torch.float64, device=dev) for _ in range(3 * k)]
+    ga.ga_init_state(integ, u, torch.zeros_like(u), state0)
+    warm = [t.clone() for t in state0]
+    ga.ga_step(integ, warm, args.warmup)
+    state = [t.clone() for t in state0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = ga.ga_step(integ, state, nsteps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    integ.close()
+    ndof = (n + p) ** 2
+    log(f"[bench] wave2d: {dt / nsteps * 1e3:.3f} ms/step, iters {np.mean(its):.2f}")
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] wave2d cpu baseline (oracle)")
+        cpu = cpu_baseline(n=n, p=p, k=k, rho=rho, dim=2, tau=tau, budget_s=20.0, max_steps=nsteps)
+    out = {"metric": "DOF-steps/s, 2-D standing wave p=2 32^2 k=1", "value": ndof * nsteps / dt,
+           "unit": "DOF-steps/s", "n_gpus": 1, "steps": nsteps, "warmup": args.warmup,
+           "ms_per_step": dt / nsteps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "wave2d_identity_p2_n32_k1", "n_dof": ndof, "n_free": pt.n_free, "k": k,
+                      "rho": rho, "tau": tau, "rtol": args.rtol, "pcg_iters_mean": float(np.mean(its)),
+                      "bound": "launch latency (1156 DOFs per step)"},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
 
 
 def bench_c3(args):
@@ -401,12 +448,13 @@ def main():
                     help="counter-collection mode: run only these operator applies (e.g. K2,M2), "
                          "three times each, then a 1 GiB device copy used to calibrate "
                          "FETCH_SIZE/WRITE_SIZE, and exit")
-    ap.add_argument("--workload", default="cube", choices=["cube", "multipatch", "glued", "dispersion", "c3"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "multipatch", "glued", "dispersion", "c3", "wave2d"],
                     help="cube: the single-patch headline workload; multipatch: 12 independent "
                          "patches of uneven size and degree stepped as one batch; glued: a 2x2x2 "
                          "brick of C0-glued patches with the additive Schwarz preconditioner; "
                          "dispersion: the 1-D study of Sec. 6.2, every wavenumber one system; "
-                         "c3: deformed cube p=4 128^3 k=3, FP64 and mixed, error per step")
+                         "c3: deformed cube p=4 128^3 k=3, FP64 and mixed, error per step; "
+                         "wave2d: the 2-D standing wave p=2 32^2 k=1, 200 steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on exactly one GPU (asked for {args.gpus}); the "
@@ -422,6 +470,8 @@ def main():
         return bench_glued(args)
     if args.workload == "dispersion":
         return bench_dispersion(args)
+    if args.workload == "wave2d":
+        return bench_wave2d(args)
     if args.workload == "c3":
         return bench_c3(args)
     n, p, k, rho = args.n, args.p, args.k, 0.5
