@@ -18,8 +18,9 @@
 //             points (value; or x-, y-derivatives and value);
 //   z sweep   per Gauss layer: contraction along z, the 1 or 6 quadrature
 //             factors (a small ring prefetches the next layers; the factor
-//             stream is contiguous along z, read once, fully coalesced) and
-//             the transposed z contraction into accumulators s[f][p];
+//             stream is contiguous along z, read once with nontemporal, fully
+//             coalesced loads) and the transposed z contraction into
+//             accumulators s[f][p];
 //   backward  the plane no later layer touches is finished: transposed y and
 //             x contractions as dense products with zero-padded transposed
 //             basis tables in LDS, then FP64 atomic adds into y (xy
@@ -31,8 +32,6 @@
 // [qz][component pair][qy][qx][2] (each thread reads its 6 components as three
 // 16-byte pairs).
 #include <hip/hip_runtime.h>
-
-#include <type_traits>
 
 #include "ga_internal.h"
 #include "kernels.h"
@@ -164,18 +163,20 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   const S* fcol = fac + (size_t)txy * qz_tot * NC * NT + tid;
   // factors of Gauss layer q: the stiffness stores its 6 components as 3 pairs
   // per thread ([layer][pair][thread][2]), read with 16-byte loads
+  // The factor stream is read exactly once per apply: nontemporal loads keep it from
+  // displacing the coefficient vectors (re-read by neighbouring tiles) in the caches.
   auto load_fac = [&](int q, S (&dst)[NC]) {
     if constexpr (MODE == 1) {
-      using V2 = typename std::conditional<sizeof(S) == 8, double2, float2>::type;
+      typedef S V2 __attribute__((ext_vector_type(2)));
       const V2* b2 = reinterpret_cast<const V2*>(fac + ((size_t)txy * qz_tot + q) * NC * NT) + tid;
 #pragma unroll
       for (int h = 0; h < NC / 2; ++h) {
-        const V2 v = b2[(size_t)h * NT];
+        const V2 v = __builtin_nontemporal_load(b2 + (size_t)h * NT);
         dst[2 * h] = v.x;
         dst[2 * h + 1] = v.y;
       }
     } else {
-      dst[0] = fcol[(size_t)q * NT];
+      dst[0] = __builtin_nontemporal_load(fcol + (size_t)q * NT);
     }
   };
 
