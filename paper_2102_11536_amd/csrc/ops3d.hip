@@ -22,9 +22,10 @@
 //             coalesced loads) and the transposed z contraction into
 //             accumulators s[f][p];
 //   backward  the plane no later layer touches is finished: transposed y and
-//             x contractions as dense products with zero-padded transposed
-//             basis tables in LDS, then FP64 atomic adds into y (xy
-//             neighbours and the two ends of a z range share planes).
+//             x contractions with zero-padded transposed basis tables in LDS
+//             (dense products for the mass; for the stiffness only the taps of
+//             the elements each basis function touches), then FP64 atomic adds
+//             into y (xy neighbours and the two ends of a z range share planes).
 // The stiffness kernel uses 4x4-element columns (6 factors per point, high
 // register use); the mass kernels use wider columns so the fixed per-plane
 // work is spread over more Gauss points.
@@ -91,6 +92,17 @@ constexpr int mass_ring(int P, int NR) {
 #endif
 }
 
+// Value held by lane (l ^ 1) of the wave (DPP quad permutation [1,0,3,2]); both
+// lanes of the pair must be active.
+__device__ __forceinline__ double lane_xor1(double v) {
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
 // MODE: 0 mass, 1 stiffness, 2 diag(M) (tables hold squared values, x unused)
 // One workgroup's share: logical tile `lid` = (xy column, z range) of one patch.
 // x and y hold NR right-hand sides `n_free` entries apart.
@@ -107,7 +119,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   constexpr int NPL = NB * NB;                  // coefficients per plane of the box
   constexpr int NF = (MODE == 1) ? 3 : 1;       // fields at the Gauss points
   constexpr int NA = (MODE == 1) ? 2 : 1;       // x-contracted fields
-  constexpr int NRF = (MODE == 1) ? 2 : 1;      // y-back-contracted fields
+  constexpr int NFY = NF;                       // y-back-contracted rows per right-hand side
   constexpr int NC = (MODE == 1) ? 6 : 1;       // factor components per Gauss point
   constexpr int XPR = (NR * NPL + NT - 1) / NT; // prefetched plane values per thread
   constexpr int QP = QT + 1;                    // padded LDS row (no bank conflicts)
@@ -123,7 +135,11 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   __shared__ S Xs[NR][NPL];
   __shared__ S As[NR][NA][NB * QT];
   __shared__ S Ss[NR][NF][NT];
-  __shared__ S Rs[NR][NRF][NB * QP];
+  __shared__ S Rs[NR][NFY][NB * QP];
+  // box indices 0..NB-1 ordered by decreasing number of elements of the tile their
+  // basis function touches (the middle ones first): the stiffness's y-stage rows in
+  // this order have nearly equal trip counts within a wave
+  __shared__ int ordv[NB];
 
   const int tid = threadIdx.x;
   const int qx = tid % QT, qy = tid / QT;
@@ -158,6 +174,12 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
     const int a = i / QT, q = i % QT;
     xB[a][q] = (S)tB0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a];
     xD[a][q] = MODE == 1 ? (S)tD0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a] : (S)0;
+  }
+  if (tid == 0) {
+    int j = 0;
+    for (int ne = (P + 1 < TE ? P + 1 : TE); ne >= 1; --ne)
+      for (int i = 0; i < NB; ++i)
+        if (min(TE - 1, i) - max(0, i - P) + 1 == ne) ordv[j++] = i;
   }
   const int eyq = qy / Q, jyq = qy % Q;
   const S* fcol = fac + (size_t)txy * qz_tot * NC * NT + tid;
@@ -202,6 +224,92 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
         if (f >= 0) v = x[(size_t)r * n_free + f];
       }
       xpre[k] = v;
+    }
+  };
+
+  // backward, y stage: Rs[r][f][iy][q] = sum over the Gauss rows k of the elements
+  // that basis iy touches of W_f(iy, k) Ss[r][f][k][q], W = y derivative (field 1 of
+  // the stiffness) or value.  Stiffness: one field per row, rows in ordv order, q
+  // fastest, only the nonzero taps (half the work of the dense product and no mixed
+  // one- and two-field items within a wave)
+  auto back_y = [&]() {
+    if constexpr (MODE != 1) {
+      // mass and diag(M): one field, dense products with the zero-padded transposed
+      // table (measured faster for these short-register kernels)
+      int lz = 0;
+      asm volatile("" : "+v"(lz));
+      for (int i = tid; i < NR * NB * QT; i += NT) {
+        const int r = i / (NB * QT), b = i % (NB * QT);
+        const int q = b % QT, iy = b / QT;
+        const S* ty_ = &tBs[1][iy * QP + lz];
+        S acc = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < QT; ++k) acc += ty_[k] * Ss[r][0][k * QT + q];
+        Rs[r][0][iy * QP + q] = acc;
+      }
+      return;
+    }
+    for (int i = tid; i < NB * NR * NFY * QT; i += NT) {
+      const int q = i % QT, row = i / QT;
+      const int f = row % NFY, r = (row / NFY) % NR, iy = ordv[row / (NFY * NR)];
+      const S* w = (MODE == 1 && f == 1) ? &tDs[1][iy * QP] : &tBs[1][iy * QP];
+      const S* src = &Ss[r][f][q];
+      const int k1 = (min(TE - 1, iy) + 1) * Q;
+      S acc = 0.0;
+      for (int k = max(0, iy - P) * Q; k < k1; k += Q) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) acc += w[k + j] * src[(k + j) * QT];
+      }
+      Rs[r][f][iy * QP + q] = acc;
+    }
+  };
+  // backward, x stage and the atomic adds of plane iz: coefficient (ix, iy) sums
+  // over the Gauss points of the elements basis ix touches (x derivative for field
+  // 0 of the stiffness, value otherwise).  Stiffness: two lanes share a coefficient,
+  // each taking every other element, combined by a lane exchange (every thread runs
+  // the same number of rounds); coefficients in x-fastest order, so the atomic adds
+  // of a wave fall on few cache lines (half the write traffic of the support order)
+  auto back_x = [&](int iz) {
+    if constexpr (MODE != 1) {
+      int lz = 0;
+      asm volatile("" : "+v"(lz));
+      for (int i = tid; i < NR * NPL; i += NT) {
+        const int r = i / NPL, b = i % NPL;
+        const int ix = b % NB, iy = b / NB;
+        const S* tx_ = &tBs[0][ix * QP + lz];
+        S acc = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < QT; ++k) acc += tx_[k] * Rs[r][0][iy * QP + k];
+        const long long f = free_index3(g, e0x + ix, e0y + iy, iz);
+        if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
+      }
+      return;
+    }
+    constexpr int NX = 2 * NB * NR * NB;
+    for (int i0 = 0; i0 < NX; i0 += NT) {
+      const int l = i0 + tid, h = l & 1, it = l >> 1;
+      const bool act = l < NX;
+      const int ix = it % NB, iy = (it / NB) % NB, r = act ? it / NPL : 0;
+      S acc = 0.0;
+      if (act) {
+        const int e1 = min(TE - 1, ix);
+        for (int e = max(0, ix - P) + h; e <= e1; e += 2) {
+#pragma unroll
+          for (int j = 0; j < Q; ++j) {
+            const int k = e * Q + j;
+            if constexpr (MODE == 1)
+              acc += tDs[0][ix * QP + k] * Rs[r][0][iy * QP + k] +
+                     tBs[0][ix * QP + k] * (Rs[r][1][iy * QP + k] + Rs[r][2][iy * QP + k]);
+            else
+              acc += tBs[0][ix * QP + k] * Rs[r][0][iy * QP + k];
+          }
+        }
+      }
+      acc += lane_xor1(acc);
+      if (act && h == 0) {
+        const long long f = free_index3(g, e0x + ix, e0y + iy, iz);
+        if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
+      }
     }
   };
 
@@ -258,45 +366,15 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
 
   // finish coefficient plane iz from s[.][.][0]: transposed y and x contractions
   auto backward_plane = [&](int iz) {
-    int lz = 0;
-    asm volatile("" : "+v"(lz));
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int f = 0; f < NF; ++f) Ss[r][f][tid] = s[r][f][0];
     __syncthreads();
-    for (int i = tid; i < NR * NRF * NB * QT; i += NT) {
-      const int r = i / (NRF * NB * QT), b = i % (NRF * NB * QT);
-      const int q = b % QT, iy = (b / QT) % NB, cf = b / (NB * QT);
-      const S* ty_ = &tBs[1][iy * QP + lz];
-      const S* tdy = &tDs[1][iy * QP + lz];
-      S acc = 0.0;
-      if (MODE == 1 && cf == 1) {
-#pragma unroll 4
-        for (int k = 0; k < QT; ++k)
-          acc += tdy[k] * Ss[r][1][k * QT + q] + ty_[k] * Ss[r][2][k * QT + q];
-      } else {
-#pragma unroll 4
-        for (int k = 0; k < QT; ++k) acc += ty_[k] * Ss[r][0][k * QT + q];
-      }
-      Rs[r][cf][iy * QP + q] = acc;
-    }
+    back_y();
     __syncthreads();
-    for (int i = tid; i < NR * NPL; i += NT) {
-      const int r = i / NPL, b = i % NPL;
-      const int ix = b % NB, iy = b / NB;
-      const S* tx_ = &tBs[0][ix * QP + lz];
-      const S* tdx = &tDs[0][ix * QP + lz];
-      S acc = 0.0;
-#pragma unroll 4
-      for (int k = 0; k < QT; ++k) {
-        if (MODE == 1) acc += tdx[k] * Rs[r][0][iy * QP + k] + tx_[k] * Rs[r][1][iy * QP + k];
-        else acc += tx_[k] * Rs[r][0][iy * QP + k];
-      }
-      const long long f = free_index3(g, e0x + ix, e0y + iy, iz);
-      if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
-    }
+    back_x(iz);
   };
 
   auto shift_c_ = [&]() {
@@ -323,22 +401,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
       if (i < NR * NPL) Xs[i / NPL][i % NPL] = xpre[k];
     }
     __syncthreads();
-    for (int i = tid; i < NR * NRF * NB * QT; i += NT) {
-      const int r = i / (NRF * NB * QT), b = i % (NRF * NB * QT);
-      const int q = b % QT, iy = (b / QT) % NB, cf = b / (NB * QT);
-      const S* ty_ = &tBs[1][iy * QP + lz];
-      const S* tdy = &tDs[1][iy * QP + lz];
-      S acc = 0.0;
-      if (MODE == 1 && cf == 1) {
-#pragma unroll 4
-        for (int k = 0; k < QT; ++k)
-          acc += tdy[k] * Ss[r][1][k * QT + q] + ty_[k] * Ss[r][2][k * QT + q];
-      } else {
-#pragma unroll 4
-        for (int k = 0; k < QT; ++k) acc += ty_[k] * Ss[r][0][k * QT + q];
-      }
-      Rs[r][cf][iy * QP + q] = acc;
-    }
+    back_y();
     for (int i = tid; i < NR * NB * QT; i += NT) {
       const int r = i / (NB * QT), b = i % (NB * QT);
       const int q = b % QT, iy = b / QT;
@@ -355,20 +418,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
       }
     }
     __syncthreads();
-    for (int i = tid; i < NR * NPL; i += NT) {
-      const int r = i / NPL, b = i % NPL;
-      const int ix = b % NB, iy = b / NB;
-      const S* tx_ = &tBs[0][ix * QP + lz];
-      const S* tdx = &tDs[0][ix * QP + lz];
-      S acc = 0.0;
-#pragma unroll 4
-      for (int k = 0; k < QT; ++k) {
-        if (MODE == 1) acc += tdx[k] * Rs[r][0][iy * QP + k] + tx_[k] * Rs[r][1][iy * QP + k];
-        else acc += tx_[k] * Rs[r][0][iy * QP + k];
-      }
-      const long long f = free_index3(g, e0x + ix, e0y + iy, iz);
-      if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
-    }
+    back_x(iz);
     shift_c_();
     const S* by = &sB[1][(eyq * Q + jyq) * (P + 1) + lz];
     const S* dy = &sD[1][(eyq * Q + jyq) * (P + 1) + lz];
