@@ -106,7 +106,10 @@ __device__ __forceinline__ float lane_xor1(float v) {
 // MODE: 0 mass, 1 stiffness, 2 diag(M) (tables hold squared values, x unused)
 // One workgroup's share: logical tile `lid` = (xy column, z range) of one patch.
 // x and y hold NR right-hand sides `n_free` entries apart.
-template <int P, int TE, int MODE, int NR, typename S>
+// BW selects the backward stages: 0 dense products (any MODE), 1 dense y stage and
+// the x stage with two lanes per coefficient (mass), 2 both stages over the
+// supporting elements only (stiffness)
+template <int P, int TE, int MODE, int NR, typename S, int BW>
 __device__ __forceinline__ void
 op3d_body(const S* __restrict__ x, S* __restrict__ y,
           const S* __restrict__ fac,
@@ -119,7 +122,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   constexpr int NPL = NB * NB;                  // coefficients per plane of the box
   constexpr int NF = (MODE == 1) ? 3 : 1;       // fields at the Gauss points
   constexpr int NA = (MODE == 1) ? 2 : 1;       // x-contracted fields
-  constexpr int NFY = NF;                       // y-back-contracted rows per right-hand side
+  constexpr int NFY = (BW == 2) ? 3 : (MODE == 1 ? 2 : 1);  // y-back-contracted rows per RHS
   constexpr int NC = (MODE == 1) ? 6 : 1;       // factor components per Gauss point
   constexpr int XPR = (NR * NPL + NT - 1) / NT; // prefetched plane values per thread
   constexpr int QP = QT + 1;                    // padded LDS row (no bank conflicts)
@@ -175,7 +178,7 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
     xB[a][q] = (S)tB0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a];
     xD[a][q] = MODE == 1 ? (S)tD0[(size_t)e0x * Q * (P + 1) + q * (P + 1) + a] : (S)0;
   }
-  if (tid == 0) {
+  if (BW == 2 && tid == 0) {
     int j = 0;
     for (int ne = (P + 1 < TE ? P + 1 : TE); ne >= 1; --ne)
       for (int i = 0; i < NB; ++i)
@@ -233,19 +236,26 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   // fastest, only the nonzero taps (half the work of the dense product and no mixed
   // one- and two-field items within a wave)
   auto back_y = [&]() {
-    if constexpr (MODE != 1) {
-      // mass and diag(M): one field, dense products with the zero-padded transposed
-      // table (measured faster for these short-register kernels)
+    if constexpr (BW != 2) {
+      // dense products with the zero-padded transposed table over all Gauss rows of
+      // the tile; the stiffness sums its fields 1 and 2 in one row
       int lz = 0;
       asm volatile("" : "+v"(lz));
-      for (int i = tid; i < NR * NB * QT; i += NT) {
-        const int r = i / (NB * QT), b = i % (NB * QT);
-        const int q = b % QT, iy = b / QT;
+      for (int i = tid; i < NR * NFY * NB * QT; i += NT) {
+        const int r = i / (NFY * NB * QT), b = i % (NFY * NB * QT);
+        const int q = b % QT, iy = (b / QT) % NB, cf = b / (NB * QT);
         const S* ty_ = &tBs[1][iy * QP + lz];
+        const S* tdy = &tDs[1][iy * QP + lz];
         S acc = 0.0;
+        if (MODE == 1 && cf == 1) {
 #pragma unroll 4
-        for (int k = 0; k < QT; ++k) acc += ty_[k] * Ss[r][0][k * QT + q];
-        Rs[r][0][iy * QP + q] = acc;
+          for (int k = 0; k < QT; ++k)
+            acc += tdy[k] * Ss[r][1][k * QT + q] + ty_[k] * Ss[r][2][k * QT + q];
+        } else {
+#pragma unroll 4
+          for (int k = 0; k < QT; ++k) acc += ty_[k] * Ss[r][0][k * QT + q];
+        }
+        Rs[r][cf][iy * QP + q] = acc;
       }
       return;
     }
@@ -265,21 +275,26 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   };
   // backward, x stage and the atomic adds of plane iz: coefficient (ix, iy) sums
   // over the Gauss points of the elements basis ix touches (x derivative for field
-  // 0 of the stiffness, value otherwise).  Stiffness: two lanes share a coefficient,
+  // 0 of the stiffness, value otherwise).  BW 1, 2: two lanes share a coefficient,
   // each taking every other element, combined by a lane exchange (every thread runs
   // the same number of rounds); coefficients in x-fastest order, so the atomic adds
-  // of a wave fall on few cache lines (half the write traffic of the support order)
+  // of a wave fall on few cache lines (half the write traffic of the support order).
+  // BW 0: one lane per coefficient, dense product.
   auto back_x = [&](int iz) {
-    if constexpr (MODE != 1) {
+    if constexpr (BW == 0) {
       int lz = 0;
       asm volatile("" : "+v"(lz));
       for (int i = tid; i < NR * NPL; i += NT) {
         const int r = i / NPL, b = i % NPL;
         const int ix = b % NB, iy = b / NB;
         const S* tx_ = &tBs[0][ix * QP + lz];
+        const S* tdx = &tDs[0][ix * QP + lz];
         S acc = 0.0;
 #pragma unroll 4
-        for (int k = 0; k < QT; ++k) acc += tx_[k] * Rs[r][0][iy * QP + k];
+        for (int k = 0; k < QT; ++k) {
+          if (MODE == 1) acc += tdx[k] * Rs[r][0][iy * QP + k] + tx_[k] * Rs[r][1][iy * QP + k];
+          else acc += tx_[k] * Rs[r][0][iy * QP + k];
+        }
         const long long f = free_index3(g, e0x + ix, e0y + iy, iz);
         if (f >= 0) unsafeAtomicAdd(&y[(size_t)r * n_free + f], alpha * acc);
       }
@@ -297,9 +312,9 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
 #pragma unroll
           for (int j = 0; j < Q; ++j) {
             const int k = e * Q + j;
-            if constexpr (MODE == 1)
+            if constexpr (BW == 2)
               acc += tDs[0][ix * QP + k] * Rs[r][0][iy * QP + k] +
-                     tBs[0][ix * QP + k] * (Rs[r][1][iy * QP + k] + Rs[r][2][iy * QP + k]);
+                     tBs[0][ix * QP + k] * (Rs[r][1][iy * QP + k] + Rs[r][NFY - 1][iy * QP + k]);
             else
               acc += tBs[0][ix * QP + k] * Rs[r][0][iy * QP + k];
           }
@@ -557,8 +572,27 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   }
 }
 
+// Backward variant per instance (measured): the stiffness on up to two right-hand
+// sides takes the support-limited stages; the single-patch p = 3 FP64 mass on one
+// or two right-hand sides the two-lane x stage (its two-RHS instance then needs a
+// bound of 4 waves per SIMD to keep its occupancy); every other instance the dense
+// stages, where the extra registers would spill or cost occupancy.
+template <int P, int MODE, int NR, typename S>
+constexpr int op3d_backward() {
+  return (MODE == 1 && NR <= 2) ? 2 : ((MODE == 0 && P == 3 && NR <= 2 && sizeof(S) == 8) ? 1 : 0);
+}
+template <int P, int MODE, int NR>
+constexpr int op3d_group_backward() {
+  return (MODE == 1 && NR <= 2 && P <= 3) ? 2 : 0;
+}
+template <int P, int MODE, int NR, typename S>
+constexpr int op3d_waves() {
+  return MODE == 1 ? GA_OP3_WAVES_K
+                   : ((MODE == 0 && P == 3 && NR == 2 && sizeof(S) == 8) ? 4 : GA_OP3_WAVES_M);
+}
+
 template <int P, int TE, int MODE, int NR, typename S>
-__global__ void __launch_bounds__((Tile3<P, TE>::NT), (MODE == 1 ? GA_OP3_WAVES_K : GA_OP3_WAVES_M))
+__global__ void __launch_bounds__((Tile3<P, TE>::NT), (op3d_waves<P, MODE, NR, S>()))
 op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
             const S* __restrict__ fac,
             const double* __restrict__ tB0, const double* __restrict__ tB1,
@@ -573,8 +607,8 @@ op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
     for (int r = 0; r < NR; ++r) any |= gate[r * NSCAL + S_ACTIVE] != 0.0;
     if (!any) return;
   }
-  op3d_body<P, TE, MODE, NR, S>(x, y, fac, tB0, tB1, tB2, tD0, tD1, tD2, g, ze, n_free, alpha,
-                                xcd_remap(blockIdx.x, gridDim.x));
+  op3d_body<P, TE, MODE, NR, S, op3d_backward<P, MODE, NR, S>()>(
+      x, y, fac, tB0, tB1, tB2, tD0, tD1, tD2, g, ze, n_free, alpha, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Several patches of one degree in one launch: a static queue of tiles, the
@@ -594,9 +628,9 @@ op3d_group_kernel(const OpGroupEntry* __restrict__ ents, int nent, const S* __re
     while (e + 1 < nent && t >= ents[e + 1].tile0) ++e;
     const OpGroupEntry& d = ents[e];
     __syncthreads();  // the previous tile has finished with the LDS
-    op3d_body<P, TE, MODE, NR, S>(x + d.off, y + d.off, (const S*)d.fac, d.tB[0], d.tB[1], d.tB[2],
-                                  d.tD[0], d.tD[1], d.tD[2], d.g, d.ze, stride, alpha,
-                                  (unsigned)(t - d.tile0));
+    op3d_body<P, TE, MODE, NR, S, op3d_group_backward<P, MODE, NR>()>(x + d.off, y + d.off, (const S*)d.fac, d.tB[0], d.tB[1],
+                                             d.tB[2], d.tD[0], d.tD[1], d.tD[2], d.g, d.ze, stride,
+                                             alpha, (unsigned)(t - d.tile0));
   }
 }
 
