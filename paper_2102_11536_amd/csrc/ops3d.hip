@@ -301,6 +301,9 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
       return;
     }
     constexpr int NX = 2 * NB * NR * NB;
+    // the pair (l, l ^ 1) must be the lane pair (tid, tid ^ 1) of one wave: true when
+    // every round starts at an even l (even NT) or there is a single round
+    static_assert(BW == 0 || NT % 2 == 0 || NX <= NT, "two-lane x stage needs aligned lane pairs");
     for (int i0 = 0; i0 < NX; i0 += NT) {
       const int l = i0 + tid, h = l & 1, it = l >> 1;
       const bool act = l < NX;
@@ -332,7 +335,6 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   auto forward_plane = [&]() {
     int lz = 0;
     asm volatile("" : "+v"(lz));  // keep the basis-table reads below in LDS (no hoisting)
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < XPR; ++k) {
       const int i = tid + k * NT;
@@ -381,7 +383,6 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
 
   // finish coefficient plane iz from s[.][.][0]: transposed y and x contractions
   auto backward_plane = [&](int iz) {
-    __syncthreads();
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -405,7 +406,9 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
   auto step_planes = [&](int iz) {
     int lz = 0;
     asm volatile("" : "+v"(lz));
-    __syncthreads();
+    // no barrier needed before these writes: Ss and Xs were last read between the
+    // second and third barriers of the previous plane step (or forward/backward
+    // plane), and the z sweep in between uses no LDS
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
