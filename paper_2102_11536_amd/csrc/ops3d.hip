@@ -402,13 +402,13 @@ op3d_body(const S* __restrict__ x, S* __restrict__ y,
         for (int j = 0; j < P; ++j) c[r][f][j] = c[r][f][j + 1];
   };
   // finish plane iz (backward) and contract the prefetched plane (forward) in
-  // one pass of three barriers: the two use disjoint LDS buffers
+  // one pass of two barriers: the two use disjoint LDS buffers
   auto step_planes = [&](int iz) {
     int lz = 0;
     asm volatile("" : "+v"(lz));
-    // no barrier needed before these writes: Ss and Xs were last read between the
-    // second and third barriers of the previous plane step (or forward/backward
-    // plane), and the z sweep in between uses no LDS
+    // no barrier needed before these writes: Ss and Xs were last read before the
+    // last barrier of the previous plane step (or forward/backward plane), and the
+    // z sweep in between uses no LDS
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
