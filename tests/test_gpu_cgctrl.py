@@ -12,6 +12,12 @@ from paper_2102_11536_amd import ga, workloads
 from tests.helpers import OracleProblem, rel
 
 pytestmark = pytest.mark.gpu
+# Host- and device-controlled PCG run the same kernels; their results differ only
+# by the order of the FP64 atomic additions of the operator kernels (a different
+# order on every run), rounding the CG recurrence amplifies over its iterations:
+# up to ~1.2e-12 relative has been seen, so the bar is 1e-11, still 10x below the
+# loosest tolerance the comparisons are checked at against Cholesky (1e-10)
+ATOMIC_ORDER_BAR = 1e-11
 DEV = "cuda:0"
 
 
@@ -69,7 +75,7 @@ def test_device_control_matches_host_and_cholesky(n, p):
         assert ih == idv, (i, ih, idv)
         for r in range(B.shape[0]):
             # the same launches up to the order of the atomic additions
-            assert rel(xd[r], xh[r]) < 1e-12, (i, r)
+            assert rel(xd[r], xh[r]) < ATOMIC_ORDER_BAR, (i, r)
             assert rd[r] <= rtol
             if rtol <= 1e-10:
                 assert rel(xd[r], pr.chol.solve(B[r])) < 1e-8
@@ -102,7 +108,7 @@ def test_device_control_steps_match_oracle(k):
         o = ora[8][s - 2]
         d = res[ga.GA_CG_DEVICE][0][s] - o
         assert np.sqrt(d @ (M @ d)) <= 1e-10 * max(np.sqrt(o @ (M @ o)), 1e-300), s
-        assert rel(res[ga.GA_CG_DEVICE][0][s], res[ga.GA_CG_HOST][0][s]) < 1e-12
+        assert rel(res[ga.GA_CG_DEVICE][0][s], res[ga.GA_CG_HOST][0][s]) < ATOMIC_ORDER_BAR
     _say("  host reads: host control", res[ga.GA_CG_HOST][2][1], "device control", res[ga.GA_CG_DEVICE][2][1])
 
 
