@@ -143,7 +143,8 @@ def test_glued_solve_iterations_read_ahead():
     x2 = torch.zeros_like(x)
     its3 = ga.ga_mp_mass_solve(fresh, _t(B2.ravel()), x2, nrhs=2)
     assert list(its2) == list(its3), (its1, its2, its3)
-    assert rel(_np(x2), _np(x)) < 1e-13
+    # same launches; only the run-to-run order of the FP64 atomic additions differs
+    assert rel(_np(x2), _np(x)) < 1e-11
 
 
 def test_mp_errors():
