@@ -47,12 +47,20 @@ enum {
   GA_EUNSTABLE = -6   /* a state norm became non-finite during stepping   */
 };
 
-/* Arithmetic of the mass solves.  GA_FP64: PCG in FP64 throughout.  GA_FP32:
- * FP64 iterative refinement (residual r = b - M x with FP64 factors, FP64
- * dot products and norms, FP64 solution) around an inner FP32 flexible PCG
- * (FP32 mass factors, vectors and preconditioner; dots accumulated in FP64).
- * The stiffness apply and the state update are FP64 in both modes. */
-enum { GA_FP64 = 0, GA_FP32 = 1 };
+/* Arithmetic (precision is an addition to the paper, which computes in FP64).
+ *   GA_FP64  FP64 factors, vectors and arithmetic.
+ *   GA_FP32  FP32 factors, vectors and arithmetic.
+ *   GA_BF16  quadrature factors stored in BF16 (round to nearest even) and widened
+ *            to FP32 for the FP32 sum-factorised contractions; the preconditioner's
+ *            per-axis dense contractions on the matrix cores with BF16 operands and
+ *            FP32 accumulation (FP32 vectors).
+ * In the mass solves (ga_mass_solve, ga_integrator_create) GA_FP32 and GA_BF16 select
+ * the inner arithmetic of an FP64 iterative refinement: the residual r = b - M x
+ * with FP64 factors, the dot products and norms, the stopping test and the solution
+ * are FP64; the correction M d = r comes from an inner flexible PCG in that
+ * precision.  The stiffness apply and the state update of ga_step are FP64 in every
+ * mode. */
+enum { GA_FP64 = 0, GA_FP32 = 1, GA_BF16 = 2 };
 /* Initial guess of the stage solves in ga_step, from the stage solutions of
  * the previous steps: zero (the paper's choice), the previous step's, or the
  * polynomial extrapolation through the last (up to 4) steps, or the learned
@@ -73,9 +81,12 @@ enum { GA_GUESS_ZERO = 0, GA_GUESS_PREV = 1, GA_GUESS_EXTRAP = 2, GA_GUESS_LEARN
  *              F = sum_i C_i B_i, co-lex over the full grid of
  *              N_dof = prod (n_a + p) coefficients.  Read during the call only.
  * Builds, on the device: the quadrature factors w|det J| and
- * w|det J| J^{-1} J^{-T}, D = diag(M), the scaling s = (Dhat/D)^{1/2} and the
- * dense inverses of the univariate parametric mass matrices on the free
- * coefficients.  Returns GA_EGEOMETRY (and no handle) if det J <= 0 anywhere.
+ * w|det J| J^{-1} J^{-T}, D = diag(M), the scaling s = (Dhat/D)^{1/2}, and for
+ * each axis the univariate parametric mass matrix Mhat_a on the free coefficients
+ * as its banded Cholesky factor (used by the default preconditioner) and as its
+ * dense inverse (used by the dense preconditioner modes).  FP32 and BF16 copies
+ * of the factors, and the inverses packed for the matrix cores, are built on
+ * first use.  Returns GA_EGEOMETRY (and no handle) if det J <= 0 anywhere.
  */
 int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host,
                    void* stream, ga_patch** out);
@@ -84,7 +95,7 @@ int ga_setup_patch(int dim, const int* n_el, int p, const double* ctrl_host,
  * the homogeneous Dirichlet data (3-D only): bit 2a of dirichlet_faces is the
  * face xi_a = 0, bit 2a+1 the face xi_a = 1 (0x3F = all six, ga_setup_patch).
  * Coefficients on the other faces stay free, as on an interface of a glued
- * multi-patch domain (Sec. 5.5): along axis a the free coefficients are
+ * multi-patch domain (Sec. 5.3): along axis a the free coefficients are
  * lo_a .. m_a - 1 - hi_a with lo_a, hi_a the two face bits, and every vector
  * of the patch holds them in co-lex order.  M-hat, its factors and the scaling
  * s are those of that index range.
@@ -111,25 +122,37 @@ int ga_diag_M(ga_patch* patch, double* d_dev, void* stream);
  * mass_matrix) or K (which = 'K', stiffness of eq. mp with omega = 1),
  * restricted to the free coefficients, applied matrix-free by sum
  * factorisation over the Gauss points.  x and y must not overlap.
+ *   prec  GA_FP64; or (3-D patches) GA_FP32 / GA_BF16: x is rounded to FP32, the
+ *         factors are the FP32 / BF16 copies (built on the first such call), the
+ *         contractions run in FP32 and the FP32 result is widened into y.
+ * The low-precision forms use the patch's work area (calls on one patch from
+ * overlapping streams race).
  */
-int ga_apply_MK(ga_patch* patch, char which, int nrhs, double alpha,
+int ga_apply_MK(ga_patch* patch, char which, int nrhs, int prec, double alpha,
                 const double* x_dev, double* y_dev, void* stream);
 
 /*
  * ga_apply_Pinv -- z = P^{-1} r for nrhs vectors, with
  * P = D^{1/2} Dhat^{-1/2} Mhat Dhat^{-1/2} D^{1/2} (Sec. 5.4), applied as
  * z = s * (Mz^{-1} x My^{-1} x Mx^{-1})(s * r), one univariate solve along
- * each tensor axis: by default forward and backward substitution with the
- * banded Cholesky factor of Mhat_a (where a z-plane fits the on-chip
- * staging, 152 KiB), otherwise a product with the dense inverse of Mhat_a.
- * r and z may be the same buffer.
+ * each tensor axis.  r and z may be the same buffer.
+ *   prec  GA_FP64: the patch's preconditioner mode (ga_patch_set_pinv): by default
+ *         forward and backward substitution with the banded Cholesky factor of
+ *         Mhat_a (where a z-plane fits the on-chip staging, 152 KiB), otherwise a
+ *         product with the dense inverse of Mhat_a;
+ *         GA_FP32 (3-D): the same in FP32 (r rounded to FP32, result widened);
+ *         GA_BF16 (3-D, axes of at most 256 free coefficients): the dense inverse
+ *         products on the matrix cores with BF16 operands and FP32 accumulation.
  */
-int ga_apply_Pinv(ga_patch* patch, int nrhs, const double* r_dev, double* z_dev,
+int ga_apply_Pinv(ga_patch* patch, int nrhs, int prec, const double* r_dev, double* z_dev,
                   void* stream);
-/* Preconditioner algorithm of a patch (both compute the same P^{-1}):
- * GA_PINV_AUTO (banded solves when they fit, the default) or GA_PINV_DENSE
- * (dense inverse products always). */
-enum { GA_PINV_AUTO = 0, GA_PINV_DENSE = 1 };
+/* Preconditioner algorithm of a patch (all compute the same P^{-1}):
+ * GA_PINV_AUTO (banded solves when they fit, the default), GA_PINV_DENSE (dense
+ * inverse products on the vector ALU) or GA_PINV_MFMA (dense inverse products on
+ * the matrix cores: v_mfma_f64_16x16x4 in FP64, v_mfma_f32_32x32x2 in FP32; axes
+ * of at most 256 free coefficients).  Device-side PCG control (ga_patch_set_cg)
+ * applies to GA_PINV_AUTO only. */
+enum { GA_PINV_AUTO = 0, GA_PINV_DENSE = 1, GA_PINV_MFMA = 2 };
 int ga_patch_set_pinv(ga_patch* patch, int mode);
 /*
  * PCG control of a patch's FP64 solves (Sec. 5.6 PCG; the control is an
@@ -159,6 +182,10 @@ int ga_patch_set_pinv(ga_patch* patch, int mode);
  */
 int ga_patch_tune(ga_patch* patch, int nrhs, int reps, double* best_ms, void* stream);
 int ga_patch_tuned_layers(const ga_patch* patch, int* ze_mass, int* ze_stiff);
+/* ga_patch_set_layers -- sets the element layers per workgroup of the FP64 mass and
+ * stiffness launches of a 3-D patch (1..n_el[2]; 0 = automatic), as the autotuner
+ * would: the launch shapes change, the results do not.  GA_EINVAL out of range. */
+int ga_patch_set_layers(ga_patch* patch, int ze_mass, int ze_stiff);
 enum { GA_CG_HOST = 0, GA_CG_DEVICE = 1 };
 int ga_patch_set_cg(ga_patch* patch, int mode);
 int ga_cg_stats(const ga_patch* patch, long long* spec_iters, long long* host_checks);
@@ -169,9 +196,9 @@ int ga_cg_stats(const ga_patch* patch, long long* spec_iters, long long* host_ch
  * paper's null guess) and the solutions on return.  Each right-hand side
  * stops when sqrt(r^T P^{-1} r) <= rtol * sqrt(b^T P^{-1} b); converged
  * right-hand sides are frozen while the others continue.
- *   prec   GA_FP64 or GA_FP32 (3-D only; see above).  With GA_FP32 the
- *          stopping test uses P^{-1} applied in FP32 and iters_out counts the
- *          inner FP32 iterations.
+ *   prec   GA_FP64, or GA_FP32 / GA_BF16 (3-D only; see above).  With GA_FP32
+ *          and GA_BF16 the stopping test uses P^{-1} applied in that precision
+ *          and iters_out counts the inner iterations.
  *   iters_out[nrhs], relres_out[nrhs]  host arrays or NULL.
  * Returns GA_ENOCONV if any right-hand side did not converge in maxit.
  */
@@ -195,7 +222,8 @@ double ga_stability_limit2(double rho_b, double rho_s);
 /*
  * ga_integrator_create -- the order-2k scheme of Sec. 4 (k = 1, 2, 3, 4) with
  * rho_b = rho_s = rho in [0, 1), step tau > 0, PCG tolerance rtol and maxit,
- * mass-solve arithmetic prec (GA_FP64 or GA_FP32).
+ * mass-solve arithmetic prec (GA_FP64, GA_FP32 or GA_BF16; the last two on 3-D
+ * patches).
  * State vectors are L^a, a = -2 .. 3k-3 (U, V, A, then time derivatives of A).
  */
 int ga_integrator_create(ga_patch* patch, int k, double rho, double tau, double rtol,
@@ -342,7 +370,7 @@ int ga_batch_create(int npatch, ga_patch* const* patches, int k, double rho, dou
                     double rtol, int maxit, ga_batch** out);
 int ga_batch_destroy(ga_batch* batch);
 /*
- * ga_batch_set_precision -- arithmetic of the batch's mass solves (Sec. 6.1):
+ * ga_batch_set_precision -- arithmetic of the batch's mass solves (an addition, not in the paper):
  * GA_FP64 (default) or GA_FP32 = FP32 flexible-PCG corrections (FP32 mass
  * factors, vectors and preconditioner, inner reduction 1e-4) inside an FP64
  * iterative refinement whose residual and stopping test are FP64.  The first
@@ -385,8 +413,8 @@ int ga_batch_step(ga_batch* batch, double* const* state_dev, int nsteps, int use
                   int* iters_out, void* stream);
 
 /*
- * Glued multi-patch domain (Sec. 5.5) with the additive Schwarz mass
- * preconditioner P_ad^{-1} = sum_r R^(r)T (P^(r))^{-1} R^(r) (Sec. 5.7), P^(r)
+ * Glued multi-patch domain (Sec. 5.3) with the additive Schwarz mass
+ * preconditioner P_ad^{-1} = sum_r R^(r)T (P^(r))^{-1} R^(r) (Sec. 5.5), P^(r)
  * the preconditioner of Sec. 5.4 on patch r.  The domain is a brick: the unit
  * cube's parameter box split into P[0] x P[1] x P[2] boxes, patch r = box
  * (r % P0, (r / P0) % P1, r / (P0 P1)), each with n_el elements per direction

@@ -22,7 +22,7 @@ with sparse-matrix library calls as the only building blocks:
 * ``convnet``   -- the learned initial guess (an addition, not in the paper):
                    network definition, crop loss and its gradient, Adam.
 * ``multipatch``-- C0-glued patches and the additive Schwarz preconditioner
-                   (Sec. 5.5, 5.7).
+                   (Sec. 5.3, 5.5).
 * ``dispersion``-- the 1-D dispersion study of Sec. 6.2 (omega = 1/j).
 
 Readings of passages that are silent, ambiguous or garbled are listed in the

@@ -1,5 +1,5 @@
 """Conforming (C^0-glued) multi-patch spline spaces and the additive Schwarz
-mass preconditioner (Sec. 5.5 multi-patch B-splines, Sec. 5.7 preconditioner
+mass preconditioner (Sec. 5.3 multi-patch B-splines, Sec. 5.5 preconditioner
 on a multi-patch domain), for a brick of patches.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
@@ -10,7 +10,7 @@ patch with n elements per direction and degree p (uniform open knot vectors),
 each with its own map F^(r).  Along axis a, patch-local coefficient i (0..m-1,
 m = n + p) of box b_a has global index g = b_a (m - 1) + i, so the last
 coefficient of one box and the first of the next are the same global one (the
-conformity assumption of Sec. 5.5: matching knots and control points on the
+conformity assumption of Sec. 5.3: matching knots and control points on the
 shared face).  The global grid has P_a (m - 1) + 1 coefficients per axis; the
 homogeneous Dirichlet data fix its outer layer, so the unknowns are the global
 indices 1 .. P_a (m - 1) - 1, numbered co-lex (x fastest).

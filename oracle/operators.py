@@ -13,7 +13,7 @@ Definitions followed:
 * Homogeneous Dirichlet data (second remark of Sec. 2): the unknowns are the
   coefficients of basis functions that vanish on the boundary, i.e. all
   indices 1 <= i_a <= m_a - 2 (0-based) in every direction.  A patch of a
-  glued multi-patch domain (Sec. 5.5) keeps the coefficients of its interface
+  glued multi-patch domain (Sec. 5.3) keeps the coefficients of its interface
   faces: there the range starts at 0 or ends at m_a - 1.
 * Assumption 3 (det DF >= delta > 0) is checked at every quadrature point.
 

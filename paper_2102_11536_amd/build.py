@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libga.so")
-SOURCES = ["spline1d.cpp", "ops3d.hip", "ops2d.hip", "vec.hip", "pinv.hip", "pinv_band.hip", "mixed.hip", "gnet.hip",
+SOURCES = ["ops3d.hip", "ops3d_lowp.hip", "spline1d.cpp", "ops2d.hip", "vec.hip", "pinv.hip", "pinv_band.hip", "pinv_mfma.hip", "mixed.hip", "gnet.hip",
            "api.hip", "api_gnet.hip", "batch.hip", "wave1d.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -126,6 +126,7 @@ int ensure_work(ga_patch* pt, int nvec) {
 }
 
 constexpr int MAX_NR = 3;  // right-hand sides per kernel pass
+int ensure_packed(ga_patch* pt, int prec, hipStream_t st);
 
 int op_apply(ga_patch* pt, int mode, int nr, double alpha, const double* x, double* y,
              hipStream_t st) {
@@ -151,6 +152,14 @@ int pinv_apply(ga_patch* pt, int nr, const double* r, double* z, double* t0, dou
   const size_t n = pt->n_free;
   const int m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
   ProfScope prof(2, st);
+  if (pt->pinv_mode == GA_PINV_MFMA) {
+    int rc = ensure_packed(pt, GA_FP64, st);
+    if (rc) return rc;
+    const void* apk[3] = {pt->apk[GA_FP64][0], pt->apk[GA_FP64][1], pt->apk[GA_FP64][2]};
+    return check_launch(launch_pinv_mfma_f64(pt->dim, pt->mf, nr, r, z, t0, t1, apk, pt->s,
+                                             (long long)n, st),
+                        "matrix-core preconditioner");
+  }
   if (pt->pinv_mode != GA_PINV_DENSE) {
     const double* cb[3] = {pt->cb[0], pt->cb[1], pt->cb[2]};
     const int rc = launch_pinv_band<double>(pt->dim, pt->p, pt->mf, nr, r, z, t0, t1, cb, pt->s,
@@ -279,7 +288,7 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
   int it = 0;
   // device-side control: enqueue the iterations the last solve of nr systems
   // needed without reading the flags in between
-  const bool dev = pt->cg_ctrl == GA_CG_DEVICE && pt->dim == 3 && pt->pinv_mode != GA_PINV_DENSE &&
+  const bool dev = pt->cg_ctrl == GA_CG_DEVICE && pt->dim == 3 && pt->pinv_mode == GA_PINV_AUTO &&
                    nr <= 16 && pt->hint_nr == nr && pinv_band_fits(3, pt->p, pt->mf, sizeof(double));
   if (dev) {
     int hmax = 0;
@@ -337,10 +346,11 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
 
 // ---- mixed precision: FP32 inner PCG inside an FP64 iterative refinement ----
 
-// FP32 copies of W, the 1-D inverses and the scaling (built on first use)
+// FP32 copies of W, the 1-D inverses, the band factors and the scaling (built on
+// first use)
 int ensure_mixed(ga_patch* pt, hipStream_t st) {
   if (pt->W32) return GA_OK;
-  if (pt->dim != 3) { set_error("mixed precision needs a 3-D patch"); return GA_EINVAL; }
+  if (pt->dim != 3) { set_error("FP32 and BF16 arithmetic need a 3-D patch"); return GA_EINVAL; }
   int rc;
   if ((rc = dalloc((void**)&pt->W32, pt->nW * sizeof(float))) ||
       (rc = dalloc((void**)&pt->s32, pt->n_free * sizeof(float))))
@@ -358,19 +368,70 @@ int ensure_mixed(ga_patch* pt, hipStream_t st) {
   return check_launch(0, "mixed-precision setup");
 }
 
-int pinv_apply_f32(ga_patch* pt, int nr, const float* r, float* z, float* t0, float* t1,
-                   hipStream_t st) {
+// the low-precision factor copy an operator apply needs (mode 0 W, 1 G), built on
+// first use: FP32 (W32, G32) or BF16 (W16, G16), rounded to nearest from FP64
+int ensure_factors(ga_patch* pt, int mode, int prec, hipStream_t st) {
+  int rc = ensure_mixed(pt, st);
+  if (rc) return rc;
+  const double* src = mode == 1 ? pt->G : pt->W;
+  const size_t cnt = mode == 1 ? pt->nG : pt->nW;
+  if (prec == GA_FP32) {
+    float** dst = mode == 1 ? &pt->G32 : &pt->W32;
+    if (*dst) return GA_OK;
+    if ((rc = dalloc((void**)dst, cnt * sizeof(float)))) return rc;
+    launch_to_f32(*dst, src, cnt, st);
+  } else if (prec == GA_BF16) {
+    unsigned short** dst = mode == 1 ? &pt->G16 : &pt->W16;
+    if (*dst) return GA_OK;
+    if ((rc = dalloc((void**)dst, cnt * sizeof(unsigned short)))) return rc;
+    launch_to_bf16(*dst, src, cnt, st);
+  } else {
+    return GA_OK;
+  }
+  return check_launch(0, "low-precision factor copy");
+}
+
+// the dense 1-D inverses packed for the matrix cores in arithmetic prec (built on
+// first use)
+int ensure_packed(ga_patch* pt, int prec, hipStream_t st) {
+  for (int a = 0; a < pt->dim; ++a) {
+    if (pt->apk[prec][a]) continue;
+    if (!pinv_mfma_supported(prec, pt->mf[a])) {
+      set_error("the matrix-core preconditioner supports axes of at most 256 free coefficients");
+      return GA_EINVAL;
+    }
+    int rc = dalloc(&pt->apk[prec][a], pinv_mfma_pack_bytes(prec, pt->mf[a]));
+    if (rc) return rc;
+    if (pinv_mfma_pack(prec, pt->Minv[a], pt->mf[a], pt->apk[prec][a], st))
+      return check_launch(-1, "packing the 1-D inverses");
+  }
+  return GA_OK;
+}
+
+// z = P^{-1} r with FP32 vectors: GA_FP32 with the patch's preconditioner mode
+// (banded FP32 solves, dense FP32 products on the vector ALU, or dense FP32 products
+// on the matrix cores), GA_BF16 on the matrix cores with BF16 operands
+int pinv_apply_lp(ga_patch* pt, int prec, int nr, const float* r, float* z, float* t0, float* t1,
+                  hipStream_t st) {
   const size_t n = pt->n_free;
   const int m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
   if (!(pinv_axis_supported(m0) && pinv_axis_supported(m1) && pinv_axis_supported(m2))) {
-    set_error("mixed precision supports axes of at most 256 free coefficients");
+    set_error("FP32 and BF16 arithmetic support axes of at most 256 free coefficients");
     return GA_EINVAL;
   }
+  int rc = ensure_mixed(pt, st);
+  if (rc) return rc;
   ProfScope prof(2, st);
+  if (prec == GA_BF16 || pt->pinv_mode == GA_PINV_MFMA) {
+    if ((rc = ensure_packed(pt, prec, st))) return rc;
+    const void* apk[3] = {pt->apk[prec][0], pt->apk[prec][1], pt->apk[prec][2]};
+    return check_launch(launch_pinv_mfma_f32(prec, 3, pt->mf, nr, r, z, t0, t1, apk, pt->s32,
+                                             (long long)n, st),
+                        "matrix-core preconditioner");
+  }
   if (pt->pinv_mode != GA_PINV_DENSE) {
     const float* cb[3] = {pt->cb32[0], pt->cb32[1], pt->cb32[2]};
-    const int rc = launch_pinv_band<float>(3, pt->p, pt->mf, nr, r, z, t0, t1, cb, pt->s32,
-                                           (long long)n, st);
+    rc = launch_pinv_band<float>(3, pt->p, pt->mf, nr, r, z, t0, t1, cb, pt->s32, (long long)n, st);
     if (rc == 0) return check_launch(0, "FP32 preconditioner");
     if (rc < 0) return check_launch(-1, "FP32 preconditioner");
   }
@@ -383,16 +444,25 @@ int pinv_apply_f32(ga_patch* pt, int nr, const float* r, float* z, float* t0, fl
   return check_launch(0, "FP32 preconditioner");
 }
 
-int mass_apply_f32(ga_patch* pt, int nr, const float* x, float* y, hipStream_t st) {
-  launch_fill_f32(y, (size_t)nr * pt->n_free, st);
-  for (int r0 = 0; r0 < nr; r0 += MAX_NR) {
-    const int c = nr - r0 < MAX_NR ? nr - r0 : MAX_NR;
-    ProfScope prof(0, st);
-    int rc = launch_mass3d_f32(c, pt, x + (size_t)r0 * pt->n_free, y + (size_t)r0 * pt->n_free,
-                               1.0f, st);
-    if (check_launch(rc, "FP32 mass apply")) return GA_EDEVICE;
+// y += alpha Op x with FP32 vectors, FP32 (prec GA_FP32) or BF16 (GA_BF16) factors
+int op_apply_lp(ga_patch* pt, int mode, int prec, int nr, float alpha, const float* x, float* y,
+                hipStream_t st) {
+  int rc = ensure_factors(pt, mode, prec, st);
+  if (rc) return rc;
+  const int cmax = op3d_max_nr(pt->p, mode);
+  for (int r0 = 0; r0 < nr; r0 += cmax) {
+    const int c = nr - r0 < cmax ? nr - r0 : cmax;
+    ProfScope prof(mode == 1 ? 1 : 0, st);
+    rc = launch_op3d_lowp(mode, c, pt, x + (size_t)r0 * pt->n_free, y + (size_t)r0 * pt->n_free,
+                          alpha, prec, st);
+    if (check_launch(rc, "low-precision operator apply")) return GA_EDEVICE;
   }
   return GA_OK;
+}
+
+int mass_apply_lp(ga_patch* pt, int prec, int nr, const float* x, float* y, hipStream_t st) {
+  launch_fill_f32(y, (size_t)nr * pt->n_free, st);
+  return op_apply_lp(pt, 0, prec, nr, 1.0f, x, y, st);
 }
 
 int read_scalars(ga_patch* pt, int nr, hipStream_t st) {
@@ -406,8 +476,9 @@ int read_scalars(ga_patch* pt, int nr, hipStream_t st) {
 // sqrt(r^T P^{-1} r) <= rtol sqrt(b^T P^{-1} b) (P^{-1} applied in FP32, dots in
 // FP64); each correction M d = r comes from an FP32 flexible PCG (FP32 factors,
 // vectors and preconditioner) that reduces its residual by inner_tol.
-int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, int maxit,
-                     bool zero_guess, int* iters_out, double* relres_out, hipStream_t st) {
+int solve_mixed_impl(ga_patch* pt, int prec, int nr, const double* b, double* x, double rtol,
+                     int maxit, bool zero_guess, int* iters_out, double* relres_out,
+                     hipStream_t st) {
   const size_t n = pt->n_free;
   const size_t tot = (size_t)nr * n;
   int rc = ensure_mixed(pt, st);
@@ -425,7 +496,7 @@ int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rt
   if (zero_guess) launch_fill(x, 0.0, tot, st);
   else if ((rc = op_apply(pt, 0, nr, -1.0, x, r64, st))) return rc;
   launch_to_f32(r32, b, tot, st);
-  if ((rc = pinv_apply_f32(pt, nr, r32, z32, t0, t1, st))) return rc;
+  if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
   launch_dot_df(nr, b, z32, n, partB, st);
   std::vector<double> bn2(nr), rz(nr);
   launch_sum_partials(nr, partB, pt->scal, st);
@@ -435,7 +506,7 @@ int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rt
   bool conv = false;
   for (int outer = 0; outer < 50; ++outer) {
     launch_to_f32(r32, r64, tot, st);
-    if ((rc = pinv_apply_f32(pt, nr, r32, z32, t0, t1, st))) return rc;
+    if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
     launch_dot_df(nr, r64, z32, n, partA, st);
     launch_sum_partials(nr, partA, pt->scal, st);
     if ((rc = read_scalars(pt, nr, st))) return rc;
@@ -454,7 +525,7 @@ int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rt
           pt->host_scal[r] = bn2[r];
         }
       }
-      if (reset && (rc = pinv_apply_f32(pt, nr, r32, z32, t0, t1, st))) return rc;
+      if (reset && (rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
     }
     bool all = true;
     for (int r = 0; r < nr; ++r) {
@@ -475,11 +546,11 @@ int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rt
       bool any = false;
       for (int r = 0; r < nr; ++r) any |= pt->host_scal[r * NSCAL + S_ACTIVE] != 0.0;
       if (!any) break;
-      if ((rc = mass_apply_f32(pt, nr, p32, q32, st))) return rc;
+      if ((rc = mass_apply_lp(pt, prec, nr, p32, q32, st))) return rc;
       launch_dot_ff(nr, p32, q32, n, partA, st);
       launch_cg_alpha(nr, partA, pt->scal, st);
       launch_cg_xr_f32(nr, d32, r32, p32, q32, pt->scal, n, st);
-      if ((rc = pinv_apply_f32(pt, nr, r32, z32, t0, t1, st))) return rc;
+      if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
       launch_dot2_f32(nr, r32, z32, q32, n, partA, partB, st);
       launch_cg_beta_flex(nr, partA, partB, pt->scal, st);
       launch_cg_p_f32(nr, p32, z32, pt->scal, n, st);
@@ -506,8 +577,8 @@ int solve_mixed_impl(ga_patch* pt, int nr, const double* b, double* x, double rt
 
 int solve_any(ga_patch* pt, int nr, const double* b, double* x, double rtol, int maxit, int prec,
               bool zero_guess, int* iters_out, double* relres_out, hipStream_t st) {
-  if (prec == GA_FP32)
-    return solve_mixed_impl(pt, nr, b, x, rtol, maxit, zero_guess, iters_out, relres_out, st);
+  if (prec == GA_FP32 || prec == GA_BF16)
+    return solve_mixed_impl(pt, prec, nr, b, x, rtol, maxit, zero_guess, iters_out, relres_out, st);
   return solve_impl(pt, nr, b, x, rtol, maxit, zero_guess, iters_out, relres_out, st);
 }
 
@@ -707,6 +778,12 @@ int ga_destroy_patch(ga_patch* pt) {
   if (pt->W) hipFree(pt->W);
   if (pt->G) hipFree(pt->G);
   if (pt->W32) hipFree(pt->W32);
+  if (pt->G32) hipFree(pt->G32);
+  if (pt->W16) hipFree(pt->W16);
+  if (pt->G16) hipFree(pt->G16);
+  for (int q = 0; q < 3; ++q)
+    for (int a = 0; a < 3; ++a)
+      if (pt->apk[q][a]) hipFree(pt->apk[q][a]);
   if (pt->s32) hipFree(pt->s32);
   for (int a = 0; a < 3; ++a)
     if (pt->Minv32[a]) hipFree(pt->Minv32[a]);
@@ -828,7 +905,10 @@ int ga_cg_stats(const ga_patch* pt, long long* spec_iters, long long* host_check
 
 int ga_patch_set_pinv(ga_patch* pt, int mode) {
   if (!pt) { set_error("null patch"); return GA_EINVAL; }
-  if (mode != GA_PINV_AUTO && mode != GA_PINV_DENSE) { set_error("bad preconditioner mode"); return GA_EINVAL; }
+  if (mode != GA_PINV_AUTO && mode != GA_PINV_DENSE && mode != GA_PINV_MFMA) {
+    set_error("bad preconditioner mode");
+    return GA_EINVAL;
+  }
   pt->pinv_mode = mode;
   return GA_OK;
 }
@@ -840,24 +920,67 @@ int ga_diag_M(ga_patch* pt, double* d, void* stream) {
   return GA_OK;
 }
 
-int ga_apply_MK(ga_patch* pt, char which, int nrhs, double alpha, const double* x, double* y,
-                void* stream) {
+int ga_apply_MK(ga_patch* pt, char which, int nrhs, int prec, double alpha, const double* x,
+                double* y, void* stream) {
   if (!pt || !x || !y) { set_error("null argument"); return GA_EINVAL; }
   if (nrhs < 1) { set_error("nrhs must be >= 1"); return GA_EINVAL; }
   if (which != 'M' && which != 'K') { set_error("which must be 'M' or 'K'"); return GA_EINVAL; }
+  if (prec != GA_FP64 && prec != GA_FP32 && prec != GA_BF16) { set_error("bad prec"); return GA_EINVAL; }
   hipStream_t st = S(stream);
-  launch_fill(y, 0.0, (size_t)nrhs * pt->n_free, st);
-  return op_apply(pt, which == 'M' ? 0 : 1, nrhs, alpha, x, y, st);
+  const int mode = which == 'M' ? 0 : 1;
+  const size_t tot = (size_t)nrhs * pt->n_free;
+  if (prec == GA_FP64) {
+    launch_fill(y, 0.0, tot, st);
+    return op_apply(pt, mode, nrhs, alpha, x, y, st);
+  }
+  if (pt->dim != 3) { set_error("FP32 and BF16 applies need a 3-D patch"); return GA_EINVAL; }
+  int rc = ensure_work(pt, nrhs);   // nrhs * n_free doubles = FP32 x and y
+  if (rc) return rc;
+  float* x32 = reinterpret_cast<float*>(pt->work);
+  float* y32 = x32 + tot;
+  launch_to_f32(x32, x, tot, st);
+  launch_fill_f32(y32, tot, st);
+  if ((rc = op_apply_lp(pt, mode, prec, nrhs, (float)alpha, x32, y32, st))) return rc;
+  launch_to_f64(y, y32, tot, st);
+  return check_launch(0, "low-precision apply");
 }
 
-int ga_apply_Pinv(ga_patch* pt, int nrhs, const double* r, double* z, void* stream) {
+int ga_apply_Pinv(ga_patch* pt, int nrhs, int prec, const double* r, double* z, void* stream) {
   if (!pt || !r || !z) { set_error("null argument"); return GA_EINVAL; }
   if (nrhs < 1) { set_error("nrhs must be >= 1"); return GA_EINVAL; }
-  int rc = ensure_work(pt, 6 * nrhs);
+  if (prec != GA_FP64 && prec != GA_FP32 && prec != GA_BF16) { set_error("bad prec"); return GA_EINVAL; }
+  hipStream_t st = S(stream);
+  const size_t tot = (size_t)nrhs * pt->n_free;
+  if (prec == GA_FP64) {
+    int rc = ensure_work(pt, 6 * nrhs);
+    if (rc) return rc;
+    double* t0 = pt->work + (size_t)4 * tot;
+    double* t1 = pt->work + (size_t)5 * tot;
+    return pinv_apply(pt, nrhs, r, z, t0, t1, st);
+  }
+  if (pt->dim != 3) { set_error("FP32 and BF16 applies need a 3-D patch"); return GA_EINVAL; }
+  int rc = ensure_work(pt, 2 * nrhs);   // four FP32 vectors of nrhs * n_free
   if (rc) return rc;
-  double* t0 = pt->work + (size_t)4 * nrhs * pt->n_free;
-  double* t1 = pt->work + (size_t)5 * nrhs * pt->n_free;
-  return pinv_apply(pt, nrhs, r, z, t0, t1, S(stream));
+  float* r32 = reinterpret_cast<float*>(pt->work);
+  float* z32 = r32 + tot;
+  float* t0 = z32 + tot;
+  float* t1 = t0 + tot;
+  launch_to_f32(r32, r, tot, st);
+  if ((rc = pinv_apply_lp(pt, prec, nrhs, r32, z32, t0, t1, st))) return rc;
+  launch_to_f64(z, z32, tot, st);
+  return check_launch(0, "low-precision preconditioner");
+}
+
+int ga_patch_set_layers(ga_patch* pt, int ze_mass, int ze_stiff) {
+  if (!pt) { set_error("null patch"); return GA_EINVAL; }
+  if (pt->dim != 3) { set_error("launch shapes are for 3-D patches"); return GA_EINVAL; }
+  if (ze_mass < 0 || ze_mass > pt->n[2] || ze_stiff < 0 || ze_stiff > pt->n[2]) {
+    set_error("layers per workgroup must be in 0..n_el[2]");
+    return GA_EINVAL;
+  }
+  pt->ze_op[0] = ze_mass;
+  pt->ze_op[1] = ze_stiff;
+  return GA_OK;
 }
 
 int ga_mass_solve(ga_patch* pt, int nrhs, const double* b, double* x, double rtol, int maxit,
@@ -865,7 +988,8 @@ int ga_mass_solve(ga_patch* pt, int nrhs, const double* b, double* x, double rto
   if (!pt || !b || !x) { set_error("null argument"); return GA_EINVAL; }
   if (nrhs < 1 || nrhs > 16) { set_error("nrhs must be in 1..16"); return GA_EINVAL; }
   if (!(rtol > 0.0) || maxit < 0) { set_error("rtol must be > 0 and maxit >= 0"); return GA_EINVAL; }
-  if (prec != GA_FP64 && prec != GA_FP32) { set_error("prec must be GA_FP64 or GA_FP32"); return GA_EINVAL; }
+  if (prec != GA_FP64 && prec != GA_FP32 && prec != GA_BF16) { set_error("bad prec"); return GA_EINVAL; }
+  if (prec != GA_FP64 && pt->dim != 3) { set_error("FP32 and BF16 solves need a 3-D patch"); return GA_EINVAL; }
   return solve_any(pt, nrhs, b, x, rtol, maxit, prec, false, iters_out, relres_out, S(stream));
 }
 
@@ -928,8 +1052,8 @@ int ga_integrator_create(ga_patch* pt, int k, double rho, double tau, double rto
   if (!(rho >= 0.0 && rho < 1.0)) { set_error("rho must be in [0, 1)"); return GA_EINVAL; }
   if (!(tau > 0.0) || !(rtol > 0.0) || maxit < 1) { set_error("bad tau/rtol/maxit"); return GA_EINVAL; }
   if (guess_mode < GA_GUESS_ZERO || guess_mode > GA_GUESS_LEARNED) { set_error("bad guess mode"); return GA_EINVAL; }
-  if (prec != GA_FP64 && prec != GA_FP32) { set_error("prec must be GA_FP64 or GA_FP32"); return GA_EINVAL; }
-  if (prec == GA_FP32 && pt->dim != 3) { set_error("mixed precision needs a 3-D patch"); return GA_EINVAL; }
+  if (prec != GA_FP64 && prec != GA_FP32 && prec != GA_BF16) { set_error("bad prec"); return GA_EINVAL; }
+  if (prec != GA_FP64 && pt->dim != 3) { set_error("mixed precision needs a 3-D patch"); return GA_EINVAL; }
   ga_integrator* it = new ga_integrator();
   it->prec = prec;
   it->patch = pt;

@@ -786,8 +786,8 @@ int ga_batch_step(ga_batch* b, double* const* state, int nsteps, int use_graph, 
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Glued (C^0) multi-patch domain (Sec. 5.5) with the additive Schwarz mass
-// preconditioner (Sec. 5.7): a brick of P_x x P_y x P_z patches, each n elements
+// Glued (C^0) multi-patch domain (Sec. 5.3) with the additive Schwarz mass
+// preconditioner (Sec. 5.5): a brick of P_x x P_y x P_z patches, each n elements
 // and degree p.  The patch work runs through a batch over the patches' local
 // free coefficients (interface faces free, outer faces Dirichlet); the PCG and
 // the time stepping run on the global unknowns:

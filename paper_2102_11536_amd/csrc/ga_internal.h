@@ -126,6 +126,9 @@ struct ga_patch {
   double* G = nullptr;        // w |det J| J^-1 J^-T  (3-D: stiffness-kernel column layout)
   size_t nW = 0, nG = 0;      // entries
   float* W32 = nullptr;       // FP32 copy of W (mixed-precision inner solves)
+  float* G32 = nullptr;       // FP32 copy of G (FP32 stiffness applies)
+  unsigned short* W16 = nullptr;  // BF16 copies of W and G (bit patterns, round to nearest even)
+  unsigned short* G16 = nullptr;
   float* Minv32[3] = {nullptr, nullptr, nullptr};  // FP32 copies of the 1-D inverses
   float* s32 = nullptr;       // FP32 copy of the scaling
   double* cb[3] = {nullptr, nullptr, nullptr};    // banded Cholesky factors (Axis1D::chol)
@@ -133,6 +136,7 @@ struct ga_patch {
   double* diagM = nullptr;    // [n_free]
   double* s = nullptr;        // [n_free] (Dhat/D)^(1/2)
   double* Minv[3] = {nullptr, nullptr, nullptr};   // [mf][mf]
+  void* apk[3][3] = {};       // [prec][axis]: the inverses packed for the matrix cores
   // work buffers for solves (grown on demand)
   double* work = nullptr;
   size_t work_bytes = 0;

@@ -49,6 +49,10 @@ int launch_op3d_group(int p, int mode, int nr, const OpGroupEntry* ents, int nen
                       S* y, long long stride, S alpha, int total, int nwg, hipStream_t st);
 int launch_mass3d_f32(int nr, const ga_patch* pt, const float* x, float* y, float alpha,
                       hipStream_t st);
+// FP32-vector operator apply (mode 0 mass, 1 stiffness) with FP32 (prec GA_FP32:
+// W32, G32) or BF16 (GA_BF16: W16, G16) factors; -1 if those factors are not built
+int launch_op3d_lowp(int mode, int nr, const ga_patch* pt, const float* x, float* y, float alpha,
+                     int prec, hipStream_t st, const double* gate = nullptr);
 int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
                  hipStream_t st);
 int launch_op2d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
@@ -88,6 +92,19 @@ struct PinvEntry {
   int blk0;
 };
 int pinv_ra_class(int L);
+// dense per-axis preconditioner on the matrix cores (pinv_mfma.hip): the packed
+// inverse of one axis for arithmetic `prec` (GA_FP64, GA_FP32 or GA_BF16), its size,
+// and the three-pass application with the packed inverses apk[axis] (-1: an axis
+// is too long)
+bool pinv_mfma_supported(int prec, int L);
+size_t pinv_mfma_pack_bytes(int prec, int L);
+int pinv_mfma_pack(int prec, const double* A, int L, void* out, hipStream_t st);
+int launch_pinv_mfma_f32(int prec, int dim, const int* mf, int nr, const float* r, float* z,
+                         float* t0, float* t1, const void* const* apk, const float* s, long long n,
+                         hipStream_t st);
+int launch_pinv_mfma_f64(int dim, const int* mf, int nr, const double* r, double* z, double* t0,
+                         double* t1, const void* const* apk, const double* s, long long n,
+                         hipStream_t st);
 // banded-Cholesky preconditioner (0 launched, 1 does not fit the LDS staging, -1 error)
 template <typename S>
 int launch_pinv_band(int dim, int p, const int* mf, int nr, const S* r, S* z, S* t0, S* t1,
@@ -126,6 +143,9 @@ void launch_axpby(double* out, double a, const double* x, double b, const double
 // FP32 kernels of the mixed solve; with seg, system r covers entries
 // seg[2r] .. seg[2r] + seg[2r+1] - 1 (n is then the longest system)
 void launch_to_f32(float* o, const double* i, size_t n, hipStream_t st);
+void launch_to_f64(double* o, const float* i, size_t n, hipStream_t st);
+// BF16 bit patterns, rounded to nearest even
+void launch_to_bf16(unsigned short* o, const double* i, size_t n, hipStream_t st);
 void launch_add_f32(double* x, const float* d, size_t n, hipStream_t st);
 void launch_fill_f32(float* p, size_t n, hipStream_t st);
 void launch_copy_f32(float* d, const float* s, size_t n, hipStream_t st);

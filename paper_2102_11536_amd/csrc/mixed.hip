@@ -40,6 +40,22 @@ __global__ void to_f32_k(float* __restrict__ o, const double* __restrict__ i, si
     o[k] = (float)i[k];
 }
 
+__global__ void to_f64_k(double* __restrict__ o, const float* __restrict__ i, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * VB + threadIdx.x; k < n; k += (size_t)gridDim.x * VB)
+    o[k] = (double)i[k];
+}
+
+// FP64 -> FP32 (nearest) -> BF16 (nearest even); NaN stays NaN
+__global__ void to_bf16_k(unsigned short* __restrict__ o, const double* __restrict__ i, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * VB + threadIdx.x; k < n; k += (size_t)gridDim.x * VB) {
+    const unsigned u = __float_as_uint((float)i[k]);
+    unsigned short h;
+    if ((u & 0x7fffffffu) > 0x7f800000u) h = (unsigned short)((u >> 16) | 0x40u);
+    else h = (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    o[k] = h;
+  }
+}
+
 __global__ void add_f32_k(double* __restrict__ x, const float* __restrict__ d, size_t n) {
   for (size_t k = (size_t)blockIdx.x * VB + threadIdx.x; k < n; k += (size_t)gridDim.x * VB)
     x[k] += (double)d[k];
@@ -164,6 +180,12 @@ __global__ void cg_p_f32_k(float* __restrict__ p, const float* __restrict__ z,
 
 void launch_to_f32(float* o, const double* i, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(to_f32_k, dim3(nb(n)), dim3(VB), 0, st, o, i, n);
+}
+void launch_to_f64(double* o, const float* i, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(to_f64_k, dim3(nb(n)), dim3(VB), 0, st, o, i, n);
+}
+void launch_to_bf16(unsigned short* o, const double* i, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(to_bf16_k, dim3(nb(n)), dim3(VB), 0, st, o, i, n);
 }
 void launch_add_f32(double* x, const float* d, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(add_f32_k, dim3(nb(n)), dim3(VB), 0, st, x, d, n);

@@ -14,8 +14,8 @@ LIB_PATH = os.path.join(HERE, "libga.so")
 GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EGEOMETRY, GA_ENOCONV, GA_EUNSTABLE = 0, -1, -2, -3, -4, -5, -6
 GA_GUESS_ZERO, GA_GUESS_PREV, GA_GUESS_EXTRAP, GA_GUESS_LEARNED = 0, 1, 2, 3
 GA_GNET_NPARAM = 32033
-GA_FP64, GA_FP32 = 0, 1
-GA_PINV_AUTO, GA_PINV_DENSE = 0, 1
+GA_FP64, GA_FP32, GA_BF16 = 0, 1, 2
+GA_PINV_AUTO, GA_PINV_DENSE, GA_PINV_MFMA = 0, 1, 2
 GA_CG_HOST, GA_CG_DEVICE = 0, 1
 
 EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
@@ -26,7 +26,7 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
-           "ga_batch_tune", "ga_batch_set_precision", "ga_batch_set_tau", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers",
+           "ga_batch_tune", "ga_batch_set_precision", "ga_batch_set_tau", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers", "ga_patch_set_layers",
            "ga_stability_limit2", "ga_integrator_set_rho", "ga_wave1d_create", "ga_wave1d_destroy",
            "ga_wave1d_info", "ga_wave1d_load_sine", "ga_wave1d_apply", "ga_wave1d_init_state",
            "ga_wave1d_step", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
@@ -58,8 +58,8 @@ def load_library(path=LIB_PATH):
     lib.ga_patch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(i)]
     lib.ga_diag_M.argtypes = [vp, dp, vp]
-    lib.ga_apply_MK.argtypes = [vp, ctypes.c_char, i, d, dp, dp, vp]
-    lib.ga_apply_Pinv.argtypes = [vp, i, dp, dp, vp]
+    lib.ga_apply_MK.argtypes = [vp, ctypes.c_char, i, i, d, dp, dp, vp]
+    lib.ga_apply_Pinv.argtypes = [vp, i, i, dp, dp, vp]
     lib.ga_mass_solve.argtypes = [vp, i, dp, dp, d, i, i, ctypes.POINTER(i), ctypes.POINTER(d), vp]
     lib.ga_lambda_max.argtypes = [vp, i, ctypes.POINTER(d), vp]
     lib.ga_stability_limit.argtypes = [d]
@@ -72,6 +72,7 @@ def load_library(path=LIB_PATH):
                                    ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d), i]
     lib.ga_profile.argtypes = [i]
     lib.ga_profile_query.argtypes = [i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)]
+    lib.ga_last_error.argtypes = []
     lib.ga_last_error.restype = ctypes.c_char_p
     ip, fp = ctypes.POINTER(i), ctypes.POINTER(ctypes.c_float)
     lib.ga_stage_solution.argtypes = [vp, i, i, dp, vp]
@@ -79,6 +80,7 @@ def load_library(path=LIB_PATH):
     lib.ga_patch_set_cg.argtypes = [vp, i]
     lib.ga_patch_tune.argtypes = [vp, i, i, ctypes.POINTER(d), vp]
     lib.ga_patch_tuned_layers.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.ga_patch_set_layers.argtypes = [vp, i, i]
     lib.ga_cg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     lib.ga_integrator_set_damping.argtypes = [vp, d, d]
     lib.ga_stage_times.argtypes = [vp, d, ctypes.POINTER(d)]
@@ -206,6 +208,11 @@ def ga_patch_tuned_layers(patch):
     return a.value, b.value
 
 
+def ga_patch_set_layers(patch, ze_mass, ze_stiff):
+    """Element layers per workgroup of the FP64 mass and stiffness launches (0: automatic)."""
+    _check(_lib.ga_patch_set_layers(patch.h, int(ze_mass), int(ze_stiff)))
+
+
 def ga_patch_set_cg(patch, mode):
     """GA_CG_HOST or GA_CG_DEVICE control of the patch's FP64 PCG solves."""
     _check(_lib.ga_patch_set_cg(patch.h, int(mode)))
@@ -222,14 +229,15 @@ def ga_diag_M(patch, d):
     _check(_lib.ga_diag_M(patch.h, _ptr(d, patch.n_free), _stream()))
 
 
-def ga_apply_MK(patch, which, x, y, nrhs=1, alpha=1.0):
+def ga_apply_MK(patch, which, x, y, nrhs=1, alpha=1.0, prec=GA_FP64):
     n = nrhs * patch.n_free
-    _check(_lib.ga_apply_MK(patch.h, which.encode(), nrhs, float(alpha), _ptr(x, n), _ptr(y, n), _stream()))
+    _check(_lib.ga_apply_MK(patch.h, which.encode(), nrhs, int(prec), float(alpha), _ptr(x, n), _ptr(y, n),
+                            _stream()))
 
 
-def ga_apply_Pinv(patch, r, z, nrhs=1):
+def ga_apply_Pinv(patch, r, z, nrhs=1, prec=GA_FP64):
     n = nrhs * patch.n_free
-    _check(_lib.ga_apply_Pinv(patch.h, nrhs, _ptr(r, n), _ptr(z, n), _stream()))
+    _check(_lib.ga_apply_Pinv(patch.h, nrhs, int(prec), _ptr(r, n), _ptr(z, n), _stream()))
 
 
 def ga_mass_solve(patch, b, x, nrhs=1, rtol=1e-12, maxit=500, raise_on_noconv=True, prec=GA_FP64):

@@ -66,3 +66,48 @@ def test_profile_mask_host_checks():
     assert lib.ga_profile(16) == -1
     assert lib.ga_profile(-1) == -1
     assert lib.ga_profile(0) == 0
+
+
+def _declarations():
+    src = open(os.path.join(ROOT, "include", "ga.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(?:int|double|const char\*)\s+(ga_[A-Za-z0-9_]+)\s*\(([^)]*)\)\s*;", src):
+        params = [p.strip() for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        out[m.group(1)] = params
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    # every ctypes prototype has as many arguments as the header declares
+    from paper_2102_11536_amd import ga
+    lib = ga.load_library()
+    decl = _declarations()
+    assert sorted(decl) == declared()
+    for name, params in decl.items():
+        assert len(getattr(lib, name).argtypes) == len(params), (name, params)
+
+
+def test_apply_signatures_take_a_precision():
+    # the operator and preconditioner applies take the arithmetic (GA_FP64 / GA_FP32 /
+    # GA_BF16) right after nrhs, as the boundary specifies
+    decl = _declarations()
+    mk = decl["ga_apply_MK"]
+    assert mk[2].endswith("nrhs") and mk[3] == "int prec", mk
+    pv = decl["ga_apply_Pinv"]
+    assert pv[1].endswith("nrhs") and pv[2] == "int prec", pv
+    src = open(os.path.join(ROOT, "include", "ga.h")).read()
+    assert re.search(r"GA_FP64 = 0, GA_FP32 = 1, GA_BF16 = 2", src)
+    assert re.search(r"GA_PINV_MFMA = 2", src)
+
+
+def test_argument_checks_before_device_work():
+    # host-side validation: null handles and bad precisions are refused with
+    # GA_EINVAL before any device call
+    from paper_2102_11536_amd import ga
+    lib = ga.load_library()
+    null = ctypes.c_void_p()
+    assert lib.ga_apply_MK(null, b"M", 1, 0, 1.0, null, null, null) == ga.GA_EINVAL
+    assert lib.ga_apply_Pinv(null, 1, 2, null, null, null) == ga.GA_EINVAL
+    assert lib.ga_patch_set_layers(null, 0, 0) == ga.GA_EINVAL
+    assert lib.ga_patch_set_pinv(null, ga.GA_PINV_MFMA) == ga.GA_EINVAL

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from paper_2102_11536_amd import ga, workloads
-from tests.helpers import OracleProblem, rel
+from tests.helpers import OracleProblem, check_step_rows, rel, stratified_rows
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -123,7 +123,9 @@ def test_graph_replays_match_eager():
     bg, hg, ig = _run_batch(pts, U0s, k, tau, 6, use_graph=True)
     be, he, ie = _run_batch(pts, U0s, k, tau, 6, use_graph=False)
     assert ga.ga_batch_graph_replays(bg) >= 6 and ga.ga_batch_graph_replays(be) == 0
-    assert np.array_equal(ig, ie)
+    # the order of the FP64 atomic additions may differ between the two runs, so a
+    # residual right at the tolerance may take one iteration more in one of them
+    assert np.max(np.abs(ig - ie)) <= 1
     for step in range(1, 7):
         for s in range(3 * k):
             # same launches; only the run-to-run order of the FP64 atomic additions differs
@@ -157,7 +159,7 @@ def test_batch_per_patch_time_steps():
         ga.ga_batch_set_tau(b, [1.0] * (len(pts) - 1) + [-1.0])
 
 
-# ---- FP32 inner PCG inside FP64 refinement, batched (Sec. 6.1) ----
+# ---- FP32 inner PCG inside FP64 refinement, batched (an addition to the paper) ----
 
 def test_batch_mixed_matches_oracle():
     _say("mixed batch vs oracle")
@@ -209,7 +211,7 @@ def test_batch_mixed_graph_matches_eager():
     bg, hg, ig = _run_batch(pts, U0s, k, tau, 5, use_graph=True, prec=ga.GA_FP32)
     be, he, ie = _run_batch(pts, U0s, k, tau, 5, use_graph=False, prec=ga.GA_FP32)
     assert ga.ga_batch_graph_replays(bg) >= 5 and ga.ga_batch_graph_replays(be) == 0
-    assert np.array_equal(ig, ie)
+    assert np.max(np.abs(ig - ie)) <= 1   # atomic order (see the FP64 test)
     for step in range(1, 6):
         for s in range(3 * k):
             # same launches; only the run-to-run order of the FP64 atomic additions differs
@@ -246,3 +248,77 @@ def test_batch_errors():
     ok = ga.ga_setup_patch(3, 4, 2, workloads.deformed_cube_ctrl(4, 2))
     with pytest.raises(ga.GAError):
         ga.ga_batch_create([ok], 5, 0.5, 1e-3)
+
+
+def test_batch_long_axes_match_oracle():
+    # patches whose free axes fall in the larger register classes of the batched
+    # preconditioner passes (65..144 and 145..256 coefficients, along x, y and z),
+    # with a small cube: FP64 and mixed batches against the oracle's trajectories
+    specs = [((70, 3, 3), 2, 21, 121), ((3, 99, 3), 3, 22, 122), ((3, 3, 150), 2, 23, 123),
+             ((160, 3, 2), 4, 24, 124), (4, 3, 25, 125)]
+    _say("batch long axes", specs)
+    k = 2
+    pts, U0s = _setup(specs)
+    tau = _tau(pts)
+    for prec in (ga.GA_FP64, ga.GA_FP32):
+        b, hist, its = _run_batch(pts, U0s, k, tau, 4, tune=True, prec=prec)
+        for r, (n, p, gseed, _) in enumerate(specs):
+            pr = OracleProblem(3, n, p, geometry="random", seed=gseed)
+            ora = pr.run(U0s[r], 0 * U0s[r], k, 0.5, tau, 4)
+            M = pr.M
+            for step in (1, 4):
+                for s in range(3 * k):
+                    g = _split(b, hist[step][s])[r]
+                    o = ora[step][s - 2]
+                    d = g - o
+                    e = np.sqrt(d @ (M @ d)) / max(np.sqrt(o @ (M @ o)), 1e-300)
+                    assert e < 1e-10, (prec, r, step, s, e)
+        _say("  prec", prec, "iterations per system", its.mean(axis=0).tolist())
+
+
+@pytest.mark.parametrize("prec", [ga.GA_FP64, ga.GA_FP32])
+def test_batch_full_size_multipatch(prec):
+    # the batched workload at its real sizes (12 patches, 16..96 elements per axis,
+    # p in 2..4; free axes 20..93, so both register classes of the batched
+    # preconditioner run), in the configuration the bench times: autotuned tile
+    # queues, captured iterations, rtol 1e-10.  Two steps; every patch is compared
+    # with its single-patch integrator and, on stratified rows, with the oracle's
+    # stage equations.
+    specs = workloads.multipatch_specs(R=12, n_min=16, n_max=96, seed=7)
+    _say("batch full size", prec, specs)
+    k, rho, rtol = 2, 0.5, 1e-10
+    pts, U0s = _setup(specs)
+    tau = _tau(pts)
+    b = ga.ga_batch_create(pts, k, rho, tau, rtol=rtol)
+    if prec != ga.GA_FP64:
+        ga.ga_batch_set_precision(b, prec)
+    ga.ga_batch_tune(b, reps=2)
+    U = _t(np.concatenate(U0s))
+    state = [torch.zeros(b.n_total, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    ga.ga_batch_init_state(b, U, torch.zeros_like(U), state)
+    ga.ga_batch_step(b, state, 1, use_graph=True)
+    L = [_np(s_) for s_ in state]
+    its = ga.ga_batch_step(b, state, 1, use_graph=True)
+    Ln = [_np(s_) for s_ in state]
+    _say("  iterations per system", np.asarray(its).ravel().tolist())
+    from oracle import operators
+    for r, pt in enumerate(pts):
+        n, p, gseed, _ = specs[r]
+        # the single-patch integrator from the same state, same tau and tolerance
+        integ = ga.ga_integrator_create(pt, k, rho, tau, rtol=rtol, prec=prec)
+        st = [_t(_split(b, L[s_])[r]) for s_ in range(3 * k)]
+        ga.ga_step(integ, st, 1)
+        for s_ in range(3 * k):
+            e = rel(_split(b, Ln[s_])[r], _np(st[s_]))
+            assert e < 1e-8, (r, s_, e)   # two PCG solves, each within rtol 1e-10 of the exact one
+        if prec != ga.GA_FP64:
+            continue
+        # the oracle's stage equations on stratified rows
+        ctrl = workloads.smooth_random_ctrl(n, p, gseed)
+        sp_ = operators.Space(n, p, 3)
+        te = 4 if p <= 3 else 3
+        rows = stratified_rows(pt.mf, p, list(range(te, n, te)), list(range(4, n, 4)), 16, r)
+        La = {a: _split(b, L[a + 2])[r] for a in range(-2, 3 * k - 2)}
+        Lb = {a: _split(b, Ln[a + 2])[r] for a in range(-2, 3 * k - 2)}
+        w = check_step_rows(sp_, ctrl, rows, La, Lb, tau, k, rho, 1e-8)
+        _say("  patch", r, (n, p), "stage residual on rows", w)

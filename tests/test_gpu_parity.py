@@ -8,7 +8,7 @@ import torch
 
 from oracle import galpha, operators
 from paper_2102_11536_amd import ga, workloads
-from tests.helpers import OracleProblem, rel
+from tests.helpers import OracleProblem, oracle_rows, rel, stratified_rows
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -65,7 +65,7 @@ def test_operators_match_assembled(dim, n, p):
     assert rel(_np(y[: pt.n_free]), -2.5 * (pr.K @ X[0])) < 1e-13
 
 
-@pytest.mark.parametrize("mode", [ga.GA_PINV_AUTO, ga.GA_PINV_DENSE])
+@pytest.mark.parametrize("mode", [ga.GA_PINV_AUTO, ga.GA_PINV_DENSE, ga.GA_PINV_MFMA])
 @pytest.mark.parametrize("dim,n,p", [(2, 9, 2), (3, 5, 3), (3, (6, 5, 3), 2), (3, 3, 4), (2, (7, 12), 1),
                                      (3, (12, 9, 7), 3)])
 def test_preconditioner_matches_oracle(dim, n, p, mode):
@@ -184,39 +184,63 @@ def test_prev_guess_same_answer():
     assert i1.sum() <= i0.sum()
 
 
-@pytest.mark.parametrize("n,p,k,rtol,seed", [(64, 3, 2, 1e-12, 0), (128, 3, 2, 1e-10, 2000), (128, 4, 3, 1e-10, 2000)])
-def test_cube_full_size_sampled_rows(n, p, k, rtol, seed):
+def _layer_candidates(nz):
+    # the element layers per workgroup the autotuner tries: whole columns, then halving to 4
+    out, ze = [], nz
+    while True:
+        out.append(ze)
+        if ze <= 4:
+            return out
+        ze = (ze + 1) // 2
+
+
+@pytest.mark.parametrize("n,p,k,rtol,seed,nrows", [(64, 3, 2, 1e-12, 0, 120), (128, 3, 2, 1e-10, 2000, 520),
+                                                   (128, 4, 3, 1e-10, 2000, 120)])
+def test_cube_full_size_sampled_rows(n, p, k, rtol, seed, nrows):
     # full-size deformed cubes: 64^3 p = 3, the 128^3 p = 3 k = 2 workload in the
-    # configuration the bench times (rtol 1e-10, GRF seed 2000, device-controlled
-    # PCG), and 128^3 p = 4 k = 3.  Operator rows and one step are checked on
-    # sampled rows the oracle computes one by one.
+    # configuration the bench times (autotuned launch shapes, rtol 1e-10, GRF seed
+    # 2000, device-controlled PCG), and 128^3 p = 4 k = 3.  The operators are checked
+    # on rows stratified over the tile edges and z-range boundaries, for every launch
+    # shape the autotuner can pick; the initial data and one step on a subset, by the
+    # oracle's row-by-row operators (computed in worker processes after the GPU work).
     _say("cube sampled", n, p, k)
     ctrl = workloads.deformed_cube_ctrl(n, p)
-    sp_ = operators.Space(n, p, 3)
     pt = ga.ga_setup_patch(3, n, p, ctrl)
-    rng = np.random.default_rng(5)
-    rows = np.concatenate([[0, 1, pt.n_free - 1], rng.integers(0, pt.n_free, 20)])
+    mf = pt.mf
+    te = 4 if p <= 3 else 3          # xy tile edge (elements) of the mass and stiffness kernels
+    cand = _layer_candidates(n)
+    zedges = sorted({z for ze in cand for z in range(ze, n, ze)})
+    rows = stratified_rows(mf, p, list(range(te, n, te)), zedges, nrows, 5)
+    sub = rows[np.random.default_rng(6).choice(len(rows), min(len(rows), 120), replace=False)]
+    sub.sort()
     X = workloads.grf(n, p, seed=seed)
     x = _t(X)
     y = torch.empty_like(x)
-    for which in ("M", "K"):
-        ga.ga_apply_MK(pt, which, x, y)
-        got = _np(y)[rows]
-        ref = operators.sampled_rows(sp_, ctrl, rows, X, which)
-        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+    tuned_ms = ga.ga_patch_tune(pt, nrhs=k, reps=3)
+    tuned = ga.ga_patch_tuned_layers(pt)
+    _say("  tuned layers (mass, stiffness)", tuned, tuned_ms, "candidates", cand)
+    got = {}
+    for ze in cand + [None]:
+        if ze is not None:
+            ga.ga_patch_set_layers(pt, ze, ze)
+        else:
+            ga.ga_patch_set_layers(pt, *tuned)   # back to the tuned shapes for the rest
+        for which in ("M", "K"):
+            ga.ga_apply_MK(pt, which, x, y)
+            got[(ze, which)] = _np(y)[rows]
+    assert ga.ga_patch_tuned_layers(pt) == tuned
+    vecs = {"x": X}
     # k right-hand sides in one apply (the launch chunking the step uses)
     Xk = np.concatenate([workloads.grf(n, p, seed=seed + i) for i in range(k)])
     xk, yk = _t(Xk), torch.empty(k * pt.n_free, dtype=torch.float64, device=DEV)
     ga.ga_apply_MK(pt, "K", xk, yk, nrhs=k)
     gk = _np(yk).reshape(k, -1)
     for i in range(k):
-        ref = operators.sampled_rows(sp_, ctrl, rows, Xk[i * pt.n_free:(i + 1) * pt.n_free], "K")
-        np.testing.assert_allclose(gk[i][rows], ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+        vecs[f"xk{i}"] = Xk[i * pt.n_free:(i + 1) * pt.n_free]
     d = torch.empty_like(x)
     ga.ga_diag_M(pt, d)
-    np.testing.assert_allclose(_np(d)[rows], operators.sampled_rows(sp_, ctrl, rows, X, "D"), rtol=1e-13)
-    # steps: the stage equations M X_j + K Y_j = 0 hold on the sampled rows to the
-    # PCG tolerance, and the update relations of the other vectors exactly
+    gd = _np(d)[sub]
+    # steps at the tuned launch shapes
     rho = 0.5
     N = 3 * k - 3
     lam = ga.ga_lambda_max(pt, 25)
@@ -224,13 +248,7 @@ def test_cube_full_size_sampled_rows(n, p, k, rtol, seed):
     integ = ga.ga_integrator_create(pt, k, rho, tau, rtol=rtol, maxit=100)
     state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
     ga.ga_init_state(integ, x, torch.zeros_like(x), state)
-    bar = max(1e-9, 100 * rtol)
-    L = {a: _np(state[a + 2]) for a in range(-2, N + 1)}
-    # initial data: M L^a = -K L^{a-2}
-    for a in range(0, N + 1):
-        lhs = operators.sampled_rows(sp_, ctrl, rows, L[a], "M")
-        rhs = -operators.sampled_rows(sp_, ctrl, rows, L[a - 2], "K")
-        assert np.max(np.abs(lhs - rhs)) < bar * np.max(np.abs(rhs)) + 1e-300, a
+    L0 = {a: _np(state[a + 2]) for a in range(-2, N + 1)}
     ga.ga_step(integ, state, 2)  # with V0 = 0 some stages are trivial at the first step
     L = {a: _np(state[a + 2]) for a in range(-2, N + 1)}
     its = ga.ga_step(integ, state, 1)
@@ -239,10 +257,33 @@ def test_cube_full_size_sampled_rows(n, p, k, rtol, seed):
     Y = galpha.stage_arguments(L, T, k)
     prm = galpha.block_params(k, rho)
     for j in range(k):
-        a = 3 * j
-        Xj = T[a] + prm[j][0] * (Ln[a] - T[a])  # X_j = T + alpha P, P = L_new - T
-        lhs = operators.sampled_rows(sp_, ctrl, rows, Xj, "M")
-        rhs = -operators.sampled_rows(sp_, ctrl, rows, Y[j], "K")
+        vecs[f"X{j}"] = T[3 * j] + prm[j][0] * (Ln[3 * j] - T[3 * j])
+        vecs[f"Y{j}"] = Y[j]
+    for a in range(-2, N + 1):
+        vecs[f"L0_{a}"] = L0[a]
+    req = [("x", "M", rows), ("x", "K", rows), ("x", "D", sub)]
+    req += [(f"xk{i}", "K", sub) for i in range(k)]
+    req += [(f"L0_{a}", "M", sub) for a in range(0, N + 1)] + [(f"L0_{a - 2}", "K", sub) for a in range(0, N + 1)]
+    req += [(f"X{j}", "M", sub) for j in range(k)] + [(f"Y{j}", "K", sub) for j in range(k)]
+    ref = oracle_rows(n, p, ctrl, vecs, req)
+    refM, refK, refD = ref[0], ref[1], ref[2]
+    for (ze, which), g in got.items():
+        r_ = refM if which == "M" else refK
+        np.testing.assert_allclose(g, r_, rtol=1e-12, atol=1e-13 * np.abs(r_).max(), err_msg=f"{which} ze={ze}")
+    for i in range(k):
+        r_ = ref[3 + i]
+        np.testing.assert_allclose(gk[i][sub], r_, rtol=1e-12, atol=1e-13 * np.abs(r_).max())
+    np.testing.assert_allclose(gd, refD, rtol=1e-13)
+    bar = max(1e-9, 100 * rtol)
+    # initial data: M L^a = -K L^{a-2} on the rows
+    o = 3 + k
+    for i, a in enumerate(range(0, N + 1)):
+        lhs, rhs = ref[o + i], -ref[o + N + 1 + i]
+        assert np.max(np.abs(lhs - rhs)) < bar * np.max(np.abs(rhs)) + 1e-300, a
+    # the step: stage equations M X_j = -K Y_j, update relations exact
+    o += 2 * (N + 1)
+    for j in range(k):
+        lhs, rhs = ref[o + j], -ref[o + k + j]
         err = np.max(np.abs(lhs - rhs)) / max(np.max(np.abs(rhs)), 1e-300)
         assert np.max(np.abs(rhs)) > 0 and err < bar, (j, err)
     for j, (al, be, gm, _) in enumerate(prm):
@@ -250,7 +291,8 @@ def test_cube_full_size_sampled_rows(n, p, k, rtol, seed):
         Pj = Ln[a] - T[a]
         assert rel(Ln[a - 1], T[a - 1] + gm * tau * Pj) < 1e-12
         assert rel(Ln[a - 2], T[a - 2] + be * tau ** 2 * Pj) < 1e-12
-    _say("  its", its, "device-controlled PCG: iterations ahead, host reads", ga.ga_cg_stats(pt))
+    _say("  rows", len(rows), "its", its, "device-controlled PCG: iterations ahead, host reads",
+         ga.ga_cg_stats(pt))
 
 
 @pytest.mark.parametrize("n,p", [((20, 13, 17), 2), (16, 3), (11, 4)])
@@ -391,19 +433,6 @@ def test_mixed_step_matches_oracle(k, p, n):
     ora = pr.run(U0, 0 * U0, k, 0.5, tau, 24)
     w = _compare(hist, ora, k, 4, 1e-10, pr.M)
     _say("  worst rel L2 error vs oracle", w)
-
-
-def test_preconditioner_plane_too_large_falls_back():
-    # a z-plane of 149 x 139 FP64 coefficients does not fit the on-chip staging:
-    # the default mode must give the dense path's result
-    n, p = (150, 140, 2), 1
-    pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
-    R = _t(np.random.default_rng(5).standard_normal(pt.n_free))
-    za, zd = torch.empty_like(R), torch.empty_like(R)
-    ga.ga_apply_Pinv(pt, R, za)
-    ga.ga_patch_set_pinv(pt, ga.GA_PINV_DENSE)
-    ga.ga_apply_Pinv(pt, R, zd)
-    assert rel(_np(za), _np(zd)) < 1e-14
 
 
 # ---- initial guesses and the residual fallback ----

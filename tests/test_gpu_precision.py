@@ -1,0 +1,199 @@
+"""Reduced-precision forms of the boundary calls (an addition to the paper, which
+computes in FP64): the operator applies and the preconditioner in FP32 and BF16
+through ga_apply_MK / ga_apply_Pinv, the FP64 dense preconditioner on the matrix
+cores, and mass solves and steps whose inner arithmetic is FP32 or BF16, all
+against the FP64 oracle.
+
+Bars, from the arithmetic:
+* mass apply: M has non-negative entries (B-splines >= 0, w|det J| > 0), so every
+  rounding of a factor or of an FP32 partial sum is bounded entrywise by its unit
+  roundoff times (M|x|)_i, with a sum length of a few dozen terms: FP32 1e-5 (M|x|),
+  BF16 factors 2^-9 (M|x|) + 1e-5 (M|x|);
+* stiffness apply (G has signed components, no entrywise bound): norm-wise on random
+  vectors, FP32 1e-5, BF16 factors 1e-2 (a relative rounding of 2^-9 per factor);
+* preconditioner: FP32 5e-5 (three univariate solves with condition numbers of
+  Mhat_a up to ~60 at p = 4, each ~kappa u); BF16 2e-2 (operands rounded to 2^-9 in
+  each of three passes: a CPU emulation of that rounding gives 0.4-0.6 %);
+* solves and steps: the FP64 refinement reaches the FP64 tolerance whatever the
+  inner arithmetic, so the FP64 bars apply (1e-10)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2102_11536_amd import ga, workloads
+from tests.helpers import OracleProblem, rel
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ga.load_library()
+
+
+SHAPES = [(5, 3), ((7, 4, 6), 2), (4, 4), ((9, 5, 6), 3), ((3, 4, 2), 1)]
+
+
+@pytest.mark.parametrize("n,p", SHAPES)
+@pytest.mark.parametrize("prec", [ga.GA_FP32, ga.GA_BF16])
+def test_low_precision_applies_match_oracle(n, p, prec):
+    _say("lowp apply", n, p, prec)
+    pr = OracleProblem(3, n, p, seed=8)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    rng = np.random.default_rng(17)
+    absM = abs(pr.M)
+    for nrhs in (1, 2, 3):
+        X = rng.standard_normal((nrhs, pt.n_free))
+        x = _t(X.ravel())
+        y = torch.empty_like(x)
+        ga.ga_apply_MK(pt, "M", x, y, nrhs=nrhs, alpha=-1.5, prec=prec)
+        got = _np(y).reshape(nrhs, -1)
+        for r in range(nrhs):
+            ref = -1.5 * (pr.M @ X[r])
+            bound = 1.5 * (absM @ np.abs(X[r]))
+            fac = (2.0 ** -9 + 1e-5) if prec == ga.GA_BF16 else 1e-5
+            assert np.all(np.abs(got[r] - ref) <= fac * bound), (nrhs, r)
+        ga.ga_apply_MK(pt, "K", x, y, nrhs=nrhs, prec=prec)
+        got = _np(y).reshape(nrhs, -1)
+        for r in range(nrhs):
+            e = rel(got[r], pr.K @ X[r])
+            assert e < (1e-2 if prec == ga.GA_BF16 else 1e-5), (nrhs, r, e)
+    # FP64 through the same entry point is the plain apply
+    x = _t(X[0])
+    y = torch.empty_like(x)
+    ga.ga_apply_MK(pt, "K", x, y, prec=ga.GA_FP64)
+    assert rel(_np(y), pr.K @ X[0]) < 1e-13
+
+
+@pytest.mark.parametrize("n,p", SHAPES)
+def test_low_precision_preconditioner_matches_oracle(n, p):
+    _say("lowp pinv", n, p)
+    pr = OracleProblem(3, n, p, seed=9)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    R = np.random.default_rng(4).standard_normal((2, pt.n_free))
+    ref = [pr.P.apply(R[i]) for i in range(2)]
+    r = _t(R.ravel())
+    z = torch.empty_like(r)
+    for mode in (ga.GA_PINV_AUTO, ga.GA_PINV_DENSE, ga.GA_PINV_MFMA):
+        ga.ga_patch_set_pinv(pt, mode)
+        ga.ga_apply_Pinv(pt, r, z, nrhs=2, prec=ga.GA_FP32)
+        got = _np(z).reshape(2, -1)
+        for i in range(2):
+            assert rel(got[i], ref[i]) < 5e-5, (mode, i, rel(got[i], ref[i]))
+        ga.ga_apply_Pinv(pt, r, z, nrhs=2, prec=ga.GA_FP64)
+        got = _np(z).reshape(2, -1)
+        for i in range(2):
+            assert rel(got[i], ref[i]) < 1e-12, (mode, i, rel(got[i], ref[i]))
+    # BF16 on the matrix cores (whatever the mode)
+    ga.ga_apply_Pinv(pt, r, z, nrhs=2, prec=ga.GA_BF16)
+    got = _np(z).reshape(2, -1)
+    for i in range(2):
+        e = rel(got[i], ref[i])
+        _say("  bf16 pinv rel err", e)
+        assert e < 2e-2
+    # in place
+    ga.ga_apply_Pinv(pt, r, r, nrhs=2, prec=ga.GA_FP32)
+    assert rel(_np(r).reshape(2, -1)[1], ref[1]) < 5e-5
+
+
+@pytest.mark.parametrize("n,p", [(6, 3), ((7, 4, 6), 2), (5, 4)])
+@pytest.mark.parametrize("prec", [ga.GA_FP32, ga.GA_BF16])
+def test_low_precision_mass_solve_matches_cholesky(n, p, prec):
+    _say("lowp solve", n, p, prec)
+    pr = OracleProblem(3, n, p)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    B = np.random.default_rng(12).standard_normal((2, pt.n_free))
+    b = _t(B.ravel())
+    for mode in (ga.GA_PINV_AUTO, ga.GA_PINV_MFMA):
+        ga.ga_patch_set_pinv(pt, mode)
+        x = torch.zeros_like(b)
+        its, relres, rc = ga.ga_mass_solve(pt, b, x, nrhs=2, rtol=1e-12, prec=prec)
+        got = _np(x).reshape(2, -1)
+        for i in range(2):
+            e = rel(got[i], pr.chol.solve(B[i]))
+            _say("  mode", mode, "rel err", e, "inner its", its[i], "relres", relres[i])
+            assert e < 1e-10 and relres[i] <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [ga.GA_FP32, ga.GA_BF16])
+def test_low_precision_step_matches_oracle(prec):
+    k, p, n = 2, 3, 6
+    pr = OracleProblem(3, n, p, seed=44)
+    tau = pr.tau()
+    U0 = workloads.grf(n, p, seed=3)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    integ = ga.ga_integrator_create(pt, k, 0.5, tau, rtol=1e-12, maxit=400, prec=prec)
+    state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    ga.ga_init_state(integ, _t(U0), _t(0 * U0), state)
+    ga.ga_step(integ, state, 12)
+    ora = pr.run(U0, 0 * U0, k, 0.5, tau, 12)[-1]
+    M = pr.M
+    for s in range(3 * k):
+        g, o = _np(state[s]), ora[s - 2]
+        d = g - o
+        e = np.sqrt(d @ (M @ d)) / max(np.sqrt(o @ (M @ o)), 1e-300)
+        assert e < 1e-10, (s, e)
+
+
+@pytest.mark.parametrize("mode", [ga.GA_PINV_AUTO, ga.GA_PINV_DENSE, ga.GA_PINV_MFMA])
+@pytest.mark.parametrize("n,p", [((100, 3, 3), 2), ((3, 99, 3), 3), ((3, 3, 150), 2), ((160, 4, 3), 4),
+                                 ((3, 2, 255), 3)])
+def test_preconditioner_long_axes_match_oracle(n, p, mode):
+    # axes of 65..144 and 145..256 free coefficients (the larger register classes of
+    # the dense kernels and the largest blocks of the matrix-core kernels) along x,
+    # y and z, against the oracle's Kronecker solves
+    _say("pinv long axes", n, p, mode)
+    pr = OracleProblem(3, n, p, seed=5)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    ga.ga_patch_set_pinv(pt, mode)
+    R = np.random.default_rng(6).standard_normal((2, pt.n_free))
+    r = _t(R.ravel())
+    z = torch.empty_like(r)
+    ga.ga_apply_Pinv(pt, r, z, nrhs=2)
+    got = _np(z).reshape(2, -1)
+    for i in range(2):
+        assert rel(got[i], pr.P.apply(R[i])) < 1e-12, (i, rel(got[i], pr.P.apply(R[i])))
+    ga.ga_apply_Pinv(pt, r, z, nrhs=2, prec=ga.GA_FP32)
+    got = _np(z).reshape(2, -1)
+    for i in range(2):
+        assert rel(got[i], pr.P.apply(R[i])) < 5e-5
+    # a solve with this preconditioner
+    b = _t(R[0])
+    x = torch.zeros_like(b)
+    its, _, _ = ga.ga_mass_solve(pt, b, x, rtol=1e-12)
+    assert rel(_np(x), pr.chol.solve(R[0])) < 1e-10
+
+
+def test_plane_too_large_for_staging_matches_oracle():
+    # a z-plane of 149 x 139 FP64 coefficients does not fit the on-chip staging of
+    # the banded solves: the default mode takes the dense products; every mode
+    # against the oracle
+    n, p = (150, 140, 2), 1
+    pr = OracleProblem(3, n, p, seed=1)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    R = np.random.default_rng(5).standard_normal(pt.n_free)
+    ref = pr.P.apply(R)
+    r = _t(R)
+    z = torch.empty_like(r)
+    for mode in (ga.GA_PINV_AUTO, ga.GA_PINV_DENSE, ga.GA_PINV_MFMA):
+        ga.ga_patch_set_pinv(pt, mode)
+        ga.ga_apply_Pinv(pt, r, z)
+        assert rel(_np(z), ref) < 1e-12, mode

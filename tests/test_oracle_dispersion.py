@@ -119,3 +119,30 @@ def test_two_parameter_family_keeps_order_2k(k):
             L = galpha.step(L, tau, k, rb, lambda y: w ** 2 * y, lambda b: b, rho_s=rs)
         errs.append(abs(L[-2] - np.cos(w * T)))
     assert abs(np.log2(errs[0] / errs[1]) - 2 * k) < 0.35, errs
+
+
+@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("rb,rs", [(0.8, 0.3), (0.6, 0.2), (0.9, 0.0), (0.5, 0.5)])
+def test_two_parameter_type_j_block_roots(k, rb, rs):
+    # eq. root for the blocks j < k under the sign reading: the printed type-j
+    # Omega_b evaluated at (-rho_b, -rho_s) is the type-k Omega_b, and there every
+    # block j < k has the eigenvalues -rho_b (double) and -rho_s.  A flipped sign
+    # (type-j formulas at +rho) moves these roots off -rho_b, -rho_s.
+    _, _, omega_bj, _ = galpha.printed_type_j(-rb, -rs)
+    _, _, omega_bk, _ = galpha.printed_type_k(rb, rs)
+    assert abs(omega_bj - omega_bk) < 1e-14
+    G = galpha.amplification_matrix(k, rb, omega_bj, rho_s=rs)
+    tol = 2e-4 if rb == rs else 1e-6  # a triple root is resolved to ~eps^(1/3)
+    for j in range(k - 1):
+        ev = np.linalg.eigvals(G[3 * j:3 * j + 3, 3 * j:3 * j + 3])
+        assert np.max(np.abs(ev.imag)) < tol
+        np.testing.assert_allclose(np.sort(ev.real), np.sort([-rb, -rb, -rs]), atol=tol)
+    # the literal sign: the type-j block at +rho has other roots at this Theta
+    a, b, _, _ = galpha.printed_type_j(rb, rs)
+    th = omega_bj
+    g = 0.5 - 1 + a
+    blk = np.array([[a - b * th, a - b * th, 0.5 * (a - b * (th + 2))],
+                    [-g * th, a - g * th, a - 0.5 * g * (th + 2)],
+                    [-th, -th, a - 1 - 0.5 * th]]) / a
+    ev = np.sort(np.linalg.eigvals(blk).real)
+    assert np.max(np.abs(ev - np.sort([-rb, -rb, -rs]))) > 1e-2

@@ -58,7 +58,7 @@ def test_multiplicity(P, nadj):
 
 
 def test_glued_operators_spd_and_asm_condition():
-    # kappa(P_ad^{-1} M) <= C N_adj^2 (Sec. 5.7): bounded growth with the adjacency
+    # kappa(P_ad^{-1} M) <= C N_adj^2 (Sec. 5.5): bounded growth with the adjacency
     kap = {}
     for P, nadj in (((1, 1, 1), 1), ((2, 1, 1), 2), ((2, 2, 1), 4)):
         b = mp.Brick(P, 3, 2)

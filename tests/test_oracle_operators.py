@@ -189,3 +189,18 @@ def test_nonpositive_jacobian_rejected():
     ctrl[:, 0] = -ctrl[:, 0]
     with pytest.raises(ValueError):
         operators.assemble(sp_, ctrl)
+
+
+def test_oracle_rows_in_worker_processes():
+    # the process-pool front end of sampled_rows (used by the full-size GPU checks)
+    # returns exactly the rows the oracle computes in this process
+    from tests.helpers import oracle_rows, stratified_rows
+    n, p = 6, 3
+    ctrl = workloads.deformed_cube_ctrl(n, p)
+    sp_ = operators.Space(n, p, 3)
+    X = workloads.grf(n, p, seed=4)
+    rows = stratified_rows((n + 1,) * 3, p, [4], [2, 4], 40, 3)
+    got = oracle_rows(n, p, ctrl, {"x": X}, [("x", "M", rows), ("x", "K", rows), ("x", "D", rows)],
+                      workers=2)
+    for g, which in zip(got, "MKD"):
+        assert np.array_equal(g, operators.sampled_rows(sp_, ctrl, rows, X, which))
