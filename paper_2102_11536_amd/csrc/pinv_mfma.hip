@@ -36,7 +36,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <int KIND> struct Mf;
 // D layout of the 32 x 32 instructions: value v of lane l is row 8 (v / 4) + 4 (l / 32)
-// + v % 4, column l % 32; of the 16 x 16 FP64 instruction: row 4 (l / 16) + v, column l % 16
+// + v % 4, column l % 32; of the 16 x 16 FP64 instruction: row l / 16 + 4 v, column l % 16
 template <> struct Mf<GA_BF16> {
   using S = float;
   using Frag = bf16x8;
@@ -72,7 +72,7 @@ template <> struct Mf<GA_FP64> {
   static __device__ __forceinline__ Acc mma(Frag a, Frag b, Acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ int row(int v, int l) { return 4 * (l >> 4) + v; }
+  static __device__ __forceinline__ int row(int v, int l) { return (l >> 4) + 4 * v; }
   static __device__ __forceinline__ Frag frag(const S (&v)[KE]) { return v[0]; }
 };
 
