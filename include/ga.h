@@ -146,6 +146,24 @@ int ga_apply_MK(ga_patch* patch, char which, int nrhs, int prec, double alpha,
  */
 int ga_apply_Pinv(ga_patch* patch, int nrhs, int prec, const double* r_dev, double* z_dev,
                   void* stream);
+/*
+ * ga_apply_Pinv_noalloc -- ga_apply_Pinv with prec = GA_FP64 for callers that
+ * cannot allocate device memory (code under HIP stream or graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  It allocates nothing: its two
+ * intermediate vectors live in a fixed device array that the library holds on every
+ * GPU it runs on (2 * GA_NOALLOC_MAX_ENTRIES doubles, 72 MiB, from module load
+ * until the process ends).
+ *   nrhs * n_free must not exceed GA_NOALLOC_MAX_ENTRIES (GA_EINVAL otherwise).
+ *   With GA_PINV_MFMA the packed inverses must have been built by an earlier
+ *   ga_apply_Pinv or solve on the patch (GA_EINVAL otherwise).
+ * All calls on one GPU share that array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialized by the caller.  Results
+ * equal those of ga_apply_Pinv (the same kernels).
+ */
+#define GA_NOALLOC_MAX_ENTRIES 4718592
+int ga_apply_Pinv_noalloc(ga_patch* patch, int nrhs, const double* r_dev, double* z_dev,
+                          void* stream);
+
 /* Preconditioner algorithm of a patch (all compute the same P^{-1}):
  * GA_PINV_AUTO (banded solves when they fit, the default), GA_PINV_DENSE (dense
  * inverse products on the vector ALU) or GA_PINV_MFMA (dense inverse products on

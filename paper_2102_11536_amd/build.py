@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libga.so")
 SOURCES = ["ops3d.hip", "ops3d_lowp.hip", "spline1d.cpp", "ops2d.hip", "vec.hip", "pinv.hip", "pinv_band.hip", "pinv_mfma.hip", "mixed.hip", "gnet.hip",
-           "api.hip", "api_gnet.hip", "batch.hip", "wave1d.hip"]
+           "api.hip", "noalloc.hip", "api_gnet.hip", "batch.hip", "wave1d.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-command-line-argument"]

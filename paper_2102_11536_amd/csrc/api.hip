@@ -586,6 +586,20 @@ int solve_any(ga_patch* pt, int nr, const double* b, double* x, double rtol, int
 
 int ga::mixed_setup(ga_patch* pt, hipStream_t st) { return ensure_mixed(pt, st); }
 
+// P^{-1} in FP64 with caller-provided scratch t0, t1 (each nr * n_free); allocates
+// nothing as long as the patch's preconditioner data exist (a matrix-core mode
+// whose packed inverses are not built yet is refused)
+int ga::pinv_apply_scratch(ga_patch* pt, int nr, const double* r, double* z, double* t0, double* t1,
+                           hipStream_t st) {
+  if (pt->pinv_mode == GA_PINV_MFMA)
+    for (int a = 0; a < pt->dim; ++a)
+      if (!pt->apk[GA_FP64][a]) {
+        set_error("the matrix-core preconditioner data are built by a first ga_apply_Pinv call");
+        return GA_EINVAL;
+      }
+  return pinv_apply(pt, nr, r, z, t0, t1, st);
+}
+
 extern "C" {
 
 const char* ga_last_error(void) { return g_err.c_str(); }

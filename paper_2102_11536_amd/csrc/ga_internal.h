@@ -98,6 +98,11 @@ void block_k_params2(double rho_b, double rho_s, double& a, double& b, double& g
 // for the mixed-precision solves (built once, kept with the patch)
 int mixed_setup(ga_patch* pt, hipStream_t st);
 
+// FP64 P^{-1} with caller-provided scratch vectors t0, t1 (nr * n_free each); no
+// allocation
+int pinv_apply_scratch(ga_patch* pt, int nr, const double* r, double* z, double* t0, double* t1,
+                       hipStream_t st);
+
 // whole-grid learned guess of one stage from its four newest solutions h[0..3]
 int gnet_guess(ga_gnet* net, ga_patch* pt, const double* const* h, double* X, hipStream_t st);
 

@@ -19,7 +19,7 @@ GA_PINV_AUTO, GA_PINV_DENSE, GA_PINV_MFMA = 0, 1, 2
 GA_CG_HOST, GA_CG_DEVICE = 0, 1
 
 EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
-           "ga_apply_Pinv", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
+           "ga_apply_Pinv", "ga_apply_Pinv_noalloc", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",
            "ga_integrator_create", "ga_integrator_destroy", "ga_init_state", "ga_step",
            "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error", "ga_stage_solution", "ga_patch_set_pinv",
            "ga_integrator_set_damping", "ga_stage_times", "ga_init_state_forced", "ga_step_forced",
@@ -60,6 +60,7 @@ def load_library(path=LIB_PATH):
     lib.ga_diag_M.argtypes = [vp, dp, vp]
     lib.ga_apply_MK.argtypes = [vp, ctypes.c_char, i, i, d, dp, dp, vp]
     lib.ga_apply_Pinv.argtypes = [vp, i, i, dp, dp, vp]
+    lib.ga_apply_Pinv_noalloc.argtypes = [vp, i, dp, dp, vp]
     lib.ga_mass_solve.argtypes = [vp, i, dp, dp, d, i, i, ctypes.POINTER(i), ctypes.POINTER(d), vp]
     lib.ga_lambda_max.argtypes = [vp, i, ctypes.POINTER(d), vp]
     lib.ga_stability_limit.argtypes = [d]
@@ -238,6 +239,15 @@ def ga_apply_MK(patch, which, x, y, nrhs=1, alpha=1.0, prec=GA_FP64):
 def ga_apply_Pinv(patch, r, z, nrhs=1, prec=GA_FP64):
     n = nrhs * patch.n_free
     _check(_lib.ga_apply_Pinv(patch.h, nrhs, int(prec), _ptr(r, n), _ptr(z, n), _stream()))
+
+
+def ga_apply_Pinv_noalloc(patch, r, z, nrhs=1):
+    """FP64 P^{-1} with the library's fixed device scratch (no allocation)."""
+    n = nrhs * patch.n_free
+    _check(_lib.ga_apply_Pinv_noalloc(patch.h, nrhs, _ptr(r, n), _ptr(z, n), _stream()))
+
+
+GA_NOALLOC_MAX_ENTRIES = 4718592
 
 
 def ga_mass_solve(patch, b, x, nrhs=1, rtol=1e-12, maxit=500, raise_on_noconv=True, prec=GA_FP64):
