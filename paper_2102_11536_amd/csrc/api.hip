@@ -412,7 +412,7 @@ int ensure_packed(ga_patch* pt, int prec, hipStream_t st) {
 // (banded FP32 solves, dense FP32 products on the vector ALU, or dense FP32 products
 // on the matrix cores), GA_BF16 on the matrix cores with BF16 operands
 int pinv_apply_lp(ga_patch* pt, int prec, int nr, const float* r, float* z, float* t0, float* t1,
-                  hipStream_t st) {
+                  hipStream_t st, const double* gate = nullptr) {
   const size_t n = pt->n_free;
   const int m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
   if (!(pinv_axis_supported(m0) && pinv_axis_supported(m1) && pinv_axis_supported(m2))) {
@@ -431,7 +431,8 @@ int pinv_apply_lp(ga_patch* pt, int prec, int nr, const float* r, float* z, floa
   }
   if (pt->pinv_mode != GA_PINV_DENSE) {
     const float* cb[3] = {pt->cb32[0], pt->cb32[1], pt->cb32[2]};
-    rc = launch_pinv_band<float>(3, pt->p, pt->mf, nr, r, z, t0, t1, cb, pt->s32, (long long)n, st);
+    rc = launch_pinv_band<float>(3, pt->p, pt->mf, nr, r, z, t0, t1, cb, pt->s32, (long long)n, st,
+                                 gate);
     if (rc == 0) return check_launch(0, "FP32 preconditioner");
     if (rc < 0) return check_launch(-1, "FP32 preconditioner");
   }
@@ -446,7 +447,7 @@ int pinv_apply_lp(ga_patch* pt, int prec, int nr, const float* r, float* z, floa
 
 // y += alpha Op x with FP32 vectors, FP32 (prec GA_FP32) or BF16 (GA_BF16) factors
 int op_apply_lp(ga_patch* pt, int mode, int prec, int nr, float alpha, const float* x, float* y,
-                hipStream_t st) {
+                hipStream_t st, const double* gate = nullptr) {
   int rc = ensure_factors(pt, mode, prec, st);
   if (rc) return rc;
   const int cmax = op3d_max_nr(pt->p, mode);
@@ -454,15 +455,16 @@ int op_apply_lp(ga_patch* pt, int mode, int prec, int nr, float alpha, const flo
     const int c = nr - r0 < cmax ? nr - r0 : cmax;
     ProfScope prof(mode == 1 ? 1 : 0, st);
     rc = launch_op3d_lowp(mode, c, pt, x + (size_t)r0 * pt->n_free, y + (size_t)r0 * pt->n_free,
-                          alpha, prec, st);
+                          alpha, prec, st, gate ? gate + (size_t)r0 * NSCAL : nullptr);
     if (check_launch(rc, "low-precision operator apply")) return GA_EDEVICE;
   }
   return GA_OK;
 }
 
-int mass_apply_lp(ga_patch* pt, int prec, int nr, const float* x, float* y, hipStream_t st) {
+int mass_apply_lp(ga_patch* pt, int prec, int nr, const float* x, float* y, hipStream_t st,
+                  const double* gate = nullptr) {
   launch_fill_f32(y, (size_t)nr * pt->n_free, st);
-  return op_apply_lp(pt, 0, prec, nr, 1.0f, x, y, st);
+  return op_apply_lp(pt, 0, prec, nr, 1.0f, x, y, st, gate);
 }
 
 int read_scalars(ga_patch* pt, int nr, hipStream_t st) {
@@ -472,10 +474,20 @@ int read_scalars(ga_patch* pt, int nr, hipStream_t st) {
   return GA_OK;
 }
 
-// Outer FP64 refinement: r = b - M x (FP64 factors and arithmetic), stop when
-// sqrt(r^T P^{-1} r) <= rtol sqrt(b^T P^{-1} b) (P^{-1} applied in FP32, dots in
-// FP64); each correction M d = r comes from an FP32 flexible PCG (FP32 factors,
-// vectors and preconditioner) that reduces its residual by inner_tol.
+// Mixed precision: FP64 iterative refinement around an inner flexible PCG in FP32
+// (or with BF16 factors and preconditioner).  Outer pass: the FP64 residual
+// r = b - M x (FP64 factors and arithmetic), z = P^{-1} r in the inner precision,
+// the outer test sqrt(r^T z) <= rtol sqrt(b^T P^{-1} b) with FP64-accumulated dots;
+// the inner PCG for M d = r starts from d = 0 and stops when its residual has
+// dropped to max(rtol_remaining / 2, floor) (rtol_remaining = rtol |b|_P / |r|_P, so
+// a single pass reaches rtol where the inner precision allows it; floor: what the
+// inner arithmetic resolves); then x += d in FP64.  Control stays on the device:
+// every inner launch is gated by the per-system inner flags, the host enqueues the
+// number of inner iterations the previous solve needed and reads the flags once per
+// outer pass.
+constexpr int MX_ITERS_LAST = 10;   // outer scalar slots: inner iterations of the last pass,
+constexpr int MX_CUT = 11;          //   and whether that pass ended with its inner PCG still active
+
 int solve_mixed_impl(ga_patch* pt, int prec, int nr, const double* b, double* x, double rtol,
                      int maxit, bool zero_guess, int* iters_out, double* relres_out,
                      hipStream_t st) {
@@ -483,90 +495,94 @@ int solve_mixed_impl(ga_patch* pt, int prec, int nr, const double* b, double* x,
   const size_t tot = (size_t)nr * n;
   int rc = ensure_mixed(pt, st);
   if (rc) return rc;
-  if ((rc = ensure_work(pt, 6 * nr))) return rc;
+  if ((rc = ensure_work(pt, 5 * nr))) return rc;   // r64 and seven FP32 vectors
   double* r64 = pt->work;
   float* f = reinterpret_cast<float*>(pt->work + tot);
   float *r32 = f, *z32 = f + tot, *p32 = f + 2 * tot, *q32 = f + 3 * tot, *d32 = f + 4 * tot,
         *t0 = f + 5 * tot, *t1 = f + 6 * tot;
   double* partA = pt->red;
   double* partB = pt->red + (size_t)16 * RED_BLOCKS;
-  const double inner_tol = 1e-4;
-  // outer residual and the norm of b
-  launch_copy(r64, b, tot, st);
-  if (zero_guess) launch_fill(x, 0.0, tot, st);
-  else if ((rc = op_apply(pt, 0, nr, -1.0, x, r64, st))) return rc;
-  launch_to_f32(r32, b, tot, st);
+  double* so = pt->scal;                       // outer (FP64 refinement) scalars
+  double* si = pt->scal + (size_t)32 * NSCAL;  // inner PCG scalars
+  const double floor = prec == GA_BF16 ? 2e-3 : 3e-7;
+  const int h = prec == GA_BF16 ? 1 : 0;
+  int& hint = pt->mx_hint[h];
+  if (hint < 1) hint = 2;
+  // residual of the initial guess, z = P^{-1} r, and (for a guess) P^{-1} b
+  if (zero_guess) {
+    launch_fill(x, 0.0, tot, st);
+    launch_copy(r64, b, tot, st);
+  } else {
+    launch_copy(r64, b, tot, st);
+    if ((rc = op_apply(pt, 0, nr, -1.0, x, r64, st))) return rc;
+    launch_to_f32(q32, b, tot, st);
+    if ((rc = pinv_apply_lp(pt, prec, nr, q32, p32, t0, t1, st))) return rc;
+    launch_dot_ff(nr, q32, p32, n, partB, st);
+  }
+  launch_to_f32(r32, r64, tot, st);
   if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
-  launch_dot_df(nr, b, z32, n, partB, st);
-  std::vector<double> bn2(nr), rz(nr);
-  launch_sum_partials(nr, partB, pt->scal, st);
-  if ((rc = read_scalars(pt, nr, st))) return rc;
-  for (int r = 0; r < nr; ++r) bn2[r] = pt->host_scal[r];
-  int inner_total[16] = {0};
+  launch_dot_ff(nr, r32, z32, n, partA, st);
+  launch_mx_outer(nr, partA, zero_guess ? nullptr : partB, so, si, rtol * rtol, floor * floor, 0,
+                  st);
+  // a guess worse than zero: x = 0, r = b, z = P^{-1} b (q32, p32 hold b and P^{-1} b)
+  if (!zero_guess) launch_mx_fallback(nr, x, r64, r32, z32, b, q32, p32, so, n, st);
   bool conv = false;
-  for (int outer = 0; outer < 50; ++outer) {
-    launch_to_f32(r32, r64, tot, st);
-    if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
-    launch_dot_df(nr, r64, z32, n, partA, st);
-    launch_sum_partials(nr, partA, pt->scal, st);
-    if ((rc = read_scalars(pt, nr, st))) return rc;
-    if (outer == 0 && !zero_guess) {
-      // keep the initial guess only if its residual is smaller than b's
-      bool reset = false;
+  int inner_total_max = 0;
+  for (int pass = 0; pass < 50; ++pass) {
+    if (pass > 0) {
+      GA_TRY_HIP(hipMemcpyAsync(pt->host_scal, so, sizeof(double) * NSCAL * 32,
+                                hipMemcpyDeviceToHost, st));
+      GA_TRY_HIP(hipStreamSynchronize(st));
+      pt->n_checks += 1;
+      bool any = false, cut = false;
+      int its = 0;
       for (int r = 0; r < nr; ++r) {
-        pt->n_guessed += 1;
-        pt->guess_rel_sum += bn2[r] > 0 ? std::sqrt(std::fabs(pt->host_scal[r] / bn2[r])) : 0.0;
-        if (!(pt->host_scal[r] < bn2[r])) {  // restart this right-hand side from zero
-          reset = true;
-          pt->n_fallbacks += 1;
-          launch_fill(x + (size_t)r * n, 0.0, n, st);
-          launch_copy(r64 + (size_t)r * n, b + (size_t)r * n, n, st);
-          launch_to_f32(r32 + (size_t)r * n, b + (size_t)r * n, n, st);
-          pt->host_scal[r] = bn2[r];
-        }
+        const double* s = pt->host_scal + r * NSCAL;
+        any |= s[S_ACTIVE] != 0.0;
+        cut |= s[MX_CUT] != 0.0;
+        its = std::max(its, (int)s[MX_ITERS_LAST]);
+        inner_total_max = std::max(inner_total_max, (int)s[S_ITERS]);
       }
-      if (reset && (rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
+      // next solve: as many inner iterations as this pass needed (one more if it was cut short)
+      hint = std::min(20, cut ? hint + 1 : std::max(1, its));
+      if (!any) { conv = true; break; }
+      if (inner_total_max >= maxit) break;
     }
-    bool all = true;
-    for (int r = 0; r < nr; ++r) {
-      rz[r] = pt->host_scal[r];
-      if (bn2[r] > 0.0 && rz[r] > rtol * rtol * bn2[r]) all = false;
-    }
-    int used = 0;
-    for (int r = 0; r < nr; ++r) used = std::max(used, inner_total[r]);
-    if (all) { conv = true; break; }
-    if (used >= maxit) break;
-    // inner FP32 flexible PCG for M d = r, d0 = 0: z32 already holds P^{-1} r
+    // inner flexible PCG for M d = r from d = 0 (z32 = P^{-1} r32), gated by the inner flags
     launch_fill_f32(d32, tot, st);
-    launch_dot_ff(nr, r32, z32, n, partA, st);
-    launch_cg_start(nr, partA, nullptr, pt->scal, inner_tol * inner_tol, st);
     launch_copy_f32(p32, z32, tot, st);
-    for (int it = 0; it < 20; ++it) {
-      if ((rc = read_scalars(pt, nr, st))) return rc;
-      bool any = false;
-      for (int r = 0; r < nr; ++r) any |= pt->host_scal[r * NSCAL + S_ACTIVE] != 0.0;
-      if (!any) break;
-      if ((rc = mass_apply_lp(pt, prec, nr, p32, q32, st))) return rc;
+    for (int it = 0; it < hint; ++it) {
+      if ((rc = mass_apply_lp(pt, prec, nr, p32, q32, st, si))) return rc;
       launch_dot_ff(nr, p32, q32, n, partA, st);
-      launch_cg_alpha(nr, partA, pt->scal, st);
-      launch_cg_xr_f32(nr, d32, r32, p32, q32, pt->scal, n, st);
-      if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
+      launch_cg_alpha(nr, partA, si, st);
+      launch_cg_xr_f32(nr, d32, r32, p32, q32, si, n, st);
+      if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st, si))) return rc;
       launch_dot2_f32(nr, r32, z32, q32, n, partA, partB, st);
-      launch_cg_beta_flex(nr, partA, partB, pt->scal, st);
-      launch_cg_p_f32(nr, p32, z32, pt->scal, n, st);
-      if (check_launch(0, "inner PCG")) return GA_EDEVICE;
+      launch_cg_beta_flex(nr, partA, partB, si, st);
+      launch_cg_p_f32(nr, p32, z32, si, n, st);
     }
-    if ((rc = read_scalars(pt, nr, st))) return rc;
-    for (int r = 0; r < nr; ++r) inner_total[r] += (int)pt->host_scal[r * NSCAL + S_ITERS];
-    // x += d; r = b - M x in FP64
+    if (check_launch(0, "inner PCG")) return GA_EDEVICE;
+    // x += d; r = b - M x in FP64; z = P^{-1} r; the outer test and the next inner start
     launch_add_f32(x, d32, tot, st);
     launch_copy(r64, b, tot, st);
     if ((rc = op_apply(pt, 0, nr, -1.0, x, r64, st))) return rc;
+    launch_to_f32(r32, r64, tot, st);
+    if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
+    launch_dot_ff(nr, r32, z32, n, partA, st);
+    launch_mx_outer(nr, partA, nullptr, so, si, rtol * rtol, floor * floor, 1, st);
   }
+  if (check_launch(0, "mixed-precision solve")) return GA_EDEVICE;
   pt->n_solves += nr;
   for (int r = 0; r < nr; ++r) {
-    if (iters_out) iters_out[r] = inner_total[r];
-    if (relres_out) relres_out[r] = bn2[r] > 0 ? std::sqrt(std::fabs(rz[r] / bn2[r])) : 0.0;
+    const double* s = pt->host_scal + r * NSCAL;
+    if (!zero_guess) {
+      pt->n_guessed += 1;
+      pt->n_fallbacks += s[S_FALLBACK] != 0.0 ? 1 : 0;
+      pt->guess_rel_sum += s[S_BN2] > 0 ? std::sqrt(std::fabs(s[S_RZ0] / s[S_BN2])) : 0.0;
+    }
+    if (iters_out) iters_out[r] = (int)s[S_ITERS];
+    if (relres_out) relres_out[r] = s[S_BN2] > 0 ? std::sqrt(std::fabs(s[S_RZ] / s[S_BN2])) : 0.0;
+    if (!std::isfinite(s[S_RZ])) conv = false;
   }
   if (!conv) {
     set_error("mixed-precision solve did not converge within maxit");

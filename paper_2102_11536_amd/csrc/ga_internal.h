@@ -121,6 +121,7 @@ struct ga_patch {
   int hint_nr = 0;                // iterations per right-hand side of the last FP64 solve
   int hint[16] = {0};             //   of hint_nr right-hand sides (speculative schedule)
   long long n_spec = 0, n_checks = 0;   // iterations enqueued ahead, host convergence reads
+  int mx_hint[2] = {0, 0};        // inner iterations per pass of the last FP32 / BF16 mixed solve
   long long n_free = 0, n_quad = 0, n_tiles = 0, qp_per_tile = 0;
   ga::Axis1D ax[3];
   // device data

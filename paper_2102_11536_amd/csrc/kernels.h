@@ -157,6 +157,15 @@ void launch_dot2_f32(int nr, const float* r, const float* z, const float* q, siz
                      double* p2, hipStream_t st,
                const long long* seg = nullptr);
 void launch_cg_beta_flex(int nr, const double* p1, const double* p2, double* scal, hipStream_t st);
+// mixed-precision refinement: the outer test from rz = r^T P^{-1} r (partials; pass 0
+// also sets b^T P^{-1} b from part_bn, or from rz with a zero guess, and the guess
+// fallback flag) and the start of the inner PCG (scalars si) for the next pass
+void launch_mx_outer(int nr, const double* part_rz, const double* part_bn, double* so, double* si,
+                     double rtol2, double floor2, int pass, hipStream_t st);
+// systems whose guess was rejected restart from zero: x = 0, r64 = b, r32 = b32, z32 = zb32
+void launch_mx_fallback(int nr, double* x, double* r64, float* r32, float* z32, const double* b,
+                        const float* b32, const float* zb32, const double* so, size_t n,
+                        hipStream_t st);
 void launch_cg_xr_f32(int nr, float* x, float* r, const float* p, const float* q,
                       const double* scal, size_t n, hipStream_t st,
                const long long* seg = nullptr);

@@ -149,6 +149,60 @@ __global__ void __launch_bounds__(VB) cg_beta_flex_k(const double* p1, const dou
   }
 }
 
+// outer test and inner start of the mixed-precision refinement (one block per system)
+__global__ void __launch_bounds__(VB)
+mx_outer_k(const double* part_rz, const double* part_bn, double* so, double* si, double rtol2,
+           double floor2, int pass) {
+  __shared__ double sh[VB / 64];
+  const int r = blockIdx.x;
+  double rz = sum_part(part_rz, r, sh);
+  const double bn = part_bn ? sum_part(part_bn, r, sh) : rz;
+  if (threadIdx.x != 0) return;
+  double* o = so + (size_t)r * NSCAL;
+  double* in = si + (size_t)r * NSCAL;
+  if (pass == 0) {
+    o[S_RZ0] = rz;
+    o[S_FALLBACK] = (part_bn && !(rz < bn)) ? 1.0 : 0.0;   // keep a guess only if it beats zero
+    if (o[S_FALLBACK] != 0.0) rz = bn;
+    o[S_BN2] = bn;
+    o[S_TOL2] = rtol2;
+    o[S_ITERS] = 0.0;
+    o[10] = 0.0;
+    o[11] = 0.0;
+  } else {
+    o[S_ITERS] += in[S_ITERS];
+    o[10] = in[S_ITERS];                                    // inner iterations of that pass
+    o[11] = in[S_ACTIVE];                                   // still active when the pass ended
+  }
+  o[S_RZ] = rz;
+  const double b2 = o[S_BN2];
+  const bool active = b2 > 0.0 && rz > rtol2 * b2;
+  o[S_ACTIVE] = active ? 1.0 : 0.0;
+  // inner PCG for M d = r: stop at max(rtol_remaining / 2, floor) relative to |r|_P
+  in[S_RZ] = rz;
+  in[S_BN2] = rz;
+  in[S_TOL2] = active ? fmax(0.25 * rtol2 * b2 / rz, floor2) : 1.0;
+  in[S_ITERS] = 0.0;
+  in[S_ALPHA] = 0.0;
+  in[S_BETA] = 0.0;
+  in[S_ACTIVE] = active ? 1.0 : 0.0;
+}
+
+__global__ void mx_fallback_k(double* __restrict__ x, double* __restrict__ r64, float* __restrict__ r32,
+                              float* __restrict__ z32, const double* __restrict__ b,
+                              const float* __restrict__ b32, const float* __restrict__ zb32,
+                              const double* __restrict__ so, size_t n) {
+  const int rr = blockIdx.y;
+  if (so[(size_t)rr * NSCAL + S_FALLBACK] == 0.0) return;
+  const size_t off = (size_t)rr * n;
+  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB) {
+    x[off + i] = 0.0;
+    r64[off + i] = b[off + i];
+    r32[off + i] = b32[off + i];
+    z32[off + i] = zb32[off + i];
+  }
+}
+
 __global__ void cg_xr_f32_k(float* __restrict__ x, float* __restrict__ r,
                             const float* __restrict__ p, const float* __restrict__ q,
                             const double* __restrict__ scal, size_t n,
@@ -210,6 +264,18 @@ void launch_dot2_f32(int nr, const float* r, const float* z, const float* q, siz
 }
 void launch_cg_beta_flex(int nr, const double* p1, const double* p2, double* scal, hipStream_t st) {
   hipLaunchKernelGGL(cg_beta_flex_k, dim3(nr), dim3(VB), 0, st, p1, p2, scal);
+}
+void launch_mx_outer(int nr, const double* part_rz, const double* part_bn, double* so, double* si,
+                     double rtol2, double floor2, int pass, hipStream_t st) {
+  hipLaunchKernelGGL(mx_outer_k, dim3(nr), dim3(VB), 0, st, part_rz, part_bn, so, si, rtol2, floor2,
+                     pass);
+}
+void launch_mx_fallback(int nr, double* x, double* r64, float* r32, float* z32, const double* b,
+                        const float* b32, const float* zb32, const double* so, size_t n,
+                        hipStream_t st) {
+  unsigned bl = nb(n) > 2048 ? 2048 : nb(n);
+  hipLaunchKernelGGL(mx_fallback_k, dim3(bl, nr), dim3(VB), 0, st, x, r64, r32, z32, b, b32, zb32,
+                     so, n);
 }
 void launch_cg_xr_f32(int nr, float* x, float* r, const float* p, const float* q,
                       const double* scal, size_t n, hipStream_t st, const long long* seg) {
