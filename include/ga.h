@@ -204,7 +204,16 @@ int ga_patch_tuned_layers(const ga_patch* patch, int* ze_mass, int* ze_stiff);
  * stiffness launches of a 3-D patch (1..n_el[2]; 0 = automatic), as the autotuner
  * would: the launch shapes change, the results do not.  GA_EINVAL out of range. */
 int ga_patch_set_layers(ga_patch* patch, int ze_mass, int ze_stiff);
-enum { GA_CG_HOST = 0, GA_CG_DEVICE = 1 };
+/*   GA_CG_FUSED   single-reduction (Chronopoulos-Gear) PCG under the same device
+ *                 control: six launches per iteration instead of eleven: the mass
+ *                 apply w = M z, one reduction for z^T w, one kernel that completes
+ *                 it in every workgroup, takes the alpha/beta step and updates p,
+ *                 s = M p, x and r, and the three preconditioner passes, the last of
+ *                 which sums r^T z and applies the stopping test (its last
+ *                 workgroup completes the sum).  The same iterates as GA_CG_DEVICE
+ *                 in exact arithmetic and the same stopping test.  3-D patches with
+ *                 the banded preconditioner (otherwise GA_CG_DEVICE's rules apply). */
+enum { GA_CG_HOST = 0, GA_CG_DEVICE = 1, GA_CG_FUSED = 2 };
 int ga_patch_set_cg(ga_patch* patch, int mode);
 int ga_cg_stats(const ga_patch* patch, long long* spec_iters, long long* host_checks);
 

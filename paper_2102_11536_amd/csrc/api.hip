@@ -249,12 +249,65 @@ int gated_iteration(ga_patch* pt, int nr, int it, double* x, const SolveBufs& w,
   return check_launch(0, "gated pcg iteration");
 }
 
+// One single-reduction (Chronopoulos-Gear) PCG iteration under device control, six
+// launches: w = M z (gated, grouped by the schedule as in gated_iteration), the
+// partial sums of delta = z^T w, one kernel that completes delta in every workgroup,
+// takes the alpha/beta step and updates p, s = M p, x and r, and the three
+// preconditioner passes, the last of which sums gamma = r^T z (its last workgroup
+// per right-hand side completes the sum and applies the stopping test, so a
+// converged system skips the next mass apply).
+int cgcg_iteration(ga_patch* pt, int nr, int it, double* x, double* r, double* z, double* p,
+                   double* sv, double* w, double* t0, double* t1, hipStream_t st) {
+  const size_t n = pt->n_free;
+  const double* gate = pt->scal;
+  int a = nr, b = 0;
+  for (int q = 0; q < nr; ++q)
+    if (pt->hint[q] > it) { a = std::min(a, q); b = q + 1; }
+  if (a >= b) { a = 0; b = nr; }
+  {
+    ProfScope prof(0, st);
+    int rc = 0;
+    for (int r0 = a; r0 < b && !rc; r0 += MAX_NR) {
+      const int c = std::min(MAX_NR, b - r0);
+      rc = launch_op3d(0, c, pt, z + (size_t)r0 * n, w + (size_t)r0 * n, 1.0, st,
+                       gate + (size_t)r0 * NSCAL);
+    }
+    for (int q = 0; q < nr && !rc; ++q)
+      if (q < a || q >= b)
+        rc = launch_op3d(0, 1, pt, z + (size_t)q * n, w + (size_t)q * n, 1.0, st,
+                         gate + (size_t)q * NSCAL);
+    if (check_launch(rc, "single-reduction mass apply")) return GA_EDEVICE;
+  }
+  launch_dot_partial(nr, z, w, n, pt->red, st, gate);
+  launch_cgcg_update(nr, it, x, r, p, sv, w, z, pt->red, pt->scal, n, st);
+  {
+    ProfScope prof(2, st);
+    const double* cb[3] = {pt->cb[0], pt->cb[1], pt->cb[2]};
+    CgFuse fz{pt->cgf_part, pt->cgf_cnt, pt->scal, CGF_PSTRIDE};
+    if (launch_pinv_band_cgcg(pt->p, pt->mf, nr, r, z, t0, t1, cb, pt->s, (long long)n, st, gate, fz))
+      return check_launch(-1, "single-reduction preconditioner");
+  }
+  return check_launch(0, "single-reduction pcg iteration");
+}
+
+int ensure_cgf(ga_patch* pt) {
+  if (pt->cgf_part) return GA_OK;
+  int rc = dalloc((void**)&pt->cgf_part, sizeof(double) * CGF_MAXRHS * CGF_PSTRIDE);
+  if (rc) return rc;
+  if ((rc = dalloc((void**)&pt->cgf_cnt, sizeof(unsigned) * 64))) return rc;
+  GA_TRY_HIP(hipMemset(pt->cgf_cnt, 0, sizeof(unsigned) * 64));
+  return GA_OK;
+}
+
 // PCG for nr right-hand sides; x holds the guess (zero_guess: ignored and set to 0)
 int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, int maxit,
                bool zero_guess, int* iters_out, double* relres_out, hipStream_t st) {
   const size_t n = pt->n_free;
-  int rc = ensure_work(pt, 6 * nr);
+  const bool fused = pt->cg_ctrl == GA_CG_FUSED && pt->dim == 3 && pt->pinv_mode == GA_PINV_AUTO &&
+                     nr <= 16 && pinv_band_fits(3, pt->p, pt->mf, sizeof(double));
+  int rc = ensure_work(pt, fused ? 7 * nr : 6 * nr);
   if (rc) return rc;
+  if (fused && (rc = ensure_cgf(pt))) return rc;
   SolveBufs w;
   double* base = pt->work;
   w.r = base;
@@ -283,9 +336,31 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
   }
   launch_cg_start(nr, partA, pbn, pt->scal, rtol * rtol, st);
   if (!zero_guess) launch_cg_fallback(nr, x, w.r, w.z, b, w.q, pt->scal, n, st);
-  launch_copy(w.p, w.z, tot, st);
   if (check_launch(0, "pcg start")) return GA_EDEVICE;
   int it = 0;
+  if (fused) {
+    // single-reduction PCG: w (in q) starts at zero, s is the seventh vector
+    double* sv = base + (size_t)6 * nr * n;
+    launch_fill(w.q, 0.0, tot, st);
+    if (pt->hint_nr == nr) {
+      int hmax = 0;
+      for (int r = 0; r < nr; ++r) hmax = std::max(hmax, pt->hint[r]);
+      for (; it < std::min(hmax, maxit); ++it)
+        if ((rc = cgcg_iteration(pt, nr, it, x, w.r, w.z, w.p, sv, w.q, w.t0, w.t1, st))) return rc;
+      pt->n_spec += it;
+    }
+    for (;; ++it) {
+      GA_TRY_HIP(hipMemcpyAsync(pt->host_scal, pt->scal, sizeof(double) * NSCAL * nr,
+                                hipMemcpyDeviceToHost, st));
+      GA_TRY_HIP(hipStreamSynchronize(st));
+      pt->n_checks += 1;
+      bool any = false;
+      for (int r = 0; r < nr; ++r) any |= pt->host_scal[r * NSCAL + S_ACTIVE] != 0.0;
+      if (!any || it >= maxit) break;
+      if ((rc = cgcg_iteration(pt, nr, it, x, w.r, w.z, w.p, sv, w.q, w.t0, w.t1, st))) return rc;
+    }
+  } else {
+  launch_copy(w.p, w.z, tot, st);
   // device-side control: enqueue the iterations the last solve of nr systems
   // needed without reading the flags in between
   const bool dev = pt->cg_ctrl == GA_CG_DEVICE && pt->dim == 3 && pt->pinv_mode == GA_PINV_AUTO &&
@@ -320,6 +395,7 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
     launch_cg_beta(nr, partA, pt->scal, st);
     launch_cg_p(nr, w.p, w.z, pt->scal, n, st);
     if (check_launch(0, "pcg iteration")) return GA_EDEVICE;
+  }
   }
   bool ok = true;
   for (int r = 0; r < nr; ++r) {
@@ -821,6 +897,8 @@ int ga_destroy_patch(ga_patch* pt) {
   if (pt->s) hipFree(pt->s);
   if (pt->work) hipFree(pt->work);
   if (pt->red) hipFree(pt->red);
+  if (pt->cgf_part) hipFree(pt->cgf_part);
+  if (pt->cgf_cnt) hipFree(pt->cgf_cnt);
   if (pt->scal) hipFree(pt->scal);
   if (pt->flags) hipFree(pt->flags);
   if (pt->host_scal) hipHostFree(pt->host_scal);
@@ -921,7 +999,10 @@ int ga_patch_tuned_layers(const ga_patch* pt, int* ze_mass, int* ze_stiff) {
 
 int ga_patch_set_cg(ga_patch* pt, int mode) {
   if (!pt) { set_error("null patch"); return GA_EINVAL; }
-  if (mode != GA_CG_HOST && mode != GA_CG_DEVICE) { set_error("bad PCG control mode"); return GA_EINVAL; }
+  if (mode != GA_CG_HOST && mode != GA_CG_DEVICE && mode != GA_CG_FUSED) {
+    set_error("bad PCG control mode");
+    return GA_EINVAL;
+  }
   pt->cg_ctrl = mode;
   return GA_OK;
 }

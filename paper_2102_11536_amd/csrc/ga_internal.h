@@ -149,6 +149,8 @@ struct ga_patch {
   double* red = nullptr;      // reduction partials
   double* scal = nullptr;     // device scalars
   int* flags = nullptr;       // device flags
+  double* cgf_part = nullptr;  // fused-reduction partials of the single-reduction PCG
+  unsigned* cgf_cnt = nullptr; // and its last-workgroup counters
   double* host_scal = nullptr;  // pinned host mirror of scalars
   // solve statistics
   long long n_solves = 0, n_guessed = 0, n_fallbacks = 0;

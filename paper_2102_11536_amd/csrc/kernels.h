@@ -10,6 +10,64 @@ constexpr int RED_BLOCKS = 256;   // partial sums per reduction
 constexpr int NSCAL = 12;         // device scalars per right-hand side
 enum { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_BETA = 3, S_BN2 = 4, S_ACTIVE = 5, S_ITERS = 6, S_TOL2 = 7,
        S_FALLBACK = 8, S_RZ0 = 9 };
+// single-reduction PCG (Chronopoulos-Gear): alpha and gamma of the previous update,
+// in two slots each, alternated by the parity of the iteration (the update kernel
+// reads one and its first workgroup writes the other)
+enum { S_ALPHA0 = 2, S_ALPHA1 = 3, S_GPREV0 = 1, S_GPREV1 = 11 };
+
+// Reductions fused into a producing kernel: every workgroup writes its partial sum
+// part[rhs * pstride + wg]; the last workgroup to finish (counted in cnt[slot]) sums
+// them in workgroup order (the same order every run) and updates the scalars.
+struct CgFuse {
+  double* part;
+  unsigned* cnt;
+  double* scal;       // CG scalars of right-hand side 0 of the launch
+  long long pstride;  // partial slots per right-hand side
+};
+constexpr long long CGF_PSTRIDE = 65536;  // partial slots per right-hand side
+constexpr int CGF_MAXRHS = 16;
+
+// after z = P^{-1} r: gamma = r^T z and the stopping test of the solve
+__device__ inline void cgcg_gamma(double* s, double gamma) {
+  if (s[S_ACTIVE] == 0.0) return;
+  s[S_RZ] = gamma;
+  if (!(gamma > s[S_TOL2] * s[S_BN2])) s[S_ACTIVE] = 0.0;
+}
+// the last-workgroup reduction of a fused dot: called by every thread of the
+// workgroup after its partials part[r * pstride + wg] (r < nr) are written by thread
+// 0; `done` (an LDS int) and `sh` (LDS, >= blockDim.x / 64 doubles) are scratch.
+// Returns in the last workgroup, with the totals applied by `apply(r, total)` on
+// thread 0.
+template <class F>
+__device__ inline void cgf_finish(const CgFuse& f, unsigned slot, unsigned nwg, int nr, int* done,
+                                  double* sh, F apply) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(&f.cnt[slot], 1u);
+    *done = prev == nwg - 1;
+  }
+  __syncthreads();
+  if (!*done) return;
+  __threadfence();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int r = 0; r < nr; ++r) {
+    double v = 0.0;
+    for (unsigned i = threadIdx.x; i < nwg; i += blockDim.x)
+      v += __builtin_nontemporal_load(&f.part[(long long)r * f.pstride + i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < nw; ++i) t += sh[i];
+      apply(r, t);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) f.cnt[slot] = 0u;   // ready for the next launch
+}
 
 struct StatePtrs { double* L[12]; };
 struct HistPtrs { const double* H[16]; };  // [h * 4 + j]: history slot h (newest first), stage j
@@ -106,6 +164,20 @@ int launch_pinv_mfma_f64(int dim, const int* mf, int nr, const double* r, double
                          double* t1, const void* const* apk, const double* s, long long n,
                          hipStream_t st);
 // banded-Cholesky preconditioner (0 launched, 1 does not fit the LDS staging, -1 error)
+// FP64 banded preconditioner whose last pass also sums r^T z per workgroup and, in
+// the last workgroup per right-hand side, applies cgcg_gamma (3-D patches)
+int launch_pinv_band_cgcg(int p, const int* mf, int nr, const double* r, double* z, double* t0,
+                          double* t1, const double* const* cb, const double* s, long long n_free,
+                          hipStream_t st, const double* gate, const CgFuse& f);
+// Chronopoulos-Gear update of the active right-hand sides at iteration `it`: every
+// workgroup sums the partials part_delta (RED_BLOCKS per right-hand side) of
+// delta = z^T w, w = M z, and takes beta = gamma / gamma_prev, alpha = gamma /
+// (delta - beta gamma / alpha_prev) (alpha = gamma / delta, p = z, s = w at it = 0);
+// then p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s, w = 0.  Its first
+// workgroup stores alpha and gamma for the next iteration and counts the iteration.
+void launch_cgcg_update(int nr, int it, double* x, double* r, double* p, double* s, double* w,
+                        const double* z, const double* part_delta, double* scal, size_t n,
+                        hipStream_t st);
 template <typename S>
 int launch_pinv_band(int dim, int p, const int* mf, int nr, const S* r, S* z, S* t0, S* t1,
                      const S* const* cb, const S* s, long long n_free, hipStream_t st,

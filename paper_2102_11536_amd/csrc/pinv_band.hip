@@ -30,7 +30,8 @@ namespace {
 // and the only dependent chain is one multiply-add and one multiply per step.
 template <int P, int U, typename S>
 __device__ __forceinline__ void band_solve(const S* src, S* dst, long long stride, int n,
-                                           const S* cb, const S* so) {
+                                           const S* cb, const S* so, const S* rd = nullptr,
+                                           S* rdot = nullptr) {
   constexpr int P1 = P + 1;
   S w[P];
 #pragma unroll
@@ -78,6 +79,11 @@ __device__ __forceinline__ void band_solve(const S* src, S* dst, long long strid
 #pragma unroll
       for (int u = 0; u < U; ++u) sc[u] = so[max(i0 - u, 0) * stride];
     }
+    S rv[U];
+    if (rd) {   // r at the same entries: sum r * z of the final values on the fly
+#pragma unroll
+      for (int u = 0; u < U; ++u) rv[u] = rd[max(i0 - u, 0) * stride];
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (i0 - u >= 0) {
@@ -86,6 +92,7 @@ __device__ __forceinline__ void band_solve(const S* src, S* dst, long long strid
         for (int d = P; d >= 1; --d) acc -= c[u][d] * w[d - 1];
         const S x = acc * c[u][0];
         vv[u] = x * sc[u];
+        if (rd) *rdot += rv[u] * vv[u];
 #pragma unroll
         for (int d = P - 1; d > 0; --d) w[d] = w[d - 1];
         w[0] = x;
@@ -193,6 +200,38 @@ band_col_k(const S* __restrict__ in, S* __restrict__ out, const S* __restrict__ 
                        stride, L, ct, so ? so + o : (const S*)nullptr);
 }
 
+// the z pass of the single-reduction PCG: as band_col_k (FP64, output scaling so),
+// then each thread sums r * z over its line, and the workgroup partials of each
+// right-hand side (blockIdx.y) are reduced by its last workgroup into gamma = r^T z
+template <int P>
+__global__ void __launch_bounds__(CT)
+band_col_cg_k(const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ cb,
+              long long nlines, long long stride, int L, long long n_free,
+              const double* __restrict__ so, const double* __restrict__ gate,
+              const double* __restrict__ rr, CgFuse f) {
+  if (gate && gate[(size_t)blockIdx.y * NSCAL + S_ACTIVE] == 0.0) return;
+  extern __shared__ unsigned char smem_raw[];
+  double* ct = reinterpret_cast<double*>(smem_raw);   // factor table, (L + P) x (P + 1)
+  __shared__ double sh[1];
+  __shared__ int done;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < (L + P) * (P + 1); e += CT) ct[e] = cb[e];
+  __syncthreads();
+  const long long c = (long long)blockIdx.x * CT + lane;
+  double acc = 0.0;
+  if (c < nlines) {
+    const size_t base = (size_t)blockIdx.y * n_free + c;   // lines of the z axis: per_plane = nlines
+    band_solve<P, 16, double>(in + base, out + base, stride, L, ct, so + c, rr + base, &acc);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) f.part[(long long)blockIdx.y * f.pstride + blockIdx.x] = acc;
+  CgFuse fy = f;
+  fy.part = f.part + (long long)blockIdx.y * f.pstride;
+  cgf_finish(fy, blockIdx.y, gridDim.x, 1, &done, sh,
+             [&](int, double total) { cgcg_gamma(f.scal + (size_t)blockIdx.y * NSCAL, total); });
+}
+
 constexpr size_t LDS_MAX_BYTES = 152 * 1024;
 
 template <int P, typename S>
@@ -254,6 +293,54 @@ bool pinv_band_fits(int dim, int p, const int* mf, size_t elem) {
   const size_t row_bytes = ((size_t)NL * (L0 | 1) + (size_t)(L0 + p) * (p + 1)) * elem;
   const size_t col_bytes = (size_t)(std::max(L1, L2) + p) * (p + 1) * elem;
   return row_bytes <= LDS_MAX_BYTES && col_bytes <= LDS_MAX_BYTES;
+}
+
+namespace {
+template <int P>
+int band_cgcg_p(const int* mf, int nr, const double* r, double* z, double* t0, double* t1,
+                const double* const* cb, const double* s, long long n_free, hipStream_t st,
+                const double* gate, const CgFuse& f) {
+  const long long L0 = mf[0], L1 = mf[1], L2 = mf[2];
+  const size_t row_bytes = ((size_t)NL * (L0 | 1) + (size_t)(L0 + P) * (P + 1)) * sizeof(double);
+  const size_t col_bytes = (size_t)(std::max(L1, L2) + P) * (P + 1) * sizeof(double);
+  if (row_bytes > LDS_MAX_BYTES || col_bytes > LDS_MAX_BYTES) return 1;
+  const long long nz = L0 * L1;
+  if ((nz + CT - 1) / CT > f.pstride || nr > CGF_MAXRHS) return 1;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&band_row_k<P, double>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX_BYTES);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&band_col_k<P, double>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX_BYTES);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&band_col_cg_k<P>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX_BYTES);
+    attr = true;
+  }
+  const long long rows = L1 * L2;
+  hipLaunchKernelGGL((band_row_k<P, double>), dim3((unsigned)((rows + NL - 1) / NL), nr), dim3(WT),
+                     row_bytes, st, r, t1, cb[0], (int)L0, rows, n_free, s, (const double*)nullptr,
+                     gate);
+  const long long ny = L0 * L2;
+  hipLaunchKernelGGL((band_col_k<P, double>), dim3((unsigned)((ny + CT - 1) / CT), nr), dim3(CT),
+                     (size_t)(L1 + P) * (P + 1) * sizeof(double), st, t1, t0, cb[1], ny, L0, L0 * L1,
+                     L0, (int)L1, n_free, (const double*)nullptr, gate);
+  hipLaunchKernelGGL((band_col_cg_k<P>), dim3((unsigned)((nz + CT - 1) / CT), nr), dim3(CT),
+                     (size_t)(L2 + P) * (P + 1) * sizeof(double), st, t0, z, cb[2], nz, nz, (int)L2,
+                     n_free, s, gate, r, f);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+}  // namespace
+
+int launch_pinv_band_cgcg(int p, const int* mf, int nr, const double* r, double* z, double* t0,
+                          double* t1, const double* const* cb, const double* s, long long n_free,
+                          hipStream_t st, const double* gate, const CgFuse& f) {
+  switch (p) {
+    case 1: return band_cgcg_p<1>(mf, nr, r, z, t0, t1, cb, s, n_free, st, gate, f);
+    case 2: return band_cgcg_p<2>(mf, nr, r, z, t0, t1, cb, s, n_free, st, gate, f);
+    case 3: return band_cgcg_p<3>(mf, nr, r, z, t0, t1, cb, s, n_free, st, gate, f);
+    case 4: return band_cgcg_p<4>(mf, nr, r, z, t0, t1, cb, s, n_free, st, gate, f);
+  }
+  return 1;
 }
 
 template int launch_pinv_band<double>(int, int, const int*, int, const double*, double*, double*,

@@ -152,6 +152,20 @@ dot_partial_k(const double* __restrict__ a, const double* __restrict__ b, size_t
   if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = s;
 }
 
+// the total of part[r][0 .. RED_BLOCKS-1] on every thread of the block (the same
+// additions in the same order on each)
+__device__ double sum_part_all(const double* part, int r, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += VB) v += part[(size_t)r * RED_BLOCKS + i];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < VB / 64; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
 __device__ double sum_part(const double* part, int r, double* sh) {
   double v = 0.0;
   for (int i = threadIdx.x; i < RED_BLOCKS; i += VB) v += part[(size_t)r * RED_BLOCKS + i];
@@ -255,6 +269,41 @@ __global__ void cg_xr_k(double* __restrict__ x, double* __restrict__ r,
        i += (size_t)gridDim.x * blockDim.x) {
     x[off + i] += a * p[off + i];
     r[off + i] -= a * q[off + i];
+  }
+}
+
+// single-reduction PCG update of the active right-hand sides (see launch_cgcg_update)
+__global__ void __launch_bounds__(VB)
+cgcg_update_k(int it, double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
+              double* __restrict__ s, double* __restrict__ w, const double* __restrict__ z,
+              const double* __restrict__ part, double* __restrict__ scal, size_t n) {
+  __shared__ double sh[VB / 64];
+  const int rr = blockIdx.y;
+  double* sc = scal + (size_t)rr * NSCAL;
+  if (sc[S_ACTIVE] == 0.0) return;
+  const double delta = sum_part_all(part, rr, sh);   // the same sum, in the same order, everywhere
+  const int cur = it & 1, nxt = cur ^ 1;
+  const double g = sc[S_RZ];
+  const bool first = it == 0;
+  const double beta = first ? 0.0 : g / sc[cur ? S_GPREV1 : S_GPREV0];
+  const double a = first ? g / delta : g / (delta - beta * g / sc[cur ? S_ALPHA1 : S_ALPHA0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[nxt ? S_ALPHA1 : S_ALPHA0] = a;
+    sc[nxt ? S_GPREV1 : S_GPREV0] = g;
+    sc[S_ITERS] += 1.0;
+  }
+  const size_t off = (size_t)rr * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = off + i;
+    const double zi = z[k], wi = w[k];
+    const double pi = first ? zi : zi + beta * p[k];
+    const double si = first ? wi : wi + beta * s[k];
+    p[k] = pi;
+    s[k] = si;
+    x[k] += a * pi;
+    r[k] -= a * si;
+    w[k] = 0.0;
   }
 }
 
@@ -510,6 +559,13 @@ void launch_cg_xr(int nr, double* x, double* r, const double* p, const double* q
                   const double* scal, size_t n, hipStream_t st) {
   unsigned b = nblocks(n) > 2048 ? 2048 : nblocks(n);
   hipLaunchKernelGGL(cg_xr_k, dim3(b, nr), dim3(VB), 0, st, x, r, p, q, scal, n);
+}
+void launch_cgcg_update(int nr, int it, double* x, double* r, double* p, double* s, double* w,
+                        const double* z, const double* part_delta, double* scal, size_t n,
+                        hipStream_t st) {
+  unsigned b = nblocks(n) > 2048 ? 2048 : nblocks(n);
+  hipLaunchKernelGGL(cgcg_update_k, dim3(b, nr), dim3(VB), 0, st, it, x, r, p, s, w, z, part_delta,
+                     scal, n);
 }
 void launch_cg_p(int nr, double* p, const double* z, const double* scal, size_t n,
                  hipStream_t st) {

@@ -16,7 +16,7 @@ GA_GUESS_ZERO, GA_GUESS_PREV, GA_GUESS_EXTRAP, GA_GUESS_LEARNED = 0, 1, 2, 3
 GA_GNET_NPARAM = 32033
 GA_FP64, GA_FP32, GA_BF16 = 0, 1, 2
 GA_PINV_AUTO, GA_PINV_DENSE, GA_PINV_MFMA = 0, 1, 2
-GA_CG_HOST, GA_CG_DEVICE = 0, 1
+GA_CG_HOST, GA_CG_DEVICE, GA_CG_FUSED = 0, 1, 2
 
 EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_info", "ga_diag_M", "ga_apply_MK",
            "ga_apply_Pinv", "ga_apply_Pinv_noalloc", "ga_mass_solve", "ga_lambda_max", "ga_stability_limit",

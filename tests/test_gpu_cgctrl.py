@@ -125,3 +125,75 @@ def test_device_control_falls_back_with_dense_preconditioner():
     assert ga.ga_cg_stats(pt)[0] == 0      # host control was used
     with pytest.raises(ga.GAError):
         ga.ga_patch_set_cg(pt, 5)
+
+
+# ---- single-reduction (Chronopoulos-Gear) PCG, reductions fused into the kernels ----
+
+@pytest.mark.parametrize("n,p", [(6, 3), ((7, 5, 6), 2), (5, 4), ((9, 4, 3), 1)])
+def test_fused_single_reduction_matches_host_and_cholesky(n, p):
+    # the same stopping test and, in exact arithmetic, the same iterates as the
+    # classic recurrence: iteration counts within one of the host-controlled PCG
+    # (a residual right at the tolerance may land on either side), solutions
+    # against Cholesky, through changing schedules as in the device-control test
+    _say("cg fused", n, p)
+    pr = OracleProblem(3, n, p, seed=21)
+    host = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    fus = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    ga.ga_patch_set_cg(host, ga.GA_CG_HOST)
+    ga.ga_patch_set_cg(fus, ga.GA_CG_FUSED)
+    rng = np.random.default_rng(7)
+    smooth = pr.M @ workloads.grf(n, p, seed=4)
+    seq = [(rng.standard_normal((2, host.n_free)), 1e-3),
+           (rng.standard_normal((2, host.n_free)), 1e-12),
+           (rng.standard_normal((1, host.n_free)), 1e-12),
+           (rng.standard_normal((2, host.n_free)), 1e-4),
+           (np.stack([smooth, rng.standard_normal(host.n_free), smooth]), 1e-12),
+           (np.stack([smooth, smooth, rng.standard_normal(host.n_free), smooth]), 1e-10)]
+    for i, (B, rtol) in enumerate(seq):
+        xh, ih, rh = _solve(host, B, rtol)
+        xf, itf, rf = _solve(fus, B, rtol)
+        _say("  solve", i, "rtol", rtol, "host its", ih, "fused its", itf, "relres", rf)
+        assert max(abs(a - b) for a, b in zip(ih, itf)) <= 1, (i, ih, itf)
+        for r in range(B.shape[0]):
+            assert rf[r] <= rtol
+            if rtol <= 1e-10:
+                assert rel(xf[r], pr.chol.solve(B[r])) < 1e-9
+                assert rel(xf[r], xh[r]) < 1e-9
+    spec, checks = ga.ga_cg_stats(fus)
+    assert spec > 0
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_fused_single_reduction_steps_match_oracle(k):
+    n, p = 5, 3
+    _say("cg fused steps", k)
+    pr = OracleProblem(3, n, p, seed=44)
+    tau = pr.tau()
+    U0 = workloads.grf(n, p, seed=3)
+    ora = pr.run(U0, 0 * U0, k, 0.5, tau, 8)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    ga.ga_patch_set_cg(pt, ga.GA_CG_FUSED)
+    integ = ga.ga_integrator_create(pt, k, 0.5, tau, rtol=1e-12)
+    state = [torch.zeros(pt.n_free, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+    ga.ga_init_state(integ, _t(U0), _t(0 * U0), state)
+    ga.ga_step(integ, state, 8)
+    M = pr.M
+    for s in range(3 * k):
+        o = ora[8][s - 2]
+        d = _np(state[s]) - o
+        assert np.sqrt(d @ (M @ d)) <= 1e-10 * max(np.sqrt(o @ (M @ o)), 1e-300), s
+
+
+def test_fused_single_reduction_degenerate():
+    # zero right-hand sides converge in zero iterations; a guess worse than zero
+    # falls back; the solution of a guessed solve equals Cholesky
+    pr = OracleProblem(3, 5, 3, seed=2)
+    pt = ga.ga_setup_patch(3, 5, 3, pr.ctrl)
+    ga.ga_patch_set_cg(pt, ga.GA_CG_FUSED)
+    B = np.stack([np.zeros(pt.n_free), np.random.default_rng(3).standard_normal(pt.n_free)])
+    for _ in range(2):
+        x = torch.full((2 * pt.n_free,), 7.0, dtype=torch.float64, device=DEV)
+        its, relres, _ = ga.ga_mass_solve(pt, _t(B.ravel()), x, nrhs=2, rtol=1e-12)
+        got = _np(x).reshape(2, -1)
+        assert its[0] == 0 and np.all(got[0] == 0.0), its
+        assert rel(got[1], pr.chol.solve(B[1])) < 1e-10
