@@ -184,8 +184,8 @@ int ga_patch_set_pinv(ga_patch* patch, int mode);
  *                 needed (the right-hand sides expected to be active share
  *                 one operator launch, the others get gated launches of their
  *                 own), then reads the flags once and continues per iteration
- *                 only if a system is still active.  3-D patches with the
- *                 banded preconditioner; otherwise the host control is used.
+ *                 only if a system is still active.  2-D and 3-D patches with
+ *                 the banded preconditioner; otherwise the host control is used.
  * ga_cg_stats: iterations enqueued ahead so far and host reads of the flags.
  */
 /*

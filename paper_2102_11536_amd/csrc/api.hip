@@ -222,15 +222,15 @@ int gated_iteration(ga_patch* pt, int nr, int it, double* x, const SolveBufs& w,
   {
     ProfScope prof(0, st);
     int rc = 0;
-    for (int r0 = a; r0 < b && !rc; r0 += MAX_NR) {
-      const int c = std::min(MAX_NR, b - r0);
-      rc = launch_op3d(0, c, pt, w.p + (size_t)r0 * n, w.q + (size_t)r0 * n, 1.0, st,
-                       gate + (size_t)r0 * NSCAL);
-    }
+    auto mass = [&](int r0, int c) {
+      return pt->dim == 3 ? launch_op3d(0, c, pt, w.p + (size_t)r0 * n, w.q + (size_t)r0 * n, 1.0,
+                                        st, gate + (size_t)r0 * NSCAL)
+                          : launch_op2d(0, c, pt, w.p + (size_t)r0 * n, w.q + (size_t)r0 * n, 1.0,
+                                        st, gate + (size_t)r0 * NSCAL);
+    };
+    for (int r0 = a; r0 < b && !rc; r0 += MAX_NR) rc = mass(r0, std::min(MAX_NR, b - r0));
     for (int r = 0; r < nr && !rc; ++r)
-      if (r < a || r >= b)
-        rc = launch_op3d(0, 1, pt, w.p + (size_t)r * n, w.q + (size_t)r * n, 1.0, st,
-                         gate + (size_t)r * NSCAL);
+      if (r < a || r >= b) rc = mass(r, 1);
     if (check_launch(rc, "gated mass apply")) return GA_EDEVICE;
   }
   launch_dot_partial(nr, w.p, w.q, n, partA, st, gate);
@@ -363,8 +363,8 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
   launch_copy(w.p, w.z, tot, st);
   // device-side control: enqueue the iterations the last solve of nr systems
   // needed without reading the flags in between
-  const bool dev = pt->cg_ctrl == GA_CG_DEVICE && pt->dim == 3 && pt->pinv_mode == GA_PINV_AUTO &&
-                   nr <= 16 && pt->hint_nr == nr && pinv_band_fits(3, pt->p, pt->mf, sizeof(double));
+  const bool dev = pt->cg_ctrl != GA_CG_HOST && pt->pinv_mode == GA_PINV_AUTO && nr <= 16 &&
+                   pt->hint_nr == nr && pinv_band_fits(pt->dim, pt->p, pt->mf, sizeof(double));
   if (dev) {
     int hmax = 0;
     for (int r = 0; r < nr; ++r) hmax = std::max(hmax, pt->hint[r]);

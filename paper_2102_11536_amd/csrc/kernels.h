@@ -114,7 +114,7 @@ int launch_op3d_lowp(int mode, int nr, const ga_patch* pt, const float* x, float
 int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
                  hipStream_t st);
 int launch_op2d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
-                hipStream_t st);
+                hipStream_t st, const double* gate = nullptr);
 int launch_geo2d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
                  hipStream_t st);
 

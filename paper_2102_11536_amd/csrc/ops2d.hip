@@ -34,7 +34,14 @@ __global__ void __launch_bounds__(Tile2<P>::QT)
 op2d_kernel(const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ fac,
             const double* __restrict__ tB0, const double* __restrict__ tB1,
             const double* __restrict__ tD0, const double* __restrict__ tD1, Geo2 g,
-            long long n_free, double alpha) {
+            long long n_free, double alpha, const double* __restrict__ gate) {
+  // device-side control: nothing to do once all systems of the launch have converged
+  if (gate) {
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) any |= gate[r * NSCAL + S_ACTIVE] != 0.0;
+    if (!any) return;
+  }
   using T = Tile2<P>;
   constexpr int Q = T::Q, QT = T::QT, NB = T::NB, TE = T::TE;
   __shared__ double sB[2][T::TAB];
@@ -207,7 +214,7 @@ geo2d_kernel(const double* __restrict__ ctrl, const double* __restrict__ tB0,
 
 template <int P>
 static int launch_op2d_p(int mode, int nr, const ga_patch* pt, const double* x, double* y,
-                         double alpha, hipStream_t st) {
+                         double alpha, hipStream_t st, const double* gate) {
   Geo2 g;
   for (int a = 0; a < 2; ++a) { g.n[a] = pt->n[a]; g.m[a] = pt->m[a]; g.mf[a] = pt->mf[a]; g.nt[a] = pt->nt[a]; }
   const double* const* B = (mode == 2) ? pt->tabB2 : pt->tabB;
@@ -215,7 +222,7 @@ static int launch_op2d_p(int mode, int nr, const ga_patch* pt, const double* x, 
   dim3 grid((unsigned)pt->n_tiles), block(Tile2<P>::QT);
 #define GA_OP2(MODE, NRV)                                                                     \
   hipLaunchKernelGGL((op2d_kernel<P, MODE, NRV>), grid, block, 0, st, x, y, fac, B[0], B[1],   \
-                     pt->tabD[0], pt->tabD[1], g, pt->n_free, alpha)
+                     pt->tabD[0], pt->tabD[1], g, pt->n_free, alpha, gate)
   if (mode == 0) {
     if (nr == 1) GA_OP2(0, 1); else if (nr == 2) GA_OP2(0, 2); else GA_OP2(0, 3);
   } else if (mode == 1) {
@@ -228,12 +235,12 @@ static int launch_op2d_p(int mode, int nr, const ga_patch* pt, const double* x, 
 }
 
 int launch_op2d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
-                hipStream_t st) {
+                hipStream_t st, const double* gate) {
   switch (pt->p) {
-    case 1: return launch_op2d_p<1>(mode, nr, pt, x, y, alpha, st);
-    case 2: return launch_op2d_p<2>(mode, nr, pt, x, y, alpha, st);
-    case 3: return launch_op2d_p<3>(mode, nr, pt, x, y, alpha, st);
-    case 4: return launch_op2d_p<4>(mode, nr, pt, x, y, alpha, st);
+    case 1: return launch_op2d_p<1>(mode, nr, pt, x, y, alpha, st, gate);
+    case 2: return launch_op2d_p<2>(mode, nr, pt, x, y, alpha, st, gate);
+    case 3: return launch_op2d_p<3>(mode, nr, pt, x, y, alpha, st, gate);
+    case 4: return launch_op2d_p<4>(mode, nr, pt, x, y, alpha, st, gate);
   }
   return -1;
 }

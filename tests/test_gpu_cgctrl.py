@@ -197,3 +197,28 @@ def test_fused_single_reduction_degenerate():
         got = _np(x).reshape(2, -1)
         assert its[0] == 0 and np.all(got[0] == 0.0), its
         assert rel(got[1], pr.chol.solve(B[1])) < 1e-10
+
+
+@pytest.mark.parametrize("n,p", [(16, 2), ((11, 7), 3)])
+def test_device_control_2d(n, p):
+    # 2-D patches: gated 2-D operator launches and banded preconditioner passes; the
+    # same iteration counts and solutions as host control, fewer host reads
+    _say("cg control 2-D", n, p)
+    pr = OracleProblem(2, n, p, seed=6)
+    host = ga.ga_setup_patch(2, n, p, pr.ctrl)
+    dev = ga.ga_setup_patch(2, n, p, pr.ctrl)
+    ga.ga_patch_set_cg(host, ga.GA_CG_HOST)
+    ga.ga_patch_set_cg(dev, ga.GA_CG_DEVICE)
+    rng = np.random.default_rng(9)
+    for i, rtol in enumerate([1e-12, 1e-12, 1e-6, 1e-12]):
+        B = rng.standard_normal((2, host.n_free))
+        xh, ih, _ = _solve(host, B, rtol)
+        xd, idv, rd = _solve(dev, B, rtol)
+        assert ih == idv, (i, ih, idv)
+        for r in range(2):
+            assert rel(xd[r], xh[r]) < ATOMIC_ORDER_BAR
+            assert rd[r] <= rtol
+            if rtol <= 1e-10:
+                assert rel(xd[r], pr.chol.solve(B[r])) < 1e-9
+    spec, checks = ga.ga_cg_stats(dev)
+    assert spec > 0 and checks < ga.ga_cg_stats(host)[1]
