@@ -34,6 +34,7 @@ struct OpGroup {
   int p = 0, mode = 0;
   std::vector<const ga_patch*> pts;
   std::vector<long long> offs;
+  std::vector<int> sys;       // the patches' indices in the batch
   int ze_override = 0;        // 0: each patch's default
   int nwg = 0;                // 0: one workgroup per tile
   bool f32 = false;           // FP32 factors (mass only)
@@ -83,6 +84,7 @@ int upload_op_group(OpGroup& g) {
     const int ze = g.ze_override > 0 ? std::min(g.ze_override, g.pts[i]->n[2])
                                      : op3d_default_ze(g.mode, g.pts[i], g.f32);
     OpGroupEntry e = op3d_group_entry(g.mode, g.pts[i], ze, g.offs[i], tile, g.f32);
+    e.sys = i < g.sys.size() ? g.sys[i] : 0;
     tile += e.ntiles;
     h.push_back(e);
   }
@@ -97,14 +99,15 @@ int upload_op_group(OpGroup& g) {
 }
 
 int op_batch(ga_batch* b, int mode, int nr, double alpha, const double* x, double* y,
-             hipStream_t st) {
+             hipStream_t st, const double* gate = nullptr) {
   for (OpGroup& g : b->ops[mode]) {
     const int cmax = op3d_max_nr(g.p, mode);
     for (int r0 = 0; r0 < nr; r0 += cmax) {
       const int c = std::min(cmax, nr - r0);
       const int nwg = g.nwg > 0 ? std::min(g.nwg, g.total) : g.total;
       if (launch_op3d_group<double>(g.p, mode, c, g.ents, g.nent, x + (size_t)r0 * b->N,
-                                    y + (size_t)r0 * b->N, b->N, alpha, g.total, nwg, st))
+                                    y + (size_t)r0 * b->N, b->N, alpha, g.total, nwg, st,
+                                    BatchGate{gate, b->R, r0}))
         return check_launch(-1, "batched operator");
     }
   }
@@ -137,6 +140,7 @@ int build_pgroups(ga_batch* b, int nr, bool f32) {
       const long long m0 = pt->mf[0], m1 = pt->mf[1], m2 = pt->mf[2];
       PinvEntry e{};
       e.off = b->off[r];
+      e.sys = r;
       e.si = e.so = nullptr;
       long long nb = 0;
       const void* sc = f32 ? (const void*)pt->s32 : (const void*)pt->s;
@@ -194,13 +198,14 @@ int build_pgroups(ga_batch* b, int nr, bool f32) {
 
 // z = P^{-1} r for every patch (three passes, scaling folded into the first and last)
 int pinv_batch(ga_batch* b, int nr, const double* r, double* z, double* t0, double* t1,
-               hipStream_t st) {
+               hipStream_t st, const double* gate = nullptr) {
   const double* in[3] = {r, t1, t0};
   double* out[3] = {t1, t0, z};
   for (int pass = 0; pass < 3; ++pass)
     for (const PGroup& g : b->pgroups)
       if (g.nr == nr && g.pass == pass && !g.f32)
-        launch_pinv_group<double>(pass, g.ra, g.ents, g.nent, g.nblk, nr, in[pass], out[pass], b->N, st);
+        launch_pinv_group<double>(pass, g.ra, g.ents, g.nent, g.nblk, nr, in[pass], out[pass], b->N, st,
+                                  BatchGate{gate, b->R, 0});
   return check_launch(0, "batched preconditioner");
 }
 
@@ -231,12 +236,15 @@ int pcg_iteration(ga_batch* b, int nr, double* x, hipStream_t st) {
   Bufs w = bufs(b);
   double* partA = b->red;
   launch_fill(w.q, 0.0, (size_t)nr * b->N, st);
-  int rc = op_batch(b, 0, nr, 1.0, w.p, w.q, st);
+  // the operator and preconditioner launches skip the patches whose systems have all
+  // converged (device-side control: the iterations enqueued past convergence cost
+  // little)
+  int rc = op_batch(b, 0, nr, 1.0, w.p, w.q, st, b->scal);
   if (rc) return rc;
   launch_dot_partial_seg(ns, w.p, w.q, b->seg, partA, st);
   launch_cg_alpha(ns, partA, b->scal, st);
   launch_cg_xr_seg(ns, x, w.r, w.p, w.q, b->scal, b->seg, b->maxlen, st);
-  if ((rc = pinv_batch(b, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+  if ((rc = pinv_batch(b, nr, w.r, w.z, w.t0, w.t1, st, b->scal))) return rc;
   launch_dot_partial_seg(ns, w.r, w.z, b->seg, partA, st);
   launch_cg_beta(ns, partA, b->scal, st);
   launch_cg_p_seg(ns, w.p, w.z, b->scal, b->seg, b->maxlen, st);
@@ -329,14 +337,13 @@ int solve_batch64(ga_batch* b, int nr, const double* rhs, double* x, bool graph,
   if (check_launch(0, "batched pcg start")) return GA_EDEVICE;
   const bool use_graph = graph && nr == b->k && x == b->X;
   if (use_graph && !b->exec && (rc = capture_iteration(b, false))) return rc;
-  // iterations run before the first read of the convergence flags: one fewer
-  // than the fewest the previous solve of ns systems needed (an iteration leaves
-  // a converged system unchanged, so no iterate depends on this)
+  // iterations run before the first read of the convergence flags: as many as the
+  // previous solve of ns systems needed (an iteration leaves a converged system
+  // unchanged and its launches skip it, so no iterate depends on this)
   int ahead = 0;
   if (b->hint_nr == ns) {
-    ahead = b->maxit;
-    for (int s = 0; s < ns; ++s) ahead = std::min(ahead, b->hint[s] - 1);
-    ahead = std::max(ahead, 0);
+    for (int s = 0; s < ns; ++s) ahead = std::max(ahead, b->hint[s]);
+    ahead = std::min(ahead, b->maxit);
   }
   for (int it = 0;; ++it) {
     if (it >= ahead) {
@@ -561,6 +568,7 @@ int ga_batch_create(int npatch, ga_patch* const* patches, int k, double rho, dou
         if (patches[r]->p == p) {
           g.pts.push_back(patches[r]);
           g.offs.push_back(b->off[r]);
+          g.sys.push_back(r);
         }
       if (g.pts.empty()) continue;
       b->ops[mode].push_back(g);
@@ -614,6 +622,7 @@ int ga_batch_set_precision(ga_batch* b, int prec, void* stream) {
     g.mode = 0;
     g.pts = g64.pts;
     g.offs = g64.offs;
+    g.sys = g64.sys;
     g.ze_override = g64.ze_override;
     g.nwg = g64.nwg;
     g.f32 = true;

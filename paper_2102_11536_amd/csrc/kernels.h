@@ -87,7 +87,19 @@ struct OpGroupEntry {
   int ze;                     // element layers per tile along z
   long long off;              // offset of the patch's segment in the batched vectors
   int tile0, ntiles;          // the patch's entries in the tile queue
+  int sys;                    // the patch's index in the batch (its systems j * R + sys)
 };
+
+// device-side control of a batched launch: the right-hand side j (j0 + j within the
+// launch) of the patch with index sys is system (j0 + j) * R + sys, whose CG scalars
+// are scal + system * NSCAL; work of systems that have all converged is skipped
+struct BatchGate {
+  const double* scal;   // null: no gating
+  int R, j0;
+};
+__device__ inline bool batch_active(const BatchGate& g, int sys, int j) {
+  return !g.scal || g.scal[(size_t)((g.j0 + j) * g.R + sys) * NSCAL + S_ACTIVE] != 0.0;
+}
 
 int launch_op3d(int mode, int nr, const ga_patch* pt, const double* x, double* y, double alpha,
                 hipStream_t st,
@@ -104,7 +116,8 @@ OpGroupEntry op3d_group_entry(int mode, const ga_patch* pt, int ze, long long of
 // `stride` entries apart, the tile queue split over at most nwg workgroups
 template <typename S>
 int launch_op3d_group(int p, int mode, int nr, const OpGroupEntry* ents, int nent, const S* x,
-                      S* y, long long stride, S alpha, int total, int nwg, hipStream_t st);
+                      S* y, long long stride, S alpha, int total, int nwg, hipStream_t st,
+                      BatchGate gate = BatchGate{nullptr, 0, 0});
 int launch_mass3d_f32(int nr, const ga_patch* pt, const float* x, float* y, float alpha,
                       hipStream_t st);
 // FP32-vector operator apply (mode 0 mass, 1 stiffness) with FP32 (prec GA_FP32:
@@ -148,6 +161,7 @@ struct PinvEntry {
   long long p[4];
   long long off;              // segment offset in the batched vectors
   int blk0;
+  int sys;                    // the patch's index in the batch
 };
 int pinv_ra_class(int L);
 // dense per-axis preconditioner on the matrix cores (pinv_mfma.hip): the packed
@@ -184,7 +198,8 @@ int launch_pinv_band(int dim, int p, const int* mf, int nr, const S* r, S* z, S*
                      const double* gate = nullptr);
 template <typename S>
 void launch_pinv_group(int pass, int ra_class, const PinvEntry* ents, int nent, int nblk, int nr,
-                       const S* in, S* out, long long stride, hipStream_t st);
+                       const S* in, S* out, long long stride, hipStream_t st,
+                       BatchGate gate = BatchGate{nullptr, 0, 0});
 void launch_scaling(double* s, const double* diagM, const double* dh0, const double* dh1,
                     const double* dh2, int mf0, int mf1, int mf2, hipStream_t st);
 void launch_dot_partial(int nr, const double* a, const double* b, size_t n, double* part,

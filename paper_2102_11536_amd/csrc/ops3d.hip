@@ -126,18 +126,19 @@ OpGroupEntry op3d_group_entry(int mode, const ga_patch* pt, int ze, long long of
   d.off = off;
   d.tile0 = tile0;
   d.ntiles = (int)op3d_tiles(mode, pt, ze);
+  d.sys = 0;
   return d;
 }
 
 template <int P, typename S>
 static int group_p(int mode, int nr, const OpGroupEntry* ents, int nent, const S* x, S* y,
-                   long long stride, S alpha, int total, int nwg, hipStream_t st) {
+                   long long stride, S alpha, int total, int nwg, hipStream_t st, BatchGate gate) {
   constexpr int TK = te3_stiff(P), TM = te3_mass(P);
   const int per = (total + nwg - 1) / nwg;
   const dim3 grid((unsigned)((total + per - 1) / per));
 #define GA_OPG(TE, MODE, NRV)                                                                    \
   hipLaunchKernelGGL((op3d_group_kernel<P, TE, MODE, NRV, S>), grid, dim3(Tile3<P, TE>::NT), 0, st, \
-                     ents, nent, x, y, stride, alpha, total, per)
+                     ents, nent, x, y, stride, alpha, total, per, gate)
   if (mode == 0) {
     if (nr == 1) GA_OPG(TM, 0, 1); else if (nr == 2) GA_OPG(TM, 0, 2); else GA_OPG(TM, 0, 3);
   } else {
@@ -153,19 +154,21 @@ static int group_p(int mode, int nr, const OpGroupEntry* ents, int nent, const S
 
 template <typename S>
 int launch_op3d_group(int p, int mode, int nr, const OpGroupEntry* ents, int nent, const S* x,
-                      S* y, long long stride, S alpha, int total, int nwg, hipStream_t st) {
+                      S* y, long long stride, S alpha, int total, int nwg, hipStream_t st,
+                      BatchGate gate) {
   if (nr < 1 || nr > 3 || total < 1 || nwg < 1 || (mode != 0 && mode != 1)) return -1;
   switch (p) {
-    case 2: return group_p<2, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st);
-    case 3: return group_p<3, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st);
-    case 4: return group_p<4, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st);
+    case 2: return group_p<2, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st, gate);
+    case 3: return group_p<3, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st, gate);
+    case 4: return group_p<4, S>(mode, nr, ents, nent, x, y, stride, alpha, total, nwg, st, gate);
   }
   return -1;
 }
 template int launch_op3d_group<double>(int, int, int, const OpGroupEntry*, int, const double*,
-                                       double*, long long, double, int, int, hipStream_t);
+                                       double*, long long, double, int, int, hipStream_t,
+                                       BatchGate);
 template int launch_op3d_group<float>(int, int, int, const OpGroupEntry*, int, const float*,
-                                      float*, long long, float, int, int, hipStream_t);
+                                      float*, long long, float, int, int, hipStream_t, BatchGate);
 
 int launch_geo3d(const ga_patch* pt, const double* ctrl, const double* const* w, int* bad,
                  hipStream_t st) {

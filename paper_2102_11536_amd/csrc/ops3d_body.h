@@ -642,7 +642,8 @@ op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
 template <int P, int TE, int MODE, int NR, typename S>
 __global__ void __launch_bounds__((Tile3<P, TE>::NT), (MODE == 1 ? GA_OP3_WAVES_K : GA_OP3_WAVES_M))
 op3d_group_kernel(const OpGroupEntry* __restrict__ ents, int nent, const S* __restrict__ x,
-                  S* __restrict__ y, long long stride, S alpha, int total, int per_wg) {
+                  S* __restrict__ y, long long stride, S alpha, int total, int per_wg,
+                  BatchGate gate) {
   const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
   for (int i = 0; i < per_wg; ++i) {
     const int t = (int)w * per_wg + i;
@@ -650,6 +651,10 @@ op3d_group_kernel(const OpGroupEntry* __restrict__ ents, int nent, const S* __re
     int e = 0;
     while (e + 1 < nent && t >= ents[e + 1].tile0) ++e;
     const OpGroupEntry& d = ents[e];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) any |= batch_active(gate, d.sys, j);
+    if (!any) continue;   // uniform over the workgroup (one tile per iteration)
     __syncthreads();  // the previous tile has finished with the LDS
     op3d_body<P, TE, MODE, NR, S, op3d_group_backward<P, MODE, NR>(), S>(x + d.off, y + d.off, (const S*)d.fac, d.tB[0], d.tB[1],
                                              d.tB[2], d.tD[0], d.tD[1], d.tD[2], d.g, d.ze, stride,

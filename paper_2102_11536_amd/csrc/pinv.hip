@@ -190,8 +190,9 @@ __device__ __forceinline__ int pinv_entry(const PinvEntry* ents, int nent) {
 template <int RA, typename S>
 __global__ void __launch_bounds__(256)
 pinv_strided_group_k(const PinvEntry* __restrict__ ents, int nent, const S* __restrict__ in,
-                     S* __restrict__ out, long long stride) {
+                     S* __restrict__ out, long long stride, BatchGate gate) {
   const PinvEntry& d = ents[pinv_entry(ents, nent)];
+  if (!batch_active(gate, d.sys, blockIdx.y)) return;   // converged: the output is not used
   const size_t o = (size_t)d.off + (size_t)blockIdx.y * stride;
   strided_body<RA, S>(in + o, out + o, (const S*)d.A, d.L, d.p[0], d.p[1], d.p[2], d.p[3],
                       (const S*)d.si, (const S*)d.so, (long long)(blockIdx.x - d.blk0) * BN);
@@ -200,8 +201,15 @@ pinv_strided_group_k(const PinvEntry* __restrict__ ents, int nent, const S* __re
 template <int RA, typename S>
 __global__ void __launch_bounds__(256)
 pinv_contig_group_k(const PinvEntry* __restrict__ ents, int nent, const S* __restrict__ in,
-                    S* __restrict__ out, long long stride) {
+                    S* __restrict__ out, long long stride, BatchGate gate) {
   const PinvEntry& d = ents[pinv_entry(ents, nent)];
+  if (gate.scal) {   // rows r0 .. r0+63 belong to right-hand sides r0 / rpr .. (r0+63) / rpr
+    const long long r0 = (long long)(blockIdx.x - d.blk0) * 64;
+    const long long last = min(r0 + 63, d.p[0] - 1);
+    bool any = false;
+    for (long long j = r0 / d.p[1]; j <= last / d.p[1]; ++j) any |= batch_active(gate, d.sys, (int)j);
+    if (!any) return;
+  }
   contig_body<RA, S>(in + d.off, out + d.off, (const S*)d.A, d.L, d.p[0], d.p[1], stride,
                      (const S*)d.si, (const S*)d.so, (long long)(blockIdx.x - d.blk0) * 64);
 }
@@ -232,17 +240,17 @@ int pinv_ra_class(int L) { return L <= 64 ? 0 : (L <= 144 ? 1 : 2); }
 
 template <typename S>
 void launch_pinv_group(int pass, int ra_class, const PinvEntry* ents, int nent, int nblk, int nr,
-                       const S* in, S* out, long long stride, hipStream_t st) {
+                       const S* in, S* out, long long stride, hipStream_t st, BatchGate gate) {
   // pass 0 covers every right-hand side through its row index (p[0] = all rows)
   const dim3 grid((unsigned)nblk, pass == 0 ? 1u : (unsigned)nr);
 #define GA_PG(RA)                                                                             \
   do {                                                                                        \
     if (pass == 0)                                                                            \
       hipLaunchKernelGGL((pinv_contig_group_k<RA, S>), grid, dim3(256), 0, st, ents, nent, in,  \
-                         out, stride);                                                        \
+                         out, stride, gate);                                                  \
     else                                                                                      \
       hipLaunchKernelGGL((pinv_strided_group_k<RA, S>), grid, dim3(256), 0, st, ents, nent, in, \
-                         out, stride);                                                        \
+                         out, stride, gate);                                                  \
   } while (0)
   if (ra_class == 0) GA_PG(4);
   else if (ra_class == 1) GA_PG(9);
@@ -250,9 +258,9 @@ void launch_pinv_group(int pass, int ra_class, const PinvEntry* ents, int nent, 
 #undef GA_PG
 }
 template void launch_pinv_group<double>(int, int, const PinvEntry*, int, int, int, const double*,
-                                        double*, long long, hipStream_t);
+                                        double*, long long, hipStream_t, BatchGate);
 template void launch_pinv_group<float>(int, int, const PinvEntry*, int, int, int, const float*,
-                                       float*, long long, hipStream_t);
+                                       float*, long long, hipStream_t, BatchGate);
 
 template <typename S>
 void launch_pinv_strided(const S* in, S* out, const S* A, int L, long long row_stride,
