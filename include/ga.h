@@ -204,6 +204,15 @@ int ga_patch_tuned_layers(const ga_patch* patch, int* ze_mass, int* ze_stiff);
  * stiffness launches of a 3-D patch (1..n_el[2]; 0 = automatic), as the autotuner
  * would: the launch shapes change, the results do not.  GA_EINVAL out of range. */
 int ga_patch_set_layers(ga_patch* patch, int ze_mass, int ze_stiff);
+/* ga_patch_set_deterministic -- on != 0: the operator applies of a 3-D patch add the
+ * contributions of neighbouring tiles in a fixed order, so every apply, solve and
+ * step gives bitwise the same result on every run (an implementation choice: the
+ * default adds shared coefficients with FP64 atomics, whose order changes from run
+ * to run and moves the last bits).  The tiles are split into colour classes whose
+ * tiles share no coefficient (4 classes in x-y for p <= 3, 9 for p = 4, times 2 or
+ * more along z when a column is split into z ranges), launched one after the other:
+ * slower (fewer tiles per launch).  Single-patch launches only (not the batch). */
+int ga_patch_set_deterministic(ga_patch* patch, int on);
 /*   GA_CG_FUSED   single-reduction (Chronopoulos-Gear) PCG under the same device
  *                 control: six launches per iteration instead of eleven: the mass
  *                 apply w = M z, one reduction for z^T w, one kernel that completes

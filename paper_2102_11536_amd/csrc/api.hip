@@ -1082,6 +1082,13 @@ int ga_apply_Pinv(ga_patch* pt, int nrhs, int prec, const double* r, double* z, 
   return check_launch(0, "low-precision preconditioner");
 }
 
+int ga_patch_set_deterministic(ga_patch* pt, int on) {
+  if (!pt) { set_error("null patch"); return GA_EINVAL; }
+  if (pt->dim != 3) { set_error("the deterministic mode is for 3-D patches"); return GA_EINVAL; }
+  pt->deterministic = on != 0;
+  return GA_OK;
+}
+
 int ga_patch_set_layers(ga_patch* pt, int ze_mass, int ze_stiff) {
   if (!pt) { set_error("null patch"); return GA_EINVAL; }
   if (pt->dim != 3) { set_error("launch shapes are for 3-D patches"); return GA_EINVAL; }

@@ -118,6 +118,7 @@ struct ga_patch {
   int ze_op[2] = {0, 0};          // tuned layers for the mass / stiffness kernels (0: automatic)
   int pinv_mode = GA_PINV_AUTO;   // preconditioner algorithm (ga_patch_set_pinv)
   int cg_ctrl = GA_CG_DEVICE;     // PCG control (ga_patch_set_cg)
+  bool deterministic = false;     // colour-ordered operator launches (ga_patch_set_deterministic)
   int hint_nr = 0;                // iterations per right-hand side of the last FP64 solve
   int hint[16] = {0};             //   of hint_nr right-hand sides (speculative schedule)
   long long n_spec = 0, n_checks = 0;   // iterations enqueued ahead, host convergence reads

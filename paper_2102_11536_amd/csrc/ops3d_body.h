@@ -614,6 +614,14 @@ constexpr int op3d_waves() {
                    : ((MODE == 0 && P == 3 && NR == 2 && sizeof(S) == 8) ? 4 : GA_OP3_WAVES_M);
 }
 
+// One colour class of tiles (deterministic mode): tiles (tx, ty, zc) with tx = a (mod
+// cx), ty = b (mod cy), zc = c (mod cz), where the strides are large enough that two
+// tiles of one class share no coefficient; the classes run one launch after the other,
+// so every coefficient receives its contributions in a fixed order.  cx = 0: all tiles.
+struct TileColor {
+  int cx, cy, cz, a, b, c, nx, ny;  // nx, ny: tiles of the class along x and y
+};
+
 template <int P, int TE, int MODE, int NR, typename S, typename F = S>
 __global__ void __launch_bounds__((Tile3<P, TE>::NT), (op3d_waves<P, MODE, NR, S>()))
 op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
@@ -621,7 +629,8 @@ op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
             const double* __restrict__ tB0, const double* __restrict__ tB1,
             const double* __restrict__ tB2, const double* __restrict__ tD0,
             const double* __restrict__ tD1, const double* __restrict__ tD2,
-            Geo3 g, int ze, long long n_free, S alpha, const double* __restrict__ gate) {
+            Geo3 g, int ze, long long n_free, S alpha, const double* __restrict__ gate,
+            TileColor col) {
   // device-side control: with a gate (the CG scalars of the launch's first
   // right-hand side), the launch does nothing once all its systems have converged
   if (gate) {
@@ -630,8 +639,14 @@ op3d_kernel(const S* __restrict__ x, S* __restrict__ y,
     for (int r = 0; r < NR; ++r) any |= gate[r * NSCAL + S_ACTIVE] != 0.0;
     if (!any) return;
   }
+  unsigned lid = xcd_remap(blockIdx.x, gridDim.x);
+  if (col.cx) {
+    const unsigned ix = lid % col.nx, iy = (lid / col.nx) % col.ny, iz = lid / (col.nx * col.ny);
+    const unsigned tx = col.a + col.cx * ix, ty = col.b + col.cy * iy, zc = col.c + col.cz * iz;
+    lid = tx + (unsigned)g.nt[0] * (ty + (unsigned)g.nt[1] * zc);
+  }
   op3d_body<P, TE, MODE, NR, S, op3d_backward<P, MODE, NR, S>(), F>(
-      x, y, fac, tB0, tB1, tB2, tD0, tD1, tD2, g, ze, n_free, alpha, xcd_remap(blockIdx.x, gridDim.x));
+      x, y, fac, tB0, tB1, tB2, tD0, tD1, tD2, g, ze, n_free, alpha, lid);
 }
 
 // Several patches of one degree in one launch: a static queue of tiles, the
@@ -682,27 +697,46 @@ inline int launch_op3d_p(int mode, int nr, const ga_patch* pt, const S* x, S* y,
   g.nt[1] = nt[1];
   const long long ntxy = (long long)nt[0] * nt[1];
   const int ze = op3d_default_ze(mode, pt, sizeof(S) == 4);
-  const long long nwg = ntxy * ((pt->n[2] + ze - 1) / ze);
-  dim3 grid((unsigned)nwg);
+  const int nzc = (pt->n[2] + ze - 1) / ze;
+  const long long nwg = ntxy * nzc;
   const double* const* B = (mode == 2) ? pt->tabB2 : pt->tabB;
+  // deterministic mode: colour classes of tiles that share no coefficient.  Tiles t and
+  // t + c along x (or y) are disjoint when c * TE >= TE + P; z ranges when c * ze >= ze + P.
+  const int TEk = mode == 1 ? TK : TM;
+  // diag(M) (mode 2, patch setup) always takes the ordered launches: the scaling s of
+  // the preconditioner is then the same bits on every run
+  const bool ordered = pt->deterministic || mode == 2;
+  const int cxy = ordered ? 1 + (P + TEk - 1) / TEk : 0;
+  const int cz = ordered ? (nzc == 1 ? 1 : 1 + (P + ze - 1) / ze) : 0;
+  auto launch = [&](dim3 grid, TileColor col) {
 #define GA_OP3(TE, MODE, NRV)                                                                  \
   hipLaunchKernelGGL((op3d_kernel<P, TE, MODE, NRV, S, F>), grid, dim3(Tile3<P, TE>::NT), 0, st, \
                      x, y, fac, B[0], B[1], B[2], pt->tabD[0], pt->tabD[1], pt->tabD[2], g,      \
-                     ze, pt->n_free, alpha, gate)
-  if (nr < 1 || nr > 3) return -1;
-  if (mode == 0) {
-    if (nr == 1) GA_OP3(TM, 0, 1); else if (nr == 2) GA_OP3(TM, 0, 2); else GA_OP3(TM, 0, 3);
-  } else if (mode == 1) {
-    if (nr > op3d_max_nr(P, 1)) return -1;
-    if (nr == 1) GA_OP3(TK, 1, 1); else if (nr == 2) GA_OP3(TK, 1, 2); else GA_OP3(TK, 1, 3);
-  } else {
-    if constexpr (sizeof(S) == 8 && sizeof(F) == 8) {
-      GA_OP3(TM, 2, 1);
+                     ze, pt->n_free, alpha, gate, col)
+    if (mode == 0) {
+      if (nr == 1) GA_OP3(TM, 0, 1); else if (nr == 2) GA_OP3(TM, 0, 2); else GA_OP3(TM, 0, 3);
+    } else if (mode == 1) {
+      if (nr == 1) GA_OP3(TK, 1, 1); else if (nr == 2) GA_OP3(TK, 1, 2); else GA_OP3(TK, 1, 3);
     } else {
-      return -1;
+      if constexpr (sizeof(S) == 8 && sizeof(F) == 8) GA_OP3(TM, 2, 1);
     }
-  }
 #undef GA_OP3
+  };
+  if (nr < 1 || nr > 3) return -1;
+  if (mode == 1 && nr > op3d_max_nr(P, 1)) return -1;
+  if (mode == 2 && !(sizeof(S) == 8 && sizeof(F) == 8)) return -1;
+  if (!cxy) {
+    launch(dim3((unsigned)nwg), TileColor{0, 0, 0, 0, 0, 0, 0, 0});
+  } else {
+    for (int c = 0; c < cz; ++c)
+      for (int b = 0; b < cxy; ++b)
+        for (int a = 0; a < cxy; ++a) {
+          const int nx = (nt[0] - a + cxy - 1) / cxy, ny = (nt[1] - b + cxy - 1) / cxy;
+          const int nz = (nzc - c + cz - 1) / cz;
+          if (nx <= 0 || ny <= 0 || nz <= 0) continue;
+          launch(dim3((unsigned)((long long)nx * ny * nz)), TileColor{cxy, cxy, cz, a, b, c, nx, ny});
+        }
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -26,7 +26,7 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
-           "ga_batch_tune", "ga_batch_set_precision", "ga_batch_set_tau", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers", "ga_patch_set_layers",
+           "ga_batch_tune", "ga_batch_set_precision", "ga_batch_set_tau", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers", "ga_patch_set_layers", "ga_patch_set_deterministic",
            "ga_stability_limit2", "ga_integrator_set_rho", "ga_wave1d_create", "ga_wave1d_destroy",
            "ga_wave1d_info", "ga_wave1d_load_sine", "ga_wave1d_apply", "ga_wave1d_init_state",
            "ga_wave1d_step", "ga_batch_init_state", "ga_batch_step", "ga_mp_create", "ga_mp_destroy",
@@ -82,6 +82,7 @@ def load_library(path=LIB_PATH):
     lib.ga_patch_tune.argtypes = [vp, i, i, ctypes.POINTER(d), vp]
     lib.ga_patch_tuned_layers.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
     lib.ga_patch_set_layers.argtypes = [vp, i, i]
+    lib.ga_patch_set_deterministic.argtypes = [vp, i]
     lib.ga_cg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     lib.ga_integrator_set_damping.argtypes = [vp, d, d]
     lib.ga_stage_times.argtypes = [vp, d, ctypes.POINTER(d)]
@@ -212,6 +213,11 @@ def ga_patch_tuned_layers(patch):
 def ga_patch_set_layers(patch, ze_mass, ze_stiff):
     """Element layers per workgroup of the FP64 mass and stiffness launches (0: automatic)."""
     _check(_lib.ga_patch_set_layers(patch.h, int(ze_mass), int(ze_stiff)))
+
+
+def ga_patch_set_deterministic(patch, on=True):
+    """Fixed-order (colour-class) operator launches: bitwise reproducible results."""
+    _check(_lib.ga_patch_set_deterministic(patch.h, int(bool(on))))
 
 
 def ga_patch_set_cg(patch, mode):
