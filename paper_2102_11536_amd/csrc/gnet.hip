@@ -13,11 +13,14 @@
 //   Crops are channel-major [b][c][S^3]; the convolutions are "valid" and the
 //   activations of layers 1 and 2 at positions outside the grid are forced to zero,
 //   which makes a crop reproduce the whole-grid net on its interior.
-// Inference (BF16 weights and activations, FP32 accumulation, whole grid):
-//   layer 1 forms the channels from the FP64 history on the vector ALU, layer 2
-//   (55,296 of the 63,936 flops per point) runs on MFMA 32x32x16 from an LDS
-//   brick, layer 3 forms the guess.  Activations are channels-last [point][32]
-//   in BF16 (64 bytes per point).
+// Inference (whole grid, FP32 accumulation throughout):
+//   layer 1 forms the channels from the FP64 history and convolves them with FP32
+//     weights on the vector ALU;
+//   layer 2 (55,296 of the 63,936 flops per point) is the only layer with BF16
+//     weights: it runs on MFMA 32x32x16 from an LDS brick;
+//   layer 3 convolves with FP32 weights on the vector ALU and forms the guess.
+//   The activations between the layers are stored BF16, channels-last [point][32]
+//   (64 bytes per point).
 #include <hip/hip_runtime.h>
 
 #include "gnet.h"
