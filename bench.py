@@ -474,9 +474,10 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--profile-ops", default="",
-                    help="counter-collection mode: run only these operator applies (e.g. K2,M2), "
-                         "three times each, then a 1 GiB device copy used to calibrate "
-                         "FETCH_SIZE/WRITE_SIZE, and exit")
+                    help="counter-collection mode: run only these applies, three times each "
+                         "(M mass, K stiffness, P preconditioner; then the number of right-hand "
+                         "sides; an optional f or b suffix for FP32 or BF16: e.g. K2,M2,P2,M2f), "
+                         "then a 1 GiB device copy used to calibrate FETCH_SIZE/WRITE_SIZE, and exit")
     ap.add_argument("--workload", default="cube", choices=["cube", "multipatch", "glued", "dispersion", "c3", "wave2d"],
                     help="cube: the single-patch headline workload; multipatch: 12 independent "
                          "patches of uneven size and degree stepped as one batch; glued: a 2x2x2 "
@@ -514,11 +515,19 @@ def main():
     tuned_layers = ga.ga_patch_tuned_layers(pt)
     log(f"[bench] tuned layers per workgroup (mass, stiffness): {tuned_layers}, {tuned_ms:.3f} ms")
     if args.profile_ops:
-        x = torch.as_tensor(np.concatenate([U0] * k), device=dev)
+        nmax = max([k] + [int(op[1:].rstrip("fb")) for op in args.profile_ops.split(",")])
+        x = torch.as_tensor(np.concatenate([U0] * nmax), device=dev)
         y = torch.empty_like(x)
+        precs = {"": ga.GA_FP64, "f": ga.GA_FP32, "b": ga.GA_BF16}
         for op in args.profile_ops.split(","):
+            nr = int(op[1:].rstrip("fb"))
+            prec = precs[op[1:].lstrip("0123456789")]
             for _ in range(3):
-                ga.ga_apply_MK(pt, op[0], x, y, nrhs=int(op[1:]))
+                if op[0] == "P":
+                    ga.ga_apply_Pinv(pt, x[: nr * pt.n_free], y[: nr * pt.n_free], nrhs=nr, prec=prec)
+                else:
+                    ga.ga_apply_MK(pt, op[0], x[: nr * pt.n_free], y[: nr * pt.n_free], nrhs=nr,
+                                   prec=prec)
         a = torch.empty(2 ** 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         a.fill_(1.0)

@@ -84,7 +84,7 @@ int upload_origins(ga_gnet* net, int nb, const int* org, hipStream_t st) {
 
 int pack_if_needed(ga_gnet* net, hipStream_t st) {
   if (net->packed) return GA_OK;
-  gnet_pack_bf16(net->params, net->w2pk, st);
+  gnet_pack_bf16(net->params, net->wpk, st);
   net->packed = true;
   return check_launch(0, "net weight packing");
 }
@@ -102,7 +102,7 @@ int gnet_guess(ga_gnet* net, ga_patch* pt, const double* const* h, double* X, hi
   gnet_diff_norms(f, (long long)n, net->part, RED_BLOCKS, st);
   launch_sum_partials(4, net->part, net->scal, st);
   char* a1 = (char*)net->iw;
-  gnet_infer_grid(net->params, net->w2pk, f, pt->mf, net->scal, a1, a1 + n * 64, X, st);
+  gnet_infer_grid(net->params, net->wpk, f, pt->mf, net->scal, a1, a1 + n * 64, X, st);
   return check_launch(0, "learned guess");
 }
 
@@ -118,7 +118,7 @@ int ga_gnet_create(const float* params_host, ga_gnet** out) {
   if ((rc = dalloc((void**)&net->params, GNET_NPARAM * sizeof(float))) ||
       (rc = dalloc((void**)&net->m, GNET_NPARAM * sizeof(float))) ||
       (rc = dalloc((void**)&net->v, GNET_NPARAM * sizeof(float))) ||
-      (rc = dalloc(&net->w2pk, GNET_PACK2 * 2)) ||
+      (rc = dalloc(&net->wpk, GNET_PACK * 2)) ||
       (rc = dalloc((void**)&net->scal, 8 * sizeof(double))) ||
       (rc = dalloc((void**)&net->part, (size_t)4 * RED_BLOCKS * sizeof(double) + MSE_PARTS * sizeof(double)))) {
     ga_gnet_destroy(net);
@@ -135,7 +135,7 @@ int ga_gnet_create(const float* params_host, ga_gnet** out) {
 int ga_gnet_destroy(ga_gnet* net) {
   if (!net) return GA_OK;
   hipDeviceSynchronize();
-  for (void* p : {(void*)net->params, (void*)net->m, (void*)net->v, net->w2pk, (void*)net->tw,
+  for (void* p : {(void*)net->params, (void*)net->m, (void*)net->v, net->wpk, (void*)net->tw,
                   (void*)net->org, (void*)net->scal, (void*)net->part, net->iw})
     if (p) hipFree(p);
   delete net;

@@ -180,7 +180,7 @@ struct ga_gnet {
   float* m = nullptr;         // Adam moments
   float* v = nullptr;
   long long adam_t = 0;
-  void* w2pk = nullptr;       // BF16 layer-2 weights packed for MFMA
+  void* wpk = nullptr;        // BF16 inference weights of the three layers, packed
   bool packed = false;
   float* tw = nullptr;        // training activations and gradients
   size_t tw_bytes = 0;

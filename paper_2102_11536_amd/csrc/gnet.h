@@ -14,7 +14,13 @@ constexpr int GNET_B2 = GNET_W2 + 27 * 32 * 32;
 constexpr int GNET_W3 = GNET_B2 + 32;
 constexpr int GNET_B3 = GNET_W3 + 27 * 32;
 constexpr int GNET_NPARAM = GNET_B3 + 1;   // 32033
-constexpr int GNET_PACK2 = 27 * 2 * 64 * 8;  // bf16 entries of the MFMA-packed W2
+// BF16 inference weights, one buffer: W2 packed for the MFMA A operand, then W1 packed
+// likewise (7 k-slices of 4 taps x 4 channels, the 28th tap zero), then W3 as
+// channel pairs [27][16] for the packed dot products
+constexpr int GNET_PACK2 = 27 * 2 * 64 * 8;
+constexpr int GNET_PACK1 = 7 * 64 * 8;
+constexpr int GNET_PACK3 = 27 * 32;
+constexpr int GNET_PACK = GNET_PACK2 + GNET_PACK1 + GNET_PACK3;  // bf16 entries
 
 // four history fields (newest first) and the solution they are paired with
 struct GnetFields {
@@ -39,10 +45,10 @@ void gnet_diff_norms(GnetFields f, long long n, double* part, int nparts, hipStr
 void gnet_make_batch(GnetFields f, const int* grid3, const int* org_dev, int S, int nb,
                      const double* sq, float* in, float* tgt, hipStream_t st);
 
-// inference on the whole grid (BF16 weights and activations, FP32 accumulation):
-// X = E + s_3 * net(D / s), sq[c] = sum of D_c^2
-void gnet_pack_bf16(const float* params, void* w2pk, hipStream_t st);
-void gnet_infer_grid(const float* params, const void* w2pk, GnetFields f, const int* grid3,
+// inference on the whole grid (BF16 inputs, weights and activations, FP32
+// accumulation): X = E + s_3 * net(D / s), sq[c] = sum of D_c^2
+void gnet_pack_bf16(const float* params, void* wpk, hipStream_t st);
+void gnet_infer_grid(const float* params, const void* wpk, GnetFields f, const int* grid3,
                      const double* sq, void* a1, void* a2, double* X, hipStream_t st);
 
 }  // namespace ga

@@ -13,13 +13,14 @@
 //   Crops are channel-major [b][c][S^3]; the convolutions are "valid" and the
 //   activations of layers 1 and 2 at positions outside the grid are forced to zero,
 //   which makes a crop reproduce the whole-grid net on its interior.
-// Inference (whole grid, FP32 accumulation throughout):
-//   layer 1 forms the channels from the FP64 history and convolves them with FP32
-//     weights on the vector ALU;
-//   layer 2 (55,296 of the 63,936 flops per point) is the only layer with BF16
-//     weights: it runs on MFMA 32x32x16 from an LDS brick;
-//   layer 3 convolves with FP32 weights on the vector ALU and forms the guess.
-//   The activations between the layers are stored BF16, channels-last [point][32]
+// Inference (whole grid; BF16 inputs, weights and activations; FP32 accumulation),
+// three kernels over the same tiles, each staging its input brick in LDS:
+//   layer 1 forms the four channels from the FP64 history into the brick and runs
+//     on MFMA 32x32x16 (7 k-slices of 4 taps x 4 channels);
+//   layer 2 (55,296 of the 63,936 flops per point) runs on MFMA 32x32x16;
+//   layer 3 (one output channel) takes packed BF16 dot products on the vector ALU
+//     and forms the guess in FP64.
+//   The activations between the layers are stored channels-last [point][32]
 //   (64 bytes per point).
 #include <hip/hip_runtime.h>
 
@@ -34,6 +35,19 @@ constexpr int VB = 256;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// value held by lane (l ^ 1) of the wave (DPP quad permutation [1,0,3,2]); both lanes
+// of the pair must be active
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ bf16x2 as_bf16x2(unsigned u) {
+  bf16x2 r;
+  __builtin_memcpy(&r, &u, 4);
+  return r;
+}
 
 inline unsigned nbk(long long n) {
   long long b = (n + VB - 1) / VB;
@@ -286,61 +300,31 @@ make_batch_k(GnetFields f, Dims grid, const int* __restrict__ org, int S, int nb
 
 // ---------------------------------------------------------------- inference
 
-// W2 packed for the MFMA A operand: entry ((t*2 + kc)*64 + lane)*8 + i holds
-// W2[t][ci = 16 kc + 8 (lane/32) + i][co = lane % 32]
-__global__ void pack_w2_k(const float* __restrict__ W2, __bf16* __restrict__ pk) {
+// One buffer of BF16 weights:
+//   [0, GNET_PACK2): W2 for the MFMA A operand, entry ((t*2 + kc)*64 + lane)*8 + i
+//     holds W2[t][ci = 16 kc + 8 (lane/32) + i][co = lane % 32];
+//   then GNET_PACK1: W1 likewise, entry (j*64 + lane)*8 + i holds W1[t][ci][co] with
+//     t = 4 j + 2 (lane/32) + i/4, ci = i % 4, co = lane % 32 (zero for t = 27);
+//   then GNET_PACK3: W3 as [t][ci], pairs of consecutive channels in one 32-bit word.
+__global__ void pack_w_k(const float* __restrict__ params, __bf16* __restrict__ pk) {
   const int e = blockIdx.x * VB + threadIdx.x;
-  if (e >= GNET_PACK2) return;
-  const int i = e % 8, lane = (e / 8) % 64, kc = (e / 512) % 2, t = e / 1024;
-  const int ci = 16 * kc + 8 * (lane / 32) + i, co = lane % 32;
-  pk[e] = (__bf16)W2[(t * 32 + ci) * 32 + co];
-}
-
-// layer 1 on the whole grid, input channels D_c / s_c formed from the FP64
-// history, output BF16 channels-last
-__global__ void __launch_bounds__(VB)
-conv1_hist_k(GnetFields f, Dims grid, const double* __restrict__ sq,
-             const float* __restrict__ W, const float* __restrict__ bias, bf16x8* __restrict__ out) {
-  const long long v = grid.vol();
-  double is[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) is[c] = inv_rms(sq, c, v);
-  for (long long o = (long long)blockIdx.x * VB + threadIdx.x; o < v; o += (long long)gridDim.x * VB) {
-    const int ox = (int)(o % grid.x), oy = (int)((o / grid.x) % grid.y),
-              oz = (int)(o / ((long long)grid.x * grid.y));
-    float acc[32];
-#pragma unroll
-    for (int c = 0; c < 32; ++c) acc[c] = bias[c];
-    for (int t = 0; t < 27; ++t) {
-      const int x = ox + t % 3 - 1, y = oy + (t / 3) % 3 - 1, z = oz + t / 9 - 1;
-      if (!inside(x, y, z, grid)) continue;
-      const long long p = x + (long long)grid.x * (y + (long long)grid.y * z);
-      double d[4];
-      differences(f.h[0][p], f.h[1][p], f.h[2][p], f.h[3][p], d);
-#pragma unroll
-      for (int ci = 0; ci < 4; ++ci) {
-        const float val = (float)(d[ci] * is[ci]);
-        const float* w = W + (t * 4 + ci) * 32;
-#pragma unroll
-        for (int c = 0; c < 32; ++c) acc[c] += w[c] * val;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      bf16x8 r;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) r[i] = (__bf16)fmaxf(acc[8 * q + i], 0.0f);
-      out[o * 4 + q] = r;
-    }
+  if (e < GNET_PACK2) {
+    const int i = e % 8, lane = (e / 8) % 64, kc = (e / 512) % 2, t = e / 1024;
+    const int ci = 16 * kc + 8 * (lane / 32) + i, co = lane % 32;
+    pk[e] = (__bf16)params[GNET_W2 + (t * 32 + ci) * 32 + co];
+  } else if (e < GNET_PACK2 + GNET_PACK1) {
+    const int r = e - GNET_PACK2;
+    const int i = r % 8, lane = (r / 8) % 64, j = r / 512;
+    const int t = 4 * j + 2 * (lane / 32) + i / 4, ci = i % 4, co = lane % 32;
+    pk[e] = t < 27 ? (__bf16)params[GNET_W1 + (t * 4 + ci) * 32 + co] : (__bf16)0.0f;
+  } else if (e < GNET_PACK) {
+    pk[e] = (__bf16)params[GNET_W3 + (e - GNET_PACK2 - GNET_PACK1)];
   }
 }
 
-// layer 2 on MFMA.  Workgroup tile: 16 (x) x 8 (y) x 4 (z) output points; its input
-// brick with a one-point halo (18 x 10 x 6 points x 32 channels, BF16) sits in LDS,
-// 16-byte channel chunk c of brick point n stored at slot c ^ ((n >> 1) & 3) so that
-// 8 consecutive points read by one LDS phase hit distinct banks.  Wave w owns z-plane
-// w of the tile; each MFMA covers 32 output channels x 32 points (16 x by 2 y) and one
-// 16-channel slice of one tap: 54 MFMAs per group of 32 points.
+// Workgroup tile of every inference kernel: 16 (x) x 8 (y) x 4 (z) output points; its
+// input brick with a one-point halo is 18 x 10 x 6 points.  Wave w owns z-plane w of
+// the tile; an MFMA 32x32x16 covers 32 output channels x 32 points (16 x by 2 y).
 constexpr int TX = 16, TY = 8, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int HP = HX * HY * HZ;
 
@@ -352,53 +336,17 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned bid, unsigned nwg) {
   return base + loc;
 }
 
-__global__ void __launch_bounds__(256)
-conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wpk,
-             const float* __restrict__ bias, __bf16* __restrict__ a2, int ntx, int nty) {
-  __shared__ uint4 brick[HP * 4];
-  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < HP * 4; e += 256) {
-    const int n = e >> 2, c = e & 3;
-    const int hx = n % HX, hy = (n / HX) % HY, hz = n / (HX * HY);
-    const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (inside(x, y, z, g)) v = a1[(x + (long long)g.x * (y + (long long)g.y * z)) * 4 + c];
-    brick[n * 4 + (c ^ ((n >> 1) & 3))] = v;
-  }
-  __syncthreads();
-  const int lane = tid & 63, w = tid >> 6;
-  const int n32 = lane & 31, half = lane >> 5, lx = n32 & 15, ly = n32 >> 4;
-  f32x16 acc[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[r][v] = 0.0f;
-  for (int t = 0; t < 27; ++t) {
-    const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc) {
-      const bf16x8 A = wpk[(t * 2 + kc) * 64 + lane];
-      const int c = kc * 2 + half;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int n = ((w + dz) * HY + (2 * r + ly + dy)) * HX + (lx + dx);
-        const uint4 raw = brick[n * 4 + (c ^ ((n >> 1) & 3))];
-        bf16x8 B;
-        __builtin_memcpy(&B, &raw, 16);
-        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[r], 0, 0, 0);
-      }
-    }
-  }
-  // accumulator v of lane l holds channel 8 (v/4) + 4 (l/32) + v%4 of point l%32
-  const int oz = z0 + w;
+// ReLU(acc + bias) of 4 groups of 32 points to BF16 channels-last rows of 32
+// channels (accumulator v of lane l holds channel 8 (v/4) + 4 (l/32) + v%4 of point
+// l%32), points outside the grid skipped
+__device__ __forceinline__ void store_act(const f32x16 (&acc)[4], const float* __restrict__ bias,
+                                          __bf16* __restrict__ out, Dims g, int x0, int y0, int oz,
+                                          int lx, int ly, int half) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int ox = x0 + lx, oy = y0 + 2 * r + ly;
     if (!inside(ox, oy, oz, g)) continue;
-    __bf16* dst = a2 + (ox + (long long)g.x * (oy + (long long)g.y * oz)) * 32;
+    __bf16* dst = out + (ox + (long long)g.x * (oy + (long long)g.y * oz)) * 32;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int c0 = 8 * q + 4 * half;
@@ -410,31 +358,212 @@ conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wp
   }
 }
 
-// layer 3 and the guess: X = E + s_3 * (b3 + sum W3 * a2)
-__global__ void __launch_bounds__(VB)
-conv3_guess_k(const bf16x8* __restrict__ a2, GnetFields f, Dims grid,
-              const double* __restrict__ sq, const float* __restrict__ W,
-              const float* __restrict__ bias, double* __restrict__ X) {
-  const long long v = grid.vol();
-  const double s3 = 1.0 / inv_rms(sq, 3, v);
-  for (long long o = (long long)blockIdx.x * VB + threadIdx.x; o < v; o += (long long)gridDim.x * VB) {
-    const int ox = (int)(o % grid.x), oy = (int)((o / grid.x) % grid.y),
-              oz = (int)(o / ((long long)grid.x * grid.y));
-    float acc = bias[0];
-    for (int t = 0; t < 27; ++t) {
-      const int x = ox + t % 3 - 1, y = oy + (t / 3) % 3 - 1, z = oz + t / 9 - 1;
-      if (!inside(x, y, z, grid)) continue;
-      const long long p = x + (long long)grid.x * (y + (long long)grid.y * z);
+// Stage a brick of 32-channel BF16 activations (64 bytes per point, zero outside the
+// grid) with every load of a thread in flight before the first LDS store; 16-byte
+// channel chunk c of brick point n goes to slot c ^ ((n >> 1) & 3)
+__device__ __forceinline__ void stage_act_brick(const uint4* __restrict__ src, Dims g, int x0,
+                                                int y0, int z0, uint4* brick, int tid) {
+  constexpr int NE = (HP * 4 + 255) / 256;
+  uint4 v[NE];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bf16x8 a = a2[p * 4 + q];
-        const float* wq = W + t * 32 + 8 * q;
+  for (int k = 0; k < NE; ++k) {
+    const int e = tid + k * 256, n = e >> 2, c = e & 3;
+    const int hx = n % HX, hy = (n / HX) % HY, hz = n / (HX * HY);
+    const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
+    v[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (e < HP * 4 && inside(x, y, z, g))
+      v[k] = src[(x + (long long)g.x * (y + (long long)g.y * z)) * 4 + c];
+  }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) acc += wq[i] * (float)a[i];
+  for (int k = 0; k < NE; ++k) {
+    const int e = tid + k * 256, n = e >> 2, c = e & 3;
+    if (e < HP * 4) brick[n * 4 + (c ^ ((n >> 1) & 3))] = v[k];
+  }
+}
+
+// layer 1 on MFMA.  The brick holds the four input channels D_c / s_c of each point
+// as BF16 (8 bytes per point), formed from the FP64 history (zero outside the grid);
+// the 108 products per output channel (27 taps x 4 channels) are 7 k-slices of 4 taps.
+__global__ void __launch_bounds__(256)
+conv1_mfma_k(GnetFields f, Dims g, const double* __restrict__ sq, const bf16x8* __restrict__ wpk,
+             const float* __restrict__ bias, __bf16* __restrict__ a1, int ntx, int nty) {
+  __shared__ uint2 brick[HP];
+  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int tid = threadIdx.x;
+  const long long vol = g.vol();
+  double is[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) is[c] = inv_rms(sq, c, vol);
+  // every history load of a thread in flight before the first LDS store
+  constexpr int NE = (HP + 255) / 256;
+  double hv[NE][4];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int n = tid + k * 256;
+    const int hx = n % HX, hy = (n / HX) % HY, hz = n / (HX * HY);
+    const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
+    const bool in = n < HP && inside(x, y, z, g);
+    const long long p = in ? x + (long long)g.x * (y + (long long)g.y * z) : 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) hv[k][c] = in ? f.h[c][p] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int n = tid + k * 256;
+    if (n >= HP) continue;
+    double d[4];
+    differences(hv[k][0], hv[k][1], hv[k][2], hv[k][3], d);
+    bf16x4 v;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = (__bf16)(float)(d[c] * is[c]);
+    __builtin_memcpy(&brick[n], &v, 8);
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int n32 = lane & 31, half = lane >> 5, lx = n32 & 15, ly = n32 >> 4;
+  f32x16 acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[r][v] = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const bf16x8 A = wpk[j * 64 + lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint2 raw[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = 4 * j + 2 * half + h;
+        raw[h] = make_uint2(0u, 0u);
+        if (t < 27) {
+          const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
+          raw[h] = brick[((w + dz) * HY + (2 * r + ly + dy)) * HX + (lx + dx)];
+        }
+      }
+      bf16x8 B;
+      __builtin_memcpy(&B, raw, 16);
+      acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[r], 0, 0, 0);
+    }
+  }
+  store_act(acc, bias, a1, g, x0, y0, z0 + w, lx, ly, half);
+}
+
+// layer 2 on MFMA.  The brick holds the 32 layer-1 channels of each point (BF16,
+// 64 bytes); 16-byte channel chunk c of brick point n sits at slot c ^ ((n >> 1) & 3)
+// so that 8 consecutive points read by one LDS phase hit distinct banks.  Each MFMA
+// covers one 16-channel slice of one tap: 54 MFMAs per group of 32 points.
+__global__ void __launch_bounds__(256)
+conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wpk,
+             const float* __restrict__ bias, __bf16* __restrict__ a2, int ntx, int nty) {
+  __shared__ uint4 brick[HP * 4];
+  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int tid = threadIdx.x;
+  stage_act_brick(a1, g, x0, y0, z0, brick, tid);
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int n32 = lane & 31, half = lane >> 5, lx = n32 & 15, ly = n32 >> 4;
+  f32x16 acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[r][v] = 0.0f;
+  // operands of k-step s = 2 t + kc (tap t, channel slice kc); the next step's are
+  // read before this step's four MFMAs are issued
+  auto load_step = [&](int st, bf16x8& A, bf16x8 (&B)[4]) {
+    const int t = st >> 1, kc = st & 1;
+    const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
+    const int c = kc * 2 + half;
+    A = wpk[st * 64 + lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = ((w + dz) * HY + (2 * r + ly + dy)) * HX + (lx + dx);
+      const uint4 raw = brick[n * 4 + (c ^ ((n >> 1) & 3))];
+      __builtin_memcpy(&B[r], &raw, 16);
+    }
+  };
+  bf16x8 A0, A1, B0[4], B1[4];
+  load_step(0, A0, B0);
+  for (int st = 0; st < 54; st += 2) {
+    load_step(st + 1, A1, B1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, B0[r], acc[r], 0, 0, 0);
+    if (st + 2 < 54) load_step(st + 2, A0, B0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1[r], acc[r], 0, 0, 0);
+  }
+  store_act(acc, bias, a2, g, x0, y0, z0 + w, lx, ly, half);
+}
+
+// layer 3 and the guess, X = E + s_3 * (b3 + sum W3 * a2): the tile's layer-2 brick
+// (layout of layer 2's) and the BF16 weight pairs in LDS.  A pair of lanes owns one
+// (x, y) column of the tile's 4 output points in z, each lane half of the channels:
+// for each (dx, dy) it reads the column's 6 brick points once and the 3 taps' weights
+// once, and adds every brick point to the (up to 3) outputs it reaches; FP32 dot
+// products of BF16 pairs, the two halves summed by a lane exchange.
+__global__ void __launch_bounds__(256)
+conv3_lds_k(const uint4* __restrict__ a2, GnetFields f, Dims g, const double* __restrict__ sq,
+            const uint4* __restrict__ w3, const float* __restrict__ bias,
+            double* __restrict__ X, int ntx, int nty) {
+  static_assert(TX * TY * 2 == 256 && TZ == 4, "a lane pair per column of 4 points");
+  __shared__ uint4 brick[HP * 4];
+  __shared__ uint4 sw[27 * 4];
+  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int tid = threadIdx.x;
+  if (tid < 27 * 4) sw[tid] = w3[tid];
+  stage_act_brick(a2, g, x0, y0, z0, brick, tid);
+  __syncthreads();
+  const int h = tid & 1, col = tid >> 1, lx = col % TX, ly = col / TX;
+  float acc[TZ];
+#pragma unroll
+  for (int z = 0; z < TZ; ++z) acc[z] = 0.0f;
+  for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      uint4 w[3][2];   // taps (dz, dy, dx), this lane's two channel chunks
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) w[dz][k] = sw[(9 * dz + 3 * dy + dx) * 4 + 2 * h + k];
+#pragma unroll
+      for (int bz = 0; bz < TZ + 2; ++bz) {
+        const int n = (bz * HY + (ly + dy)) * HX + (lx + dx);
+        uint4 a[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) a[k] = brick[n * 4 + ((2 * h + k) ^ ((n >> 1) & 3))];
+#pragma unroll
+        for (int lz = 0; lz < TZ; ++lz) {
+          const int dz = bz - lz;
+          if (dz < 0 || dz > 2) continue;
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            acc[lz] = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a[k].x), as_bf16x2(w[dz][k].x), acc[lz], false);
+            acc[lz] = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a[k].y), as_bf16x2(w[dz][k].y), acc[lz], false);
+            acc[lz] = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a[k].z), as_bf16x2(w[dz][k].z), acc[lz], false);
+            acc[lz] = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a[k].w), as_bf16x2(w[dz][k].w), acc[lz], false);
+          }
+        }
       }
     }
-    const double e = 4.0 * f.h[0][o] - 6.0 * f.h[1][o] + 4.0 * f.h[2][o] - f.h[3][o];
-    X[o] = e + s3 * (double)acc;
+  }
+  const double s3 = 1.0 / inv_rms(sq, 3, g.vol());
+  const float b3 = bias[0];
+#pragma unroll
+  for (int lz = 0; lz < TZ; ++lz) {
+    const float tot = b3 + (acc[lz] + lane_xor1(acc[lz]));
+    // lane 0 of the pair stores z 0, 1, lane 1 z 2, 3
+    if ((lz >> 1) != h) continue;
+    const int ox = x0 + lx, oy = y0 + ly, oz = z0 + lz;
+    if (!inside(ox, oy, oz, g)) continue;
+    const long long p = ox + (long long)g.x * (oy + (long long)g.y * oz);
+    const double e = 4.0 * f.h[0][p] - 6.0 * f.h[1][p] + 4.0 * f.h[2][p] - f.h[3][p];
+    X[p] = e + s3 * (double)tot;
   }
 }
 
@@ -496,22 +625,23 @@ void gnet_make_batch(GnetFields f, const int* grid3, const int* org_dev, int S, 
                      Dims{grid3[0], grid3[1], grid3[2]}, org_dev, S, nb, sq, in, tgt);
 }
 
-void gnet_pack_bf16(const float* params, void* w2pk, hipStream_t st) {
-  hipLaunchKernelGGL(pack_w2_k, dim3((GNET_PACK2 + VB - 1) / VB), dim3(VB), 0, st,
-                     params + GNET_W2, (__bf16*)w2pk);
+void gnet_pack_bf16(const float* params, void* wpk, hipStream_t st) {
+  hipLaunchKernelGGL(pack_w_k, dim3((GNET_PACK + VB - 1) / VB), dim3(VB), 0, st, params,
+                     (__bf16*)wpk);
 }
 
-void gnet_infer_grid(const float* params, const void* w2pk, GnetFields f, const int* grid3,
+void gnet_infer_grid(const float* params, const void* wpk, GnetFields f, const int* grid3,
                      const double* sq, void* a1, void* a2, double* X, hipStream_t st) {
   const Dims g{grid3[0], grid3[1], grid3[2]};
-  const long long v = g.vol();
-  hipLaunchKernelGGL(conv1_hist_k, dim3(nbk(v)), dim3(VB), 0, st, f, g, sq,
-                     params + GNET_W1, params + GNET_B1, (bf16x8*)a1);
   const int ntx = (g.x + TX - 1) / TX, nty = (g.y + TY - 1) / TY, ntz = (g.z + TZ - 1) / TZ;
-  hipLaunchKernelGGL(conv2_mfma_k, dim3((unsigned)(ntx * nty * ntz)), dim3(256), 0, st,
-                     (const uint4*)a1, g, (const bf16x8*)w2pk, params + GNET_B2, (__bf16*)a2, ntx, nty);
-  hipLaunchKernelGGL(conv3_guess_k, dim3(nbk(v)), dim3(VB), 0, st, (const bf16x8*)a2, f, g,
-                     sq, params + GNET_W3, params + GNET_B3, X);
+  const dim3 grid((unsigned)(ntx * nty * ntz));
+  const __bf16* pk = (const __bf16*)wpk;
+  hipLaunchKernelGGL(conv1_mfma_k, grid, dim3(256), 0, st, f, g, sq,
+                     (const bf16x8*)(pk + GNET_PACK2), params + GNET_B1, (__bf16*)a1, ntx, nty);
+  hipLaunchKernelGGL(conv2_mfma_k, grid, dim3(256), 0, st, (const uint4*)a1, g,
+                     (const bf16x8*)pk, params + GNET_B2, (__bf16*)a2, ntx, nty);
+  hipLaunchKernelGGL(conv3_lds_k, grid, dim3(256), 0, st, (const uint4*)a2, f, g, sq,
+                     (const uint4*)(pk + GNET_PACK2 + GNET_PACK1), params + GNET_B3, X, ntx, nty);
 }
 
 }  // namespace ga
