@@ -305,32 +305,36 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
   const size_t n = pt->n_free;
   const bool fused = pt->cg_ctrl == GA_CG_FUSED && pt->dim == 3 && pt->pinv_mode == GA_PINV_AUTO &&
                      nr <= 16 && pinv_band_fits(3, pt->p, pt->mf, sizeof(double));
-  int rc = ensure_work(pt, fused ? 7 * nr : 6 * nr);
+  // slots of nr vectors: r, a copy of b, z, q, p, t0 (two), t1 (two), s (fused):
+  // with a guess, [r | b] -> [z | q] is one preconditioner apply of 2 nr right-hand
+  // sides (its passes take as long for 2 nr as for nr: too few lines for the chip)
+  int rc = ensure_work(pt, fused ? 10 * nr : 9 * nr);
   if (rc) return rc;
   if (fused && (rc = ensure_cgf(pt))) return rc;
   SolveBufs w;
   double* base = pt->work;
+  const size_t tot = (size_t)nr * n;
   w.r = base;
-  w.z = base + (size_t)nr * n;
-  w.p = base + (size_t)2 * nr * n;
-  w.q = base + (size_t)3 * nr * n;
-  w.t0 = base + (size_t)4 * nr * n;
-  w.t1 = base + (size_t)5 * nr * n;
+  double* bq = base + tot;
+  w.z = base + 2 * tot;
+  w.q = base + 3 * tot;
+  w.p = base + 4 * tot;
+  w.t0 = base + 5 * tot;
+  w.t1 = base + 7 * tot;
   double* partA = pt->red;
   double* partB = pt->red + (size_t)16 * RED_BLOCKS;
-  const size_t tot = (size_t)nr * n;
+  const double* pbn = nullptr;
   if (zero_guess) {
     launch_fill(x, 0.0, tot, st);
     launch_copy(w.r, b, tot, st);
+    if ((rc = pinv_apply(pt, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+    launch_dot_partial(nr, w.r, w.z, n, partA, st);
   } else {
     launch_copy(w.r, b, tot, st);
+    launch_copy(bq, b, tot, st);
     if ((rc = op_apply(pt, 0, nr, -1.0, x, w.r, st))) return rc;
-  }
-  if ((rc = pinv_apply(pt, nr, w.r, w.z, w.t0, w.t1, st))) return rc;
-  launch_dot_partial(nr, w.r, w.z, n, partA, st);
-  const double* pbn = nullptr;
-  if (!zero_guess) {
-    if ((rc = pinv_apply(pt, nr, b, w.q, w.t0, w.t1, st))) return rc;
+    if ((rc = pinv_apply(pt, 2 * nr, w.r, w.z, w.t0, w.t1, st))) return rc;
+    launch_dot_partial(nr, w.r, w.z, n, partA, st);
     launch_dot_partial(nr, b, w.q, n, partB, st);
     pbn = partB;
   }
@@ -339,8 +343,8 @@ int solve_impl(ga_patch* pt, int nr, const double* b, double* x, double rtol, in
   if (check_launch(0, "pcg start")) return GA_EDEVICE;
   int it = 0;
   if (fused) {
-    // single-reduction PCG: w (in q) starts at zero, s is the seventh vector
-    double* sv = base + (size_t)6 * nr * n;
+    // single-reduction PCG: w (in q) starts at zero, s is the last vector
+    double* sv = base + 9 * tot;
     launch_fill(w.q, 0.0, tot, st);
     if (pt->hint_nr == nr) {
       int hmax = 0;
@@ -571,11 +575,13 @@ int solve_mixed_impl(ga_patch* pt, int prec, int nr, const double* b, double* x,
   const size_t tot = (size_t)nr * n;
   int rc = ensure_mixed(pt, st);
   if (rc) return rc;
-  if ((rc = ensure_work(pt, 5 * nr))) return rc;   // r64 and seven FP32 vectors
+  // r64 and nine FP32 vectors: r, q (b), z, p (P^-1 b), d, t0 (two), t1 (two); with a
+  // guess, [r | b] -> [z | P^-1 b] is one preconditioner apply of 2 nr right-hand sides
+  if ((rc = ensure_work(pt, 6 * nr))) return rc;
   double* r64 = pt->work;
   float* f = reinterpret_cast<float*>(pt->work + tot);
-  float *r32 = f, *z32 = f + tot, *p32 = f + 2 * tot, *q32 = f + 3 * tot, *d32 = f + 4 * tot,
-        *t0 = f + 5 * tot, *t1 = f + 6 * tot;
+  float *r32 = f, *q32 = f + tot, *z32 = f + 2 * tot, *p32 = f + 3 * tot, *d32 = f + 4 * tot,
+        *t0 = f + 5 * tot, *t1 = f + 7 * tot;
   double* partA = pt->red;
   double* partB = pt->red + (size_t)16 * RED_BLOCKS;
   double* so = pt->scal;                       // outer (FP64 refinement) scalars
@@ -588,15 +594,16 @@ int solve_mixed_impl(ga_patch* pt, int prec, int nr, const double* b, double* x,
   if (zero_guess) {
     launch_fill(x, 0.0, tot, st);
     launch_copy(r64, b, tot, st);
+    launch_to_f32(r32, r64, tot, st);
+    if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
   } else {
     launch_copy(r64, b, tot, st);
     if ((rc = op_apply(pt, 0, nr, -1.0, x, r64, st))) return rc;
+    launch_to_f32(r32, r64, tot, st);
     launch_to_f32(q32, b, tot, st);
-    if ((rc = pinv_apply_lp(pt, prec, nr, q32, p32, t0, t1, st))) return rc;
+    if ((rc = pinv_apply_lp(pt, prec, 2 * nr, r32, z32, t0, t1, st))) return rc;
     launch_dot_ff(nr, q32, p32, n, partB, st);
   }
-  launch_to_f32(r32, r64, tot, st);
-  if ((rc = pinv_apply_lp(pt, prec, nr, r32, z32, t0, t1, st))) return rc;
   launch_dot_ff(nr, r32, z32, n, partA, st);
   launch_mx_outer(nr, partA, zero_guess ? nullptr : partB, so, si, rtol * rtol, floor * floor, 0,
                   st);
