@@ -234,7 +234,13 @@ int ga_cg_stats(const ga_patch* patch, long long* spec_iters, long long* host_ch
  * right-hand sides are frozen while the others continue.
  *   prec   GA_FP64, or GA_FP32 / GA_BF16 (3-D only; see above).  With GA_FP32
  *          and GA_BF16 the stopping test uses P^{-1} applied in that precision
- *          and iters_out counts the inner iterations.
+ *          and iters_out counts the inner iterations.  Where rtol is at least 8
+ *          times the inner arithmetic's accuracy floor (3e-7 for GA_FP32, 2e-3
+ *          for GA_BF16), a refinement pass whose inner PCG reached half the
+ *          tolerance, with a rounding error (about floor times the pass's
+ *          starting residual) of at most an eighth of it, ends that right-hand
+ *          side without a further FP64 residual; its relres_out is then the
+ *          inner residual estimate.
  *   iters_out[nrhs], relres_out[nrhs]  host arrays or NULL.
  * Returns GA_ENOCONV if any right-hand side did not converge in maxit.
  */

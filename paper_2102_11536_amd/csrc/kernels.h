@@ -250,6 +250,8 @@ void launch_cg_beta_flex(int nr, const double* p1, const double* p2, double* sca
 void launch_mx_outer(int nr, const double* part_rz, const double* part_bn, double* so, double* si,
                      double rtol2, double floor2, int pass, hipStream_t st);
 // systems whose guess was rejected restart from zero: x = 0, r64 = b, r32 = b32, z32 = zb32
+// accept inner solves the inner arithmetic resolves (nr <= 64), without an FP64 residual
+void launch_mx_accept(int nr, double* so, const double* si, double floor2, hipStream_t st);
 void launch_mx_fallback(int nr, double* x, double* r64, float* r32, float* z32, const double* b,
                         const float* b32, const float* zb32, const double* so, size_t n,
                         hipStream_t st);

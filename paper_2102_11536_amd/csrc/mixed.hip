@@ -160,6 +160,18 @@ mx_outer_k(const double* part_rz, const double* part_bn, double* so, double* si,
   if (threadIdx.x != 0) return;
   double* o = so + (size_t)r * NSCAL;
   double* in = si + (size_t)r * NSCAL;
+  // a system that converged in an earlier pass, or whose inner result was accepted in
+  // this one (o[11] < 0, set by mx_accept_k), keeps its scalars (its inner flags are
+  // already off); only the per-pass iteration record is cleared or finished
+  if (pass != 0 && o[S_ACTIVE] == 0.0) {
+    if (o[11] < 0.0) {
+      o[11] = 0.0;
+    } else {
+      o[10] = 0.0;
+      o[11] = 0.0;
+    }
+    return;
+  }
   if (pass == 0) {
     o[S_RZ0] = rz;
     o[S_FALLBACK] = (part_bn && !(rz < bn)) ? 1.0 : 0.0;   // keep a guess only if it beats zero
@@ -186,6 +198,25 @@ mx_outer_k(const double* part_rz, const double* part_bn, double* so, double* si,
   in[S_ALPHA] = 0.0;
   in[S_BETA] = 0.0;
   in[S_ACTIVE] = active ? 1.0 : 0.0;
+}
+
+// Acceptance of an inner solve without an FP64 residual (one thread per system): the
+// inner PCG converged to at most half the outer tolerance, and the inner arithmetic's
+// error, about floor |r|_P for the pass's starting residual r, is at most an eighth of
+// it; the inner residual estimate then stands for the outer one
+__global__ void mx_accept_k(int nr, double* so, const double* si, double floor2) {
+  const int r = threadIdx.x;
+  if (r >= nr) return;
+  double* o = so + (size_t)r * NSCAL;
+  const double* in = si + (size_t)r * NSCAL;
+  if (o[S_ACTIVE] == 0.0 || in[S_ACTIVE] != 0.0) return;
+  const double t2 = o[S_TOL2] * o[S_BN2];
+  if (!(in[S_RZ] <= 0.25 * t2) || !(64.0 * floor2 * o[S_RZ] <= t2)) return;
+  o[S_ITERS] += in[S_ITERS];
+  o[10] = in[S_ITERS];   // inner iterations of this pass
+  o[11] = -1.0;          // accepted in this pass (mx_outer_k turns it into 0: not cut)
+  o[S_RZ] = in[S_RZ];
+  o[S_ACTIVE] = 0.0;
 }
 
 __global__ void mx_fallback_k(double* __restrict__ x, double* __restrict__ r64, float* __restrict__ r32,
@@ -269,6 +300,9 @@ void launch_mx_outer(int nr, const double* part_rz, const double* part_bn, doubl
                      double rtol2, double floor2, int pass, hipStream_t st) {
   hipLaunchKernelGGL(mx_outer_k, dim3(nr), dim3(VB), 0, st, part_rz, part_bn, so, si, rtol2, floor2,
                      pass);
+}
+void launch_mx_accept(int nr, double* so, const double* si, double floor2, hipStream_t st) {
+  hipLaunchKernelGGL(mx_accept_k, dim3(1), dim3(64), 0, st, nr, so, si, floor2);
 }
 void launch_mx_fallback(int nr, double* x, double* r64, float* r32, float* z32, const double* b,
                         const float* b32, const float* zb32, const double* so, size_t n,
