@@ -15,11 +15,11 @@ constexpr int GNET_W3 = GNET_B2 + 32;
 constexpr int GNET_B3 = GNET_W3 + 27 * 32;
 constexpr int GNET_NPARAM = GNET_B3 + 1;   // 32033
 // BF16 inference weights, one buffer: W2 packed for the MFMA A operand, then W1 packed
-// likewise (7 k-slices of 4 taps x 4 channels, the 28th tap zero), then W3 as
-// channel pairs [27][16] for the packed dot products
+// likewise (7 k-slices of 4 taps x 4 channels, the 28th tap zero), then W3 packed as
+// the A operand of the per-tap products of layer 3 (taps as rows, 2 channel slices)
 constexpr int GNET_PACK2 = 27 * 2 * 64 * 8;
 constexpr int GNET_PACK1 = 7 * 64 * 8;
-constexpr int GNET_PACK3 = 27 * 32;
+constexpr int GNET_PACK3 = 2 * 64 * 8;
 constexpr int GNET_PACK = GNET_PACK2 + GNET_PACK1 + GNET_PACK3;  // bf16 entries
 
 // four history fields (newest first) and the solution they are paired with
@@ -46,7 +46,8 @@ void gnet_make_batch(GnetFields f, const int* grid3, const int* org_dev, int S, 
                      const double* sq, float* in, float* tgt, hipStream_t st);
 
 // inference on the whole grid (BF16 inputs, weights and activations, FP32
-// accumulation): X = E + s_3 * net(D / s), sq[c] = sum of D_c^2
+// accumulation): X = E + s_3 * net(D / s), sq[c] = sum of D_c^2; scratch a1 of 64
+// bytes per grid point (layer-1 activations), a2 of 54 (layer 3's tap planes)
 void gnet_pack_bf16(const float* params, void* wpk, hipStream_t st);
 void gnet_infer_grid(const float* params, const void* wpk, GnetFields f, const int* grid3,
                      const double* sq, void* a1, void* a2, double* X, hipStream_t st);

@@ -17,11 +17,13 @@
 // three kernels over the same tiles, each staging its input brick in LDS:
 //   layer 1 forms the four channels from the FP64 history into the brick and runs
 //     on MFMA 32x32x16 (7 k-slices of 4 taps x 4 channels);
-//   layer 2 (55,296 of the 63,936 flops per point) runs on MFMA 32x32x16;
-//   layer 3 (one output channel) takes packed BF16 dot products on the vector ALU
-//     and forms the guess in FP64.
-//   The activations between the layers are stored channels-last [point][32]
-//   (64 bytes per point).
+//   layer 2 (55,296 of the 63,936 flops per point) runs on MFMA 32x32x16, and in
+//     its epilogue two more MFMAs per group form layer 3's per-tap products
+//     u[t][p] = sum_c W3[t][c] a2[p][c] (taps as rows), stored as 27 BF16 planes;
+//   a last kernel sums u[t] over the 27 tap offsets of each point and forms the
+//     guess in FP64.
+//   The layer-1 activations are stored channels-last [point][32] (64 bytes per
+//   point), the tap planes in 54 bytes per point.
 #include <hip/hip_runtime.h>
 
 #include "gnet.h"
@@ -35,19 +37,6 @@ constexpr int VB = 256;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-
-// value held by lane (l ^ 1) of the wave (DPP quad permutation [1,0,3,2]); both lanes
-// of the pair must be active
-__device__ __forceinline__ float lane_xor1(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ bf16x2 as_bf16x2(unsigned u) {
-  bf16x2 r;
-  __builtin_memcpy(&r, &u, 4);
-  return r;
-}
 
 inline unsigned nbk(long long n) {
   long long b = (n + VB - 1) / VB;
@@ -305,7 +294,16 @@ make_batch_k(GnetFields f, Dims grid, const int* __restrict__ org, int S, int nb
 //     holds W2[t][ci = 16 kc + 8 (lane/32) + i][co = lane % 32];
 //   then GNET_PACK1: W1 likewise, entry (j*64 + lane)*8 + i holds W1[t][ci][co] with
 //     t = 4 j + 2 (lane/32) + i/4, ci = i % 4, co = lane % 32 (zero for t = 27);
-//   then GNET_PACK3: W3 as [t][ci], pairs of consecutive channels in one 32-bit word.
+//   then GNET_PACK3: W3 for the A operand of layer 3's per-tap products, entry
+//     (s*64 + lane)*8 + i holds W3[t = lane % 32][layer3_channel(s, lane / 32, i)]
+//     (zero for t >= 27).
+// Channel that k index 8 h + i of k-slice s stands for in layer 3's products: lane
+// half h of layer 2's accumulators holds channels 8 q + 4 h + j (q, j < 4) as entries
+// 4 q + j, so slice s takes entries 8 s .. 8 s + 7 of each lane as they are
+__host__ __device__ constexpr int layer3_channel(int s, int h, int i) {
+  return 8 * (2 * s + i / 4) + 4 * h + i % 4;
+}
+
 __global__ void pack_w_k(const float* __restrict__ params, __bf16* __restrict__ pk) {
   const int e = blockIdx.x * VB + threadIdx.x;
   if (e < GNET_PACK2) {
@@ -318,7 +316,10 @@ __global__ void pack_w_k(const float* __restrict__ params, __bf16* __restrict__ 
     const int t = 4 * j + 2 * (lane / 32) + i / 4, ci = i % 4, co = lane % 32;
     pk[e] = t < 27 ? (__bf16)params[GNET_W1 + (t * 4 + ci) * 32 + co] : (__bf16)0.0f;
   } else if (e < GNET_PACK) {
-    pk[e] = (__bf16)params[GNET_W3 + (e - GNET_PACK2 - GNET_PACK1)];
+    const int r = e - GNET_PACK2 - GNET_PACK1;
+    const int i = r % 8, lane = (r / 8) % 64, sl = r / 512;
+    const int t = lane % 32, ci = layer3_channel(sl, lane / 32, i);
+    pk[e] = t < 27 ? (__bf16)params[GNET_W3 + t * 32 + ci] : (__bf16)0.0f;
   }
 }
 
@@ -457,7 +458,8 @@ conv1_mfma_k(GnetFields f, Dims g, const double* __restrict__ sq, const bf16x8* 
 // covers one 16-channel slice of one tap: 54 MFMAs per group of 32 points.
 __global__ void __launch_bounds__(256)
 conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wpk,
-             const float* __restrict__ bias, __bf16* __restrict__ a2, int ntx, int nty) {
+             const float* __restrict__ bias, const bf16x8* __restrict__ w3pk,
+             __bf16* __restrict__ u, int ntx, int nty) {
   __shared__ uint4 brick[HP * 4];
   const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
@@ -496,74 +498,61 @@ conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wp
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1[r], acc[r], 0, 0, 0);
   }
-  store_act(acc, bias, a2, g, x0, y0, z0 + w, lx, ly, half);
-}
-
-// layer 3 and the guess, X = E + s_3 * (b3 + sum W3 * a2): the tile's layer-2 brick
-// (layout of layer 2's) and the BF16 weight pairs in LDS.  A pair of lanes owns one
-// (x, y) column of the tile's 4 output points in z, each lane half of the channels:
-// for each (dx, dy) it reads the column's 6 brick points once and the 3 taps' weights
-// once, and adds every brick point to the (up to 3) outputs it reaches; FP32 dot
-// products of BF16 pairs, the two halves summed by a lane exchange.
-__global__ void __launch_bounds__(256)
-conv3_lds_k(const uint4* __restrict__ a2, GnetFields f, Dims g, const double* __restrict__ sq,
-            const uint4* __restrict__ w3, const float* __restrict__ bias,
-            double* __restrict__ X, int ntx, int nty) {
-  static_assert(TX * TY * 2 == 256 && TZ == 4, "a lane pair per column of 4 points");
-  __shared__ uint4 brick[HP * 4];
-  __shared__ uint4 sw[27 * 4];
-  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-  const int tid = threadIdx.x;
-  if (tid < 27 * 4) sw[tid] = w3[tid];
-  stage_act_brick(a2, g, x0, y0, z0, brick, tid);
-  __syncthreads();
-  const int h = tid & 1, col = tid >> 1, lx = col % TX, ly = col / TX;
-  float acc[TZ];
+  // layer 3's per-tap products of the tile's points, u[t][p] = sum_c W3[t][c] a2[p][c]:
+  // the BF16 activations (bias, ReLU) of each group are the B operand of two MFMAs
+  // (k-slice s takes accumulator entries 8 s .. 8 s + 7, see layer3_channel) whose
+  // rows are the taps; u is stored as 27 BF16 planes over the grid
+  const bf16x8 A3[2] = {w3pk[lane], w3pk[64 + lane]};
+  const long long vol = g.vol();
 #pragma unroll
-  for (int z = 0; z < TZ; ++z) acc[z] = 0.0f;
-  for (int dy = 0; dy < 3; ++dy) {
+  for (int r = 0; r < 4; ++r) {
+    bf16x8 B3[2];
 #pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      uint4 w[3][2];   // taps (dz, dy, dx), this lane's two channel chunks
-#pragma unroll
-      for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int k = 0; k < 2; ++k) w[dz][k] = sw[(9 * dz + 3 * dy + dx) * 4 + 2 * h + k];
-#pragma unroll
-      for (int bz = 0; bz < TZ + 2; ++bz) {
-        const int n = (bz * HY + (ly + dy)) * HX + (lx + dx);
-        uint4 a[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) a[k] = brick[n * 4 + ((2 * h + k) ^ ((n >> 1) & 3))];
-#pragma unroll
-        for (int lz = 0; lz < TZ; ++lz) {
-          const int dz = bz - lz;
-          if (dz < 0 || dz > 2) continue;
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            acc[lz] = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a[k].x), as_bf16x2(w[dz][k].x), acc[lz], false);
-            acc[lz] = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a[k].y), as_bf16x2(w[dz][k].y), acc[lz], false);
-            acc[lz] = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a[k].z), as_bf16x2(w[dz][k].z), acc[lz], false);
-            acc[lz] = __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a[k].w), as_bf16x2(w[dz][k].w), acc[lz], false);
-          }
-        }
-      }
+    for (int v = 0; v < 16; ++v) {
+      const int ch = 8 * (v / 4) + 4 * half + v % 4;
+      B3[v / 8][v % 8] = (__bf16)fmaxf(acc[r][v] + bias[ch], 0.0f);
     }
-  }
-  const double s3 = 1.0 / inv_rms(sq, 3, g.vol());
-  const float b3 = bias[0];
+    f32x16 ut;
 #pragma unroll
-  for (int lz = 0; lz < TZ; ++lz) {
-    const float tot = b3 + (acc[lz] + lane_xor1(acc[lz]));
-    // lane 0 of the pair stores z 0, 1, lane 1 z 2, 3
-    if ((lz >> 1) != h) continue;
-    const int ox = x0 + lx, oy = y0 + ly, oz = z0 + lz;
+    for (int v = 0; v < 16; ++v) ut[v] = 0.0f;
+    ut = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3[0], B3[0], ut, 0, 0, 0);
+    ut = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3[1], B3[1], ut, 0, 0, 0);
+    const int ox = x0 + lx, oy = y0 + 2 * r + ly, oz = z0 + w;
     if (!inside(ox, oy, oz, g)) continue;
     const long long p = ox + (long long)g.x * (oy + (long long)g.y * oz);
-    const double e = 4.0 * f.h[0][p] - 6.0 * f.h[1][p] + 4.0 * f.h[2][p] - f.h[3][p];
-    X[p] = e + s3 * (double)tot;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int t = 8 * (v / 4) + 4 * half + v % 4;   // output row of entry v
+      if (t < 27) u[t * vol + p] = (__bf16)ut[v];
+    }
+  }
+}
+
+// layer 3's sum over the taps and the guess: X[q] = E + s_3 (b3 + sum_t u[t][q + o_t]),
+// o_t the offset of tap t (zero padding: taps outside the grid are left out); each
+// plane is read once over the grid, coalesced.  I is the type of the point index
+// (32-bit while the grid has fewer than 2^32 points: no 64-bit division).
+template <typename I>
+__global__ void __launch_bounds__(VB)
+layer3_gather_k(const __bf16* __restrict__ u, GnetFields f, Dims g, const double* __restrict__ sq,
+                const float* __restrict__ bias, double* __restrict__ X) {
+  const long long v = g.vol(), sy = g.x, sz = (long long)g.x * g.y;
+  const double s3 = 1.0 / inv_rms(sq, 3, v);
+  const I gx = (I)g.x, gy = (I)g.y;
+  for (long long o = (long long)blockIdx.x * VB + threadIdx.x; o < v; o += (long long)gridDim.x * VB) {
+    const I io = (I)o, row = io / gx;
+    const int ox = (int)(io - row * gx), oy = (int)(row % gy), oz = (int)(row / gy);
+    const bool in[3][3] = {{ox > 0, true, ox + 1 < g.x}, {oy > 0, true, oy + 1 < g.y},
+                           {oz > 0, true, oz + 1 < g.z}};
+    float acc = bias[0];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+      const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
+      if (!(in[0][dx] && in[1][dy] && in[2][dz])) continue;
+      acc += (float)u[t * v + o + (dx - 1) + (dy - 1) * sy + (dz - 1) * sz];
+    }
+    const double e = 4.0 * f.h[0][o] - 6.0 * f.h[1][o] + 4.0 * f.h[2][o] - f.h[3][o];
+    X[o] = e + s3 * (double)acc;
   }
 }
 
@@ -639,9 +628,14 @@ void gnet_infer_grid(const float* params, const void* wpk, GnetFields f, const i
   hipLaunchKernelGGL(conv1_mfma_k, grid, dim3(256), 0, st, f, g, sq,
                      (const bf16x8*)(pk + GNET_PACK2), params + GNET_B1, (__bf16*)a1, ntx, nty);
   hipLaunchKernelGGL(conv2_mfma_k, grid, dim3(256), 0, st, (const uint4*)a1, g,
-                     (const bf16x8*)pk, params + GNET_B2, (__bf16*)a2, ntx, nty);
-  hipLaunchKernelGGL(conv3_lds_k, grid, dim3(256), 0, st, (const uint4*)a2, f, g, sq,
-                     (const uint4*)(pk + GNET_PACK2 + GNET_PACK1), params + GNET_B3, X, ntx, nty);
+                     (const bf16x8*)pk, params + GNET_B2, (const bf16x8*)(pk + GNET_PACK2 + GNET_PACK1),
+                     (__bf16*)a2, ntx, nty);
+  if (g.vol() < (1ll << 32))
+    hipLaunchKernelGGL(layer3_gather_k<unsigned>, dim3(nbk(g.vol())), dim3(VB), 0, st,
+                       (const __bf16*)a2, f, g, sq, params + GNET_B3, X);
+  else
+    hipLaunchKernelGGL(layer3_gather_k<unsigned long long>, dim3(nbk(g.vol())), dim3(VB), 0, st,
+                       (const __bf16*)a2, f, g, sq, params + GNET_B3, X);
 }
 
 }  // namespace ga
