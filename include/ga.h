@@ -44,7 +44,8 @@ enum {
   GA_EDEVICE = -3,    /* a HIP call failed                                */
   GA_EGEOMETRY = -4,  /* det DF <= 0 at a quadrature point (Assumption 3) */
   GA_ENOCONV = -5,    /* PCG hit maxit; the last iterate is still written */
-  GA_EUNSTABLE = -6   /* a state norm became non-finite during stepping   */
+  GA_EUNSTABLE = -6   /* stepping diverged: a state norm became non-finite, or
+                         |U| + tau |V| grew past the bound of a stable step (ga_step) */
 };
 
 /* Arithmetic (precision is an addition to the paper, which computes in FP64).
@@ -285,8 +286,13 @@ int ga_init_state(ga_integrator* integ, const double* U0_dev, const double* V0_d
  * Taylor predictors, the k stage right-hand sides -K Y_j (eq. ho1), solves
  * the k mass systems together by PCG, and applies the updates of eq. ho2.
  *   iters_out  host array [nsteps][k] of PCG iterations, or NULL.
- * Returns GA_ENOCONV if a stage solve did not converge, GA_EUNSTABLE if the
- * displacement norm became non-finite.
+ * Returns GA_ENOCONV if a stage solve did not converge, GA_EUNSTABLE if U or V
+ * became non-finite or N = |U| + tau |V| (Euclidean norms of the coefficient
+ * vectors) grew by more than 10 * 1.05^nsteps over the call: a stable step keeps
+ * the discrete energy bounded, and growth from a small start (U0 = 0: N grows
+ * about like nsteps + 1 while nsteps * tau * omega << 1) stays within that bound
+ * for every nsteps, while an unstable mode grows geometrically.  ga_step_forced
+ * checks only for non-finite values (a load may make the state grow).
  */
 int ga_step(ga_integrator* integ, double* const* state_dev, int nsteps,
             int* iters_out, void* stream);

@@ -1358,6 +1358,46 @@ int step_once(ga_integrator* it, const StatePtrs& sp, const Coefs& cf, const dou
   return GA_OK;
 }
 
+// |U|^2 and |V|^2 of a state into scal slots dst, dst + 1 (enqueued, no host read)
+constexpr int GROWTH_SLOT = NSCAL * 63;
+void launch_state_norms(ga_patch* pt, const double* u, const double* v, double* dst,
+                        hipStream_t st) {
+  double* part = pt->red;
+  launch_dot_partial(1, u, u, pt->n_free, part, st);
+  launch_dot_partial(1, v, v, pt->n_free, part + RED_BLOCKS, st);
+  launch_sum_partials(2, part, dst, st);
+}
+
+// after nsteps unforced steps: non-finite U or V, or N = |U| + tau |V| grown by more
+// than 10 * 1.05^nsteps since the norms taken before the steps (slots +2, +3), is
+// GA_EUNSTABLE.  A stable step keeps the discrete energy bounded; N can still grow
+// from a small start (U0 = 0: N_n ~ (n + 1) N_0 while n tau omega << 1), which the
+// bound admits for every n, while an unstable mode grows geometrically.
+int check_growth(ga_integrator* it, const double* u, const double* v, int nsteps,
+                 hipStream_t st) {
+  ga_patch* pt = it->patch;
+  double* slot = pt->scal + GROWTH_SLOT;
+  launch_state_norms(pt, u, v, slot, st);
+  double h[4];
+  GA_TRY_HIP(hipMemcpyAsync(h, slot, sizeof(h), hipMemcpyDeviceToHost, st));
+  GA_TRY_HIP(hipStreamSynchronize(st));
+  if (!std::isfinite(h[0]) || !std::isfinite(h[1])) {
+    set_error("displacement or velocity became non-finite");
+    return GA_EUNSTABLE;
+  }
+  const double n1 = std::sqrt(h[0]) + it->tau * std::sqrt(h[1]);
+  const double n0 = std::sqrt(h[2]) + it->tau * std::sqrt(h[3]);
+  if (n0 > 0.0 && std::log(n1 / n0) > std::log(10.0) + nsteps * std::log(1.05)) {
+    char msg[160];
+    snprintf(msg, sizeof(msg),
+             "|U| + tau |V| grew by %.3g over %d steps: beyond the growth of a stable step",
+             n1 / n0, nsteps);
+    set_error(msg);
+    return GA_EUNSTABLE;
+  }
+  return GA_OK;
+}
+
 int check_finite(ga_patch* pt, const double* u, hipStream_t st) {
   double* part = pt->red;
   launch_dot_partial(1, u, u, pt->n_free, part, st);
@@ -1393,13 +1433,14 @@ int ga_step(ga_integrator* it, double* const* state, int nsteps, int* iters_out,
   int rc = step_setup(it, state, sp, cf);
   if (rc) return rc;
   hipStream_t st = S(stream);
+  launch_state_norms(it->patch, state[0], state[1], it->patch->scal + GROWTH_SLOT + 2, st);
   int iters[16];
   for (int step = 0; step < nsteps; ++step) {
     if ((rc = step_once(it, sp, cf, nullptr, iters, st))) return rc;
     if (iters_out)
       for (int j = 0; j < it->k; ++j) iters_out[(size_t)step * it->k + j] = iters[j];
   }
-  return check_finite(it->patch, state[0], st);
+  return check_growth(it, state[0], state[1], nsteps, st);
 }
 
 int ga_step_forced(ga_integrator* it, double* const* state, const double* const* forcing,

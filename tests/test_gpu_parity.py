@@ -397,6 +397,40 @@ def test_unstable_step_detected():
     assert e.value.code in (ga.GA_EUNSTABLE, ga.GA_ENOCONV)
 
 
+
+def test_unstable_growth_detected_while_finite():
+    # tau 1.5x above the limit of the order-4 scheme: the growth bound of ga_step
+    # (|U| + tau |V| at most 10 * 1.05^n times its value before the n steps) trips
+    # within the first call, while every value is still finite
+    pr = OracleProblem(3, 5, 2, seed=3)
+    pt = ga.ga_setup_patch(3, 5, 2, pr.ctrl)
+    tau = 1.5 * pr.tau(frac=1.0)
+    integ = ga.ga_integrator_create(pt, 2, 0.5, tau, rtol=1e-10)
+    U = _t(workloads.grf(5, 2, seed=4))
+    state = [torch.zeros_like(U) for _ in range(6)]
+    ga.ga_init_state(integ, U, torch.zeros_like(U), state)
+    with pytest.raises(ga.GAError) as e:
+        ga.ga_step(integ, state, 40)
+    assert e.value.code == ga.GA_EUNSTABLE and "grew" in str(e.value)
+    assert all(np.all(np.isfinite(_np(s_))) for s_ in state)
+
+
+def test_growth_bound_admits_stable_growth_from_rest():
+    # U0 = 0: |U| grows about linearly while n tau omega << 1, by a factor ~(n + 1);
+    # no call, of one step or of many, may trip the bound; and a stable run of the
+    # velocity-driven problem stays clear of it over many steps
+    pr = OracleProblem(3, 5, 2, seed=3)
+    pt = ga.ga_setup_patch(3, 5, 2, pr.ctrl)
+    tau = 0.01 * pr.tau(frac=1.0)
+    for calls, n in ((30, 1), (1, 60), (3, 200)):
+        integ = ga.ga_integrator_create(pt, 2, 0.5, tau, rtol=1e-10)
+        V = _t(workloads.grf(5, 2, seed=5))
+        state = [torch.zeros_like(V) for _ in range(6)]
+        ga.ga_init_state(integ, torch.zeros_like(V), V, state)
+        for _ in range(calls):
+            ga.ga_step(integ, state, n)
+        integ.close()
+
 # ---- mixed precision: FP32 inner PCG inside FP64 iterative refinement ----
 
 @pytest.mark.parametrize("n,p", [(6, 3), (5, 4), ((7, 4, 6), 2)])
