@@ -474,29 +474,36 @@ conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wp
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[r][v] = 0.0f;
-  // operands of k-step s = 2 t + kc (tap t, channel slice kc); the next step's are
-  // read before this step's four MFMAs are issued
-  auto load_step = [&](int st, bf16x8& A, bf16x8 (&B)[4]) {
-    const int t = st >> 1, kc = st & 1;
-    const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
+  // k-steps in column order: for each (dz, dx, channel slice kc) the 12 MFMAs of the
+  // three dy taps and four point groups read 9 brick rows (rows 2 r + ly + dy, which
+  // the groups share across dy) and 3 weight fragments; the next column's operands
+  // are read before this column's MFMAs are issued
+  auto load_col = [&](int cs, bf16x8 (&A)[3], bf16x8 (&B)[9]) {
+    const int kc = cs & 1, dx = (cs >> 1) % 3, dz = (cs >> 1) / 3;
     const int c = kc * 2 + half;
-    A = wpk[st * 64 + lane];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int n = ((w + dz) * HY + (2 * r + ly + dy)) * HX + (lx + dx);
+    for (int dy = 0; dy < 3; ++dy) A[dy] = wpk[((9 * dz + 3 * dy + dx) * 2 + kc) * 64 + lane];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      const int n = ((w + dz) * HY + (ly + m)) * HX + (lx + dx);
       const uint4 raw = brick[n * 4 + (c ^ ((n >> 1) & 3))];
-      __builtin_memcpy(&B[r], &raw, 16);
+      __builtin_memcpy(&B[m], &raw, 16);
     }
   };
-  bf16x8 A0, A1, B0[4], B1[4];
-  load_step(0, A0, B0);
-  for (int st = 0; st < 54; st += 2) {
-    load_step(st + 1, A1, B1);
+  auto mma_col = [&](const bf16x8 (&A)[3], const bf16x8 (&B)[9]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, B0[r], acc[r], 0, 0, 0);
-    if (st + 2 < 54) load_step(st + 2, A0, B0);
+    for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1[r], acc[r], 0, 0, 0);
+      for (int r = 0; r < 4; ++r)
+        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[dy], B[2 * r + dy], acc[r], 0, 0, 0);
+  };
+  bf16x8 A0[3], A1[3], B0[9], B1[9];
+  load_col(0, A0, B0);
+  for (int cs = 0; cs < 18; cs += 2) {
+    load_col(cs + 1, A1, B1);
+    mma_col(A0, B0);
+    if (cs + 2 < 18) load_col(cs + 2, A0, B0);
+    mma_col(A1, B1);
   }
   // layer 3's per-tap products of the tile's points, u[t][p] = sum_c W3[t][c] a2[p][c]:
   // the BF16 activations (bias, ReLU) of each group are the B operand of two MFMAs
