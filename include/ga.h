@@ -336,6 +336,27 @@ int ga_step_forced(ga_integrator* integ, double* const* state_dev, const double*
 int ga_stage_solution(ga_integrator* integ, int stage, int age, double* out_dev, void* stream);
 
 /*
+ * Checkpoint and resume (an addition).  The step state is the 3k state vectors
+ * (caller-owned), tau and the integrator settings, plus, in a guess mode other
+ * than GA_GUESS_ZERO, the ring of the last (up to 4) stage solutions that the
+ * guesses are formed from.  A checkpoint saves the state vectors and, for ages
+ * 0 .. nhist-1, ga_stage_solution of every stage; a resume creates an integrator
+ * with the same settings, restores the ring with ga_integrator_set_history and
+ * steps on from the saved state vectors.  With ga_patch_set_deterministic and
+ * FP64 solves the resumed steps are bitwise those of an uninterrupted run (the
+ * mixed solves' refinement passes also depend on the patch's adaptive inner
+ * iteration counts, so they agree to the solver tolerance).
+ *   ga_integrator_history: *nhist = number of stage solutions in the ring (0..4).
+ *   ga_integrator_set_history: hist_dev[age * k + stage], age 0 the newest,
+ *     nhist in 0..4 device vectors of n_free each (copied; the caller keeps
+ *     ownership); replaces the ring.  GA_EINVAL for GA_GUESS_ZERO integrators
+ *     when nhist > 0.
+ */
+int ga_integrator_history(const ga_integrator* integ, int* nhist);
+int ga_integrator_set_history(ga_integrator* integ, int nhist, const double* const* hist_dev,
+                              void* stream);
+
+/*
  * Learned initial guess (not in the paper; an addition on top of its zero
  * initial guess).  From the last four solutions H1..H4 of stage j (newest
  * first) form the backward differences

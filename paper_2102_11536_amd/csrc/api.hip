@@ -1231,6 +1231,36 @@ int ga_integrator_set_net(ga_integrator* it, int stage, ga_gnet* net) {
   return GA_OK;
 }
 
+int ga_integrator_history(const ga_integrator* it, int* nhist) {
+  if (!it || !nhist) { set_error("null argument"); return GA_EINVAL; }
+  *nhist = it->nhist;
+  return GA_OK;
+}
+
+int ga_integrator_set_history(ga_integrator* it, int nhist, const double* const* hist,
+                              void* stream) {
+  if (!it || (nhist > 0 && !hist)) { set_error("null argument"); return GA_EINVAL; }
+  if (nhist < 0 || nhist > 4) { set_error("nhist must be in 0..4"); return GA_EINVAL; }
+  if (nhist > 0 && it->guess == GA_GUESS_ZERO) {
+    set_error("a GA_GUESS_ZERO integrator keeps no history");
+    return GA_EINVAL;
+  }
+  const int k = it->k;
+  for (int i = 0; i < nhist * k; ++i)
+    if (!hist[i]) { set_error("null history vector"); return GA_EINVAL; }
+  const size_t n = it->patch->n_free;
+  hipStream_t st = S(stream);
+  // ring slots: the newest at head = nhist - 1, age a at head - a
+  for (int a = 0; a < nhist; ++a)
+    for (int j = 0; j < k; ++j)
+      launch_copy(it->H + ((size_t)(nhist - 1 - a) * k + j) * n, hist[a * k + j], n, st);
+  it->head = nhist > 0 ? nhist - 1 : -1;
+  it->nhist = nhist;
+  if (nhist > 0) launch_copy(it->X, it->H + (size_t)it->head * k * n, (size_t)k * n, st);
+  it->have_prev = nhist > 0;
+  return check_launch(0, "history restore");
+}
+
 int ga_stage_solution(ga_integrator* it, int stage, int age, double* out, void* stream) {
   if (!it || !out) { set_error("null argument"); return GA_EINVAL; }
   if (stage < 0 || stage >= it->k || age < 0 || age > 3) { set_error("stage or age out of range"); return GA_EINVAL; }

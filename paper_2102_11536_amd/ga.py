@@ -25,7 +25,7 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_integrator_set_damping", "ga_stage_times", "ga_init_state_forced", "ga_step_forced",
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
-           "ga_integrator_set_net", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
+           "ga_integrator_set_net", "ga_integrator_history", "ga_integrator_set_history", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
            "ga_batch_tune", "ga_batch_set_precision", "ga_batch_set_tau", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers", "ga_patch_set_layers", "ga_patch_set_deterministic",
            "ga_stability_limit2", "ga_integrator_set_rho", "ga_wave1d_create", "ga_wave1d_destroy",
            "ga_wave1d_info", "ga_wave1d_load_sine", "ga_wave1d_apply", "ga_wave1d_init_state",
@@ -98,6 +98,8 @@ def load_library(path=LIB_PATH):
     lib.ga_gnet_adam.argtypes = [vp, dp, ctypes.c_float, vp]
     lib.ga_gnet_infer.argtypes = [vp, vp, ctypes.POINTER(vp), dp, vp]
     lib.ga_integrator_set_net.argtypes = [vp, i, vp]
+    lib.ga_integrator_history.argtypes = [vp, ctypes.POINTER(i)]
+    lib.ga_integrator_set_history.argtypes = [vp, i, ctypes.POINTER(vp), vp]
     lp = ctypes.POINTER(ctypes.c_longlong)
     lib.ga_batch_create.argtypes = [i, ctypes.POINTER(vp), i, d, d, d, i, ctypes.POINTER(vp)]
     lib.ga_batch_destroy.argtypes = [vp]
@@ -490,6 +492,19 @@ def ga_gnet_adam(net, grad, lr):
 
 def ga_gnet_infer(net, patch, hist, x):
     _check(_lib.ga_gnet_infer(net.h, patch.h, _hist_array(patch, hist), _ptr(x, patch.n_free), _stream()))
+
+
+def ga_integrator_history(integ):
+    n = ctypes.c_int()
+    _check(_lib.ga_integrator_history(integ.h, ctypes.byref(n)))
+    return n.value
+
+
+def ga_integrator_set_history(integ, hist):
+    """hist[age][stage]: device vectors of n_free, age 0 the newest."""
+    flat = [h for per_age in hist for h in per_age]
+    arr = (ctypes.c_void_p * max(1, len(flat)))(*[_ptr(t, integ.patch.n_free) for t in flat])
+    _check(_lib.ga_integrator_set_history(integ.h, len(hist), arr if flat else None, _stream()))
 
 
 def ga_integrator_set_net(integ, stage, net):

@@ -96,3 +96,59 @@ def test_deterministic_solves_and_steps_bitwise():
     for s in range(3 * k):
         d = sh[s].cpu().numpy() - ora[s - 2]
         assert np.sqrt(d @ (M @ d)) <= 1e-10 * max(np.sqrt(ora[s - 2] @ (M @ ora[s - 2])), 1e-300)
+
+
+@pytest.mark.parametrize("guess", [ga.GA_GUESS_ZERO, ga.GA_GUESS_EXTRAP])
+def test_checkpoint_resume_is_bitwise(guess):
+    # checkpoint after 5 of 9 steps (state vectors and the ring of past stage solutions
+    # copied to host memory), resume in a fresh integrator: the last 4 steps are
+    # bitwise those of the uninterrupted run (deterministic mode, FP64 solves)
+    _say("checkpoint/resume", guess)
+    n, p, k = (7, 6, 5), 3, 2
+    pr = OracleProblem(3, n, p, seed=12)
+    pt = ga.ga_setup_patch(3, n, p, pr.ctrl)
+    ga.ga_patch_set_deterministic(pt, 1)
+    tau = pr.tau()
+    U0 = _t(workloads.grf(n, p, seed=6))
+    nf = pt.n_free
+
+    def fresh():
+        return ga.ga_integrator_create(pt, k, 0.5, tau, rtol=1e-10, guess=guess)
+
+    def started():
+        integ = fresh()
+        st = [torch.zeros(nf, dtype=torch.float64, device=DEV) for _ in range(3 * k)]
+        ga.ga_init_state(integ, U0, torch.zeros_like(U0), st)
+        return integ, st
+
+    integ, st = started()
+    ga.ga_step(integ, st, 9)
+    ref = [s_.cpu().numpy() for s_ in st]
+    integ.close()
+
+    integ, st = started()
+    ga.ga_step(integ, st, 5)
+    ck_state = [s_.cpu().numpy() for s_ in st]
+    nh = ga.ga_integrator_history(integ)
+    assert nh == (0 if guess == ga.GA_GUESS_ZERO else 4)
+    ck_hist = []
+    for a in range(nh):
+        row = []
+        for j in range(k):
+            out = torch.empty(nf, dtype=torch.float64, device=DEV)
+            ga.ga_stage_solution(integ, j, a, out)
+            row.append(out.cpu().numpy())
+        ck_hist.append(row)
+    integ.close()
+
+    integ = fresh()
+    st = [_t(v) for v in ck_state]
+    ga.ga_integrator_set_history(integ, [[_t(v) for v in row] for row in ck_hist])
+    assert ga.ga_integrator_history(integ) == nh
+    ga.ga_step(integ, st, 4)
+    for s_, r_ in zip(st, ref):
+        assert np.array_equal(s_.cpu().numpy(), r_)
+    integ.close()
+    if guess == ga.GA_GUESS_ZERO:
+        with pytest.raises(ga.GAError):
+            ga.ga_integrator_set_history(fresh(), [[_t(ck_state[0]), _t(ck_state[0])]])
