@@ -1363,7 +1363,11 @@ int step_once(ga_integrator* it, const StatePtrs& sp, const Coefs& cf, const dou
     for (int h = 0; h < nh; ++h)
       for (int j = 0; j < k; ++j)
         hp[h * 4 + j] = it->H + ((size_t)((it->head - h + 4) % 4) * k + j) * n;
-    launch_extrap(k, nh, hp, it->X, n, st);
+    // stages with a net get their guess (which contains the extrapolation) from the
+    // net's kernels alone; the others take the extrapolation
+    bool all_nets = it->guess == GA_GUESS_LEARNED && it->nhist == 4;
+    for (int j = 0; j < k && all_nets; ++j) all_nets = it->nets[j] != nullptr;
+    if (!all_nets) launch_extrap(k, nh, hp, it->X, n, st);
     if (it->guess == GA_GUESS_LEARNED && it->nhist == 4) {
       for (int j = 0; j < k; ++j) {
         if (!it->nets[j]) continue;
