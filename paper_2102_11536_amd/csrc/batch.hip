@@ -14,8 +14,11 @@
 //     systems (stage j, patch r) keep their own scalars and stop on their own.
 // One PCG iteration is a fixed sequence of launches; it is captured once in a
 // hipGraph (on a stream the batch owns, ordered after the caller's stream by
-// events) and replayed, the host reading the per-system convergence flags
-// between replays.  ga_batch_tune times the element layers per tile (ze) and
+// events) and replayed: as many times as the previous solve of the same systems
+// needed before the host first reads the per-system convergence flags, then once per
+// read (the launches of an iteration skip patches whose systems have all converged,
+// and a converged system's scalars stop its updates, so extra replays change
+// nothing).  ga_batch_tune times the element layers per tile (ze) and
 // the number of workgroups of the tile-queue launches and keeps the fastest.
 #include <hip/hip_runtime.h>
 
