@@ -187,8 +187,20 @@ int ga_patch_set_pinv(ga_patch* patch, int mode);
  *                 own), then reads the flags once and continues per iteration
  *                 only if a system is still active.  2-D and 3-D patches with
  *                 the banded preconditioner; otherwise the host control is used.
+ *   GA_CG_FUSED   single-reduction (Chronopoulos-Gear) PCG under the same device
+ *                 control: six launches per iteration instead of eleven: the mass
+ *                 apply w = M z, one reduction for z^T w, one kernel that completes
+ *                 it in every workgroup, takes the alpha/beta step and updates p,
+ *                 s = M p, x and r, and the three preconditioner passes, the last of
+ *                 which sums r^T z and applies the stopping test (its last
+ *                 workgroup completes the sum).  The same iterates as GA_CG_DEVICE
+ *                 in exact arithmetic and the same stopping test.  3-D patches with
+ *                 the banded preconditioner (otherwise GA_CG_DEVICE's rules apply).
  * ga_cg_stats: iterations enqueued ahead so far and host reads of the flags.
  */
+enum { GA_CG_HOST = 0, GA_CG_DEVICE = 1, GA_CG_FUSED = 2 };
+int ga_patch_set_cg(ga_patch* patch, int mode);
+int ga_cg_stats(const ga_patch* patch, long long* spec_iters, long long* host_checks);
 /*
  * ga_patch_tune -- autotuner for the operator launches of a 3-D patch: for the
  * mass and the stiffness apply with nrhs (1..3) right-hand sides, times `reps`
@@ -214,18 +226,7 @@ int ga_patch_set_layers(ga_patch* patch, int ze_mass, int ze_stiff);
  * more along z when a column is split into z ranges), launched one after the other:
  * slower (fewer tiles per launch).  Single-patch launches only (not the batch). */
 int ga_patch_set_deterministic(ga_patch* patch, int on);
-/*   GA_CG_FUSED   single-reduction (Chronopoulos-Gear) PCG under the same device
- *                 control: six launches per iteration instead of eleven: the mass
- *                 apply w = M z, one reduction for z^T w, one kernel that completes
- *                 it in every workgroup, takes the alpha/beta step and updates p,
- *                 s = M p, x and r, and the three preconditioner passes, the last of
- *                 which sums r^T z and applies the stopping test (its last
- *                 workgroup completes the sum).  The same iterates as GA_CG_DEVICE
- *                 in exact arithmetic and the same stopping test.  3-D patches with
- *                 the banded preconditioner (otherwise GA_CG_DEVICE's rules apply). */
-enum { GA_CG_HOST = 0, GA_CG_DEVICE = 1, GA_CG_FUSED = 2 };
-int ga_patch_set_cg(ga_patch* patch, int mode);
-int ga_cg_stats(const ga_patch* patch, long long* spec_iters, long long* host_checks);
+
 
 /*
  * ga_mass_solve -- PCG for M x_j = b_j, j < nrhs (Sec. 5.6; solver settings of
