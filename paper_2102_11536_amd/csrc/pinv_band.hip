@@ -104,6 +104,27 @@ __device__ __forceinline__ void band_solve(const S* src, S* dst, long long strid
   }
 }
 
+// copy n table entries to LDS with nthreads threads, 8 loads of each thread in flight
+// before its stores (a wait per load would serialise the copy)
+template <typename S>
+__device__ __forceinline__ void copy_table(S* dst, const S* __restrict__ src, int n, int tid,
+                                           int nthreads) {
+  constexpr int K = 8;
+  for (int e0 = 0; e0 < n; e0 += K * nthreads) {
+    S v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = e0 + k * nthreads + tid;
+      v[k] = e < n ? src[e] : (S)0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = e0 + k * nthreads + tid;
+      if (e < n) dst[e] = v[k];
+    }
+  }
+}
+
 #ifndef GA_BAND_WT
 #define GA_BAND_WT 256
 #endif
@@ -129,7 +150,7 @@ band_row_k(const S* __restrict__ in, S* __restrict__ out, const S* __restrict__ 
   S* pl = reinterpret_cast<S*>(smem_raw);
   S* c0 = pl + (size_t)NL * RS;              // factor table, (L0 + P) x (P + 1)
   const int tid = threadIdx.x;
-  for (int e = tid; e < (L0 + P) * (P + 1); e += WT) c0[e] = cb0[e];
+  copy_table(c0, cb0, (L0 + P) * (P + 1), tid, WT);
   const long long r0 = (long long)blockIdx.x * NL;
   const int nrow = (int)min((long long)NL, rows - r0);
   const int cnt = nrow * L0;
@@ -191,7 +212,7 @@ band_col_k(const S* __restrict__ in, S* __restrict__ out, const S* __restrict__ 
   extern __shared__ unsigned char smem_raw[];
   S* ct = reinterpret_cast<S*>(smem_raw);       // factor table, (L + P) x (P + 1)
   const int lane = threadIdx.x;
-  for (int e = lane; e < (L + P) * (P + 1); e += CT) ct[e] = cb[e];
+  copy_table(ct, cb, (L + P) * (P + 1), lane, CT);
   __syncthreads();
   const long long c = (long long)blockIdx.x * CT + lane;
   if (c >= nlines) return;
@@ -215,7 +236,7 @@ band_col_cg_k(const double* __restrict__ in, double* __restrict__ out, const dou
   __shared__ double sh[1];
   __shared__ int done;
   const int lane = threadIdx.x;
-  for (int e = lane; e < (L + P) * (P + 1); e += CT) ct[e] = cb[e];
+  copy_table(ct, cb, (L + P) * (P + 1), lane, CT);
   __syncthreads();
   const long long c = (long long)blockIdx.x * CT + lane;
   double acc = 0.0;
