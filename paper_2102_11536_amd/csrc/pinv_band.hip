@@ -132,27 +132,27 @@ __device__ __forceinline__ void copy_table(S* dst, const S* __restrict__ src, in
 #define GA_BAND_NL 64
 #endif
 constexpr int WT = GA_BAND_WT;  // threads per workgroup: all stage and store, NL sweep
-constexpr int NL = GA_BAND_NL;  // lines per workgroup (one per sweeping thread)
+constexpr int NL = GA_BAND_NL;  // fewest lines per workgroup (one per sweeping thread)
 
-// x axis: a workgroup stages NL consecutive rows (NL * L0 contiguous coefficients of
-// one right-hand side) in LDS with coalesced loads by all WT threads, NL threads
+// x axis: a workgroup stages nl consecutive rows (nl * L0 contiguous coefficients of
+// one right-hand side) in LDS with coalesced loads by all WT threads, nl threads
 // solve one row each, and all threads write the rows back; the input scaling si is
 // fused into the load and the output scaling so (if given) into the store
 template <int P, typename S>
 __global__ void __launch_bounds__(WT)
 band_row_k(const S* __restrict__ in, S* __restrict__ out, const S* __restrict__ cb0, int L0,
            long long rows, long long n_free, const S* __restrict__ si, const S* __restrict__ so,
-           const double* __restrict__ gate) {
+           const double* __restrict__ gate, int nl) {
   // with a gate, a converged right-hand side (blockIdx.y) is skipped
   if (gate && gate[(size_t)blockIdx.y * NSCAL + S_ACTIVE] == 0.0) return;
   extern __shared__ unsigned char smem_raw[];
   const int RS = L0 | 1;  // odd row stride
   S* pl = reinterpret_cast<S*>(smem_raw);
-  S* c0 = pl + (size_t)NL * RS;              // factor table, (L0 + P) x (P + 1)
+  S* c0 = pl + (size_t)nl * RS;              // factor table, (L0 + P) x (P + 1)
   const int tid = threadIdx.x;
   copy_table(c0, cb0, (L0 + P) * (P + 1), tid, WT);
-  const long long r0 = (long long)blockIdx.x * NL;
-  const int nrow = (int)min((long long)NL, rows - r0);
+  const long long r0 = (long long)blockIdx.x * nl;
+  const int nrow = (int)min((long long)nl, rows - r0);
   const int cnt = nrow * L0;
   const long long base = r0 * L0;             // offset within one right-hand side
   const S* src = in + (size_t)blockIdx.y * n_free + base;
@@ -255,11 +255,46 @@ band_col_cg_k(const double* __restrict__ in, double* __restrict__ out, const dou
 
 constexpr size_t LDS_MAX_BYTES = 152 * 1024;
 
+int device_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+  }
+  return n;
+}
+
+size_t row_lds_bytes(int nl, long long L0, int p, size_t elem) {
+  return ((size_t)nl * (L0 | 1) + (size_t)(L0 + p) * (p + 1)) * elem;
+}
+
+// rows per workgroup of the x pass: the fewest resident rounds of workgroups (LDS
+// bounds the workgroups per CU), then the fewest rows (NL..WT, steps of 8); e.g. 72 for
+// two FP64 right-hand sides at L0 = 129, where 64 leaves a second round of 10
+int pick_nl(long long rows, int nr, long long L0, int p, size_t elem) {
+  const long long slots_cu_lds = 160 * 1024;
+  int best = NL;
+  long long best_rounds = -1;
+  for (int nl = NL; nl <= WT; nl += 8) {
+    const size_t bytes = row_lds_bytes(nl, L0, p, elem);
+    if (bytes > LDS_MAX_BYTES) break;
+    const long long per_cu = std::max<long long>(1, slots_cu_lds / (long long)bytes);
+    const long long nblk = (rows + nl - 1) / nl * nr;
+    const long long rounds = (nblk + per_cu * device_cus() - 1) / (per_cu * device_cus());
+    if (best_rounds < 0 || rounds < best_rounds) { best_rounds = rounds; best = nl; }
+  }
+  return best;
+}
+
 template <int P, typename S>
 int launch_p(int dim, const int* mf, int nr, const S* r, S* z, S* t0, S* t1, const S* const* cb,
              const S* s, long long n_free, hipStream_t st, const double* gate) {
   const long long L0 = mf[0], L1 = mf[1], L2 = dim == 3 ? mf[2] : 1;
-  const size_t row_bytes = ((size_t)NL * (L0 | 1) + (size_t)(L0 + P) * (P + 1)) * sizeof(S);
+  const long long rows = L1 * L2;
+  const int nl = pick_nl(rows, nr, L0, P, sizeof(S));
+  const size_t row_bytes = row_lds_bytes(nl, L0, P, sizeof(S));
   const long long Lc = std::max(L1, L2);
   const size_t col_bytes = (size_t)(Lc + P) * (P + 1) * sizeof(S);
   if (row_bytes > LDS_MAX_BYTES || col_bytes > LDS_MAX_BYTES) return 1;
@@ -271,10 +306,10 @@ int launch_p(int dim, const int* mf, int nr, const S* r, S* z, S* t0, S* t1, con
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX_BYTES);
     attr = true;
   }
-  const long long rows = L1 * L2;
   // x: r -> t1 (input scaling)
-  hipLaunchKernelGGL((band_row_k<P, S>), dim3((unsigned)((rows + NL - 1) / NL), nr), dim3(WT),
-                     row_bytes, st, r, t1, cb[0], (int)L0, rows, n_free, s, (const S*)nullptr, gate);
+  hipLaunchKernelGGL((band_row_k<P, S>), dim3((unsigned)((rows + nl - 1) / nl), nr), dim3(WT),
+                     row_bytes, st, r, t1, cb[0], (int)L0, rows, n_free, s, (const S*)nullptr, gate,
+                     nl);
   // y: t1 -> (3-D: t0; 2-D: z with the output scaling)
   const long long ny = L0 * L2;
   hipLaunchKernelGGL((band_col_k<P, S>), dim3((unsigned)((ny + CT - 1) / CT), nr), dim3(CT),
@@ -322,7 +357,9 @@ int band_cgcg_p(const int* mf, int nr, const double* r, double* z, double* t0, d
                 const double* const* cb, const double* s, long long n_free, hipStream_t st,
                 const double* gate, const CgFuse& f) {
   const long long L0 = mf[0], L1 = mf[1], L2 = mf[2];
-  const size_t row_bytes = ((size_t)NL * (L0 | 1) + (size_t)(L0 + P) * (P + 1)) * sizeof(double);
+  const long long rows = L1 * L2;
+  const int nl = pick_nl(rows, nr, L0, P, sizeof(double));
+  const size_t row_bytes = row_lds_bytes(nl, L0, P, sizeof(double));
   const size_t col_bytes = (size_t)(std::max(L1, L2) + P) * (P + 1) * sizeof(double);
   if (row_bytes > LDS_MAX_BYTES || col_bytes > LDS_MAX_BYTES) return 1;
   const long long nz = L0 * L1;
@@ -337,10 +374,9 @@ int band_cgcg_p(const int* mf, int nr, const double* r, double* z, double* t0, d
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX_BYTES);
     attr = true;
   }
-  const long long rows = L1 * L2;
-  hipLaunchKernelGGL((band_row_k<P, double>), dim3((unsigned)((rows + NL - 1) / NL), nr), dim3(WT),
+  hipLaunchKernelGGL((band_row_k<P, double>), dim3((unsigned)((rows + nl - 1) / nl), nr), dim3(WT),
                      row_bytes, st, r, t1, cb[0], (int)L0, rows, n_free, s, (const double*)nullptr,
-                     gate);
+                     gate, nl);
   const long long ny = L0 * L2;
   hipLaunchKernelGGL((band_col_k<P, double>), dim3((unsigned)((ny + CT - 1) / CT), nr), dim3(CT),
                      (size_t)(L1 + P) * (P + 1) * sizeof(double), st, t1, t0, cb[1], ny, L0, L0 * L1,
