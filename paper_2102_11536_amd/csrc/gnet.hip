@@ -25,6 +25,7 @@
 //   The layer-1 activations are stored channels-last [point][32] (64 bytes per
 //   point), the tap planes in 54 bytes per point.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "gnet.h"
 
@@ -490,21 +491,33 @@ conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wp
       __builtin_memcpy(&B[m], &raw, 16);
     }
   };
-  auto mma_col = [&](const bf16x8 (&A)[3], const bf16x8 (&B)[9]) {
+  // point groups with a row inside the grid (the last tile along y holds one row), and
+  // waves whose z-plane lies outside the grid (the last tile along z holds one plane)
+  // skip their MFMAs: the test is uniform over the wave, and no barrier follows
+  const int ngr = max(0, min(4, (g.y - y0 + 1) / 2));
+  if (z0 + w >= g.z) return;
+  // the loop is compiled once for four groups (every tile but the last along y) and
+  // once with the group test (the last), so the common case keeps a branch-free body
+  auto run = [&](auto full) {
+    auto mma_col = [&](const bf16x8 (&A)[3], const bf16x8 (&B)[9]) {
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
+      for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[dy], B[2 * r + dy], acc[r], 0, 0, 0);
+        for (int r = 0; r < 4; ++r)
+          if (decltype(full)::value || r < ngr)
+            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[dy], B[2 * r + dy], acc[r], 0, 0, 0);
+    };
+    bf16x8 A0[3], A1[3], B0[9], B1[9];
+    load_col(0, A0, B0);
+    for (int cs = 0; cs < 18; cs += 2) {
+      load_col(cs + 1, A1, B1);
+      mma_col(A0, B0);
+      if (cs + 2 < 18) load_col(cs + 2, A0, B0);
+      mma_col(A1, B1);
+    }
   };
-  bf16x8 A0[3], A1[3], B0[9], B1[9];
-  load_col(0, A0, B0);
-  for (int cs = 0; cs < 18; cs += 2) {
-    load_col(cs + 1, A1, B1);
-    mma_col(A0, B0);
-    if (cs + 2 < 18) load_col(cs + 2, A0, B0);
-    mma_col(A1, B1);
-  }
+  if (ngr == 4) run(std::true_type{});
+  else run(std::false_type{});
   // layer 3's per-tap products of the tile's points, u[t][p] = sum_c W3[t][c] a2[p][c]:
   // the BF16 activations (bias, ReLU) of each group are the B operand of two MFMAs
   // (k-slice s takes accumulator entries 8 s .. 8 s + 7, see layer3_channel) whose
@@ -513,6 +526,7 @@ conv2_mfma_k(const uint4* __restrict__ a1, Dims g, const bf16x8* __restrict__ wp
   const long long vol = g.vol();
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
+    if (r >= ngr) continue;
     bf16x8 B3[2];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
