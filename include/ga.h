@@ -372,10 +372,14 @@ int ga_integrator_set_history(ga_integrator* integ, int nhist, const double* con
  *   W1[27][4][32] b1[32] W2[27][32][32] b2[32] W3[27][32][1] b3[1],
  *   tap t = 9 kz + 3 ky + kx; W[t][ci][co] multiplies input channel ci at
  *   offset (kx-1, ky-1, kz-1) in the output channel co.
- * Training runs in FP32 on crops of S^3 points (the target is the interior
- * (S-6)^3); inference runs in BF16 (weights and activations) with FP32
- * accumulation, layer 2 on MFMA.  A net owns its parameters, Adam moments and
- * work buffers; calls that use one net on overlapping streams race.
+ * Training runs on crops of S^3 points (the target is the interior (S-6)^3)
+ * with FP32 master weights, activations and gradients; by default (GA_BF16)
+ * layer 2's forward, backward-data and backward-weight convolutions, 55,296 of
+ * the 63,936 flops per point in each pass, run on the matrix cores with BF16
+ * operands and FP32 accumulation, the rest in FP32.  Inference runs in BF16
+ * (weights and activations) with FP32 accumulation, all three layers on MFMA.
+ * A net owns its parameters, Adam moments and work buffers; calls that use one
+ * net on overlapping streams race.
  */
 #define GA_GNET_NPARAM 32033
 /* params_host: GA_GNET_NPARAM floats, or NULL for all-zero parameters. */
@@ -383,6 +387,12 @@ int ga_gnet_create(const float* params_host, ga_gnet** out);
 int ga_gnet_destroy(ga_gnet* net);
 int ga_gnet_set_params(ga_gnet* net, const float* params_host);  /* resets Adam */
 int ga_gnet_get_params(ga_gnet* net, float* params_host);
+/*
+ * ga_gnet_set_train_prec -- arithmetic of ga_gnet_forward and ga_gnet_loss_grad:
+ * GA_BF16 (the default; layer 2 on BF16 MFMA with FP32 accumulation) or GA_FP32
+ * (every convolution in FP32 on the vector units).  Other values: GA_EINVAL.
+ */
+int ga_gnet_set_train_prec(ga_gnet* net, int prec);
 /*
  * ga_gnet_make_batch -- training crops from one stage of a 3-D patch:
  *   in_dev  [nb][4][S^3]  D_c / s_c at grid points origin_b + (0..S-1)^3, zero
@@ -396,7 +406,7 @@ int ga_gnet_make_batch(ga_gnet* net, ga_patch* patch, const double* const* hist_
                        const double* x_dev, int nb, int S, const int* origins_host,
                        float* in_dev, float* tgt_dev, void* stream);
 /*
- * ga_gnet_forward -- FP32 forward pass on crops: out_dev [nb][(S-6)^3].
+ * ga_gnet_forward -- forward pass on crops: out_dev [nb][(S-6)^3] (FP32 output).
  * grid3 (host, 3 ints) and origins_host (as in ga_gnet_make_batch) place the
  * crops in the grid: layer-1 and layer-2 activations outside it are zero.
  */

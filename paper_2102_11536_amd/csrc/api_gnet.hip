@@ -1,5 +1,5 @@
-// C ABI of the learned initial guess: net handles, training crops, FP32
-// forward/gradient/Adam, BF16 whole-grid inference.
+// C ABI of the learned initial guess: net handles, training crops, forward/gradient
+// (FP32, or layer 2 on BF16 MFMA) and Adam, BF16 whole-grid inference.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -28,18 +28,30 @@ int grow(void** p, size_t* have, size_t need) {
 }
 
 // training buffers: a1 [nb][32][S1^3], a2 [nb][32][S2^3], out/d3 [nb][S3^3],
-// d2 like a2, d1 like a1
+// d2 like a2, d1 like a1, the weight gradients' partial sums; for BF16 training
+// also the packed W2 (first, 16-byte aligned) and layer 2's partial sums
 struct TrainBufs {
-  float *a1, *a2, *out, *d3, *d2, *d1;
+  float *a1, *a2, *out, *d3, *d2, *d1, *wpart;
+  void* tpk = nullptr;
+  float* part = nullptr;
 };
 
 int train_bufs(ga_gnet* net, int nb, int S, TrainBufs* b) {
   const size_t v1 = (size_t)(S - 2) * (S - 2) * (S - 2), v2 = (size_t)(S - 4) * (S - 4) * (S - 4),
                v3 = (size_t)(S - 6) * (S - 6) * (S - 6);
   const size_t n1 = (size_t)nb * 32 * v1, n2 = (size_t)nb * 32 * v2, n3 = (size_t)nb * v3;
-  int rc = grow((void**)&net->tw, &net->tw_bytes, (2 * n1 + 2 * n2 + 2 * n3) * sizeof(float));
+  const bool bf = net->train_prec == GA_BF16;
+  const size_t npk = bf ? 2 * GNET_PACK2 * sizeof(short) : 0;   // a multiple of 16 bytes
+  const size_t npart = bf ? (size_t)gnet_train_part_floats(nb, S) : 0;
+  const size_t nw = (size_t)gnet_train_wpart_floats();
+  int rc = grow((void**)&net->tw, &net->tw_bytes,
+                npk + (npart + nw + 2 * n1 + 2 * n2 + 2 * n3) * sizeof(float));
   if (rc) return rc;
-  float* q = net->tw;
+  char* base = (char*)net->tw;
+  if (bf) b->tpk = base;
+  float* q = (float*)(base + npk);
+  if (bf) { b->part = q; q += npart; }
+  b->wpart = q; q += nw;
   b->a1 = q; q += n1;
   b->a2 = q; q += n2;
   b->out = q; q += n3;
@@ -164,6 +176,13 @@ int ga_gnet_get_params(ga_gnet* net, float* params_host) {
   return GA_OK;
 }
 
+int ga_gnet_set_train_prec(ga_gnet* net, int prec) {
+  if (!net) { set_error("null net"); return GA_EINVAL; }
+  if (prec != GA_FP32 && prec != GA_BF16) { set_error("training precision must be GA_FP32 or GA_BF16"); return GA_EINVAL; }
+  net->train_prec = prec;
+  return GA_OK;
+}
+
 int ga_gnet_make_batch(ga_gnet* net, ga_patch* pt, const double* const* hist, const double* x,
                        int nb, int cs, const int* origins, float* in, float* tgt, void* stream) {
   if (!net || !pt || !hist || !x || !in || !tgt) { set_error("null argument"); return GA_EINVAL; }
@@ -189,7 +208,7 @@ int ga_gnet_forward(ga_gnet* net, int nb, int cs, const int* grid3, const int* o
   hipStream_t st = S(stream);
   TrainBufs b;
   if ((rc = upload_origins(net, nb, origins, st)) || (rc = train_bufs(net, nb, cs, &b))) return rc;
-  gnet_forward_batch(net->params, in, nb, cs, grid3, net->org, b.a1, b.a2, out, st);
+  gnet_forward_batch(net->params, in, nb, cs, grid3, net->org, b.a1, b.a2, out, b.tpk, st);
   return check_launch(0, "net forward");
 }
 
@@ -202,11 +221,12 @@ int ga_gnet_loss_grad(ga_gnet* net, int nb, int cs, const int* grid3, const int*
   hipStream_t st = S(stream);
   TrainBufs b;
   if ((rc = upload_origins(net, nb, origins, st)) || (rc = train_bufs(net, nb, cs, &b))) return rc;
-  gnet_forward_batch(net->params, in, nb, cs, grid3, net->org, b.a1, b.a2, b.out, st);
+  gnet_forward_batch(net->params, in, nb, cs, grid3, net->org, b.a1, b.a2, b.out, b.tpk, st);
   const long long nt = (long long)nb * (cs - 6) * (cs - 6) * (cs - 6);
   double* mp = net->part + 4 * RED_BLOCKS;
   gnet_mse_grad(b.out, tgt, nt, b.d3, mp, MSE_PARTS, st);
-  gnet_backward_batch(net->params, in, nb, cs, b.a1, b.a2, b.d3, b.d2, b.d1, grad, st);
+  gnet_backward_batch(net->params, in, nb, cs, b.a1, b.a2, b.d3, b.d2, b.d1, grad, b.tpk, b.part,
+                      b.wpart, st);
   if ((rc = check_launch(0, "net loss and gradient"))) return rc;
   if (loss_out) {
     std::vector<double> h(MSE_PARTS);

@@ -189,5 +189,6 @@ struct ga_gnet {
   double* scal = nullptr;     // [0..3]: sums of squares of the history differences D_0..D_3
   double* part = nullptr;     // reduction partials
   void* iw = nullptr;         // inference activations (BF16, channels-last)
+  int train_prec = GA_BF16;   // GA_BF16: layer 2 of training on MFMA; GA_FP32: all FP32
   size_t iw_bytes = 0;
 };

@@ -28,13 +28,21 @@ struct GnetFields {
   const double* x;
 };
 
-// training (FP32, channel-major crops [b][c][S^3], valid convolutions; activations of
-// layers 1-2 at positions outside the grid are zero, as with per-layer zero padding)
+// training (channel-major crops [b][c][S^3], valid convolutions; activations of
+// layers 1-2 at positions outside the grid are zero, as with per-layer zero padding).
+// FP32 throughout when tpk is null; otherwise layer 2's three passes run on BF16 MFMA
+// with FP32 accumulation: tpk holds 2 * GNET_PACK2 BF16 entries (16-byte aligned),
+// packed by the forward from params, and part gnet_train_part_floats(nb, S) floats of
+// layer 2's backward-weight partial sums.  wpart: gnet_train_wpart_floats() floats of
+// the FP32 weight gradients' partial sums.  Every sum is taken in a fixed order.
 void gnet_forward_batch(const float* params, const float* in, int nb, int S, const int* grid3,
-                        const int* org_dev, float* a1, float* a2, float* out, hipStream_t st);
+                        const int* org_dev, float* a1, float* a2, float* out, void* tpk,
+                        hipStream_t st);
 void gnet_backward_batch(const float* params, const float* in, int nb, int S, const float* a1,
                          const float* a2, const float* d3, float* d2, float* d1, float* grad,
-                         hipStream_t st);
+                         const void* tpk, float* part, float* wpart, hipStream_t st);
+long long gnet_train_part_floats(int nb, int S);
+long long gnet_train_wpart_floats();
 void gnet_mse_grad(const float* out, const float* tgt, long long n, float* d, double* part,
                    int nparts, hipStream_t st);
 void gnet_adam(float* p, float* m, float* v, const float* g, int n, float lr, float b1, float b2,

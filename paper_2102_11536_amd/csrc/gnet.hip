@@ -153,19 +153,23 @@ __device__ __forceinline__ float wsum(float v) {
   return v;
 }
 
-// gradient w.r.t. the weights and bias of a valid convolution: one workgroup per
-// (co, ci) pair, summed over every output point of the batch
+// gradient w.r.t. the weights and bias of a valid convolution, in two passes.  Pass 1:
+// workgroup (pair, chunk) sums, for the pair (co, ci) = (blockIdx.x / CI, blockIdx.x %
+// CI), the 27 tap products and the bias term over the chunk-th range of `chunk`
+// output points of the batch, into part[(chunk * CI * CO + pair) * 28 + t] (t = 27:
+// the bias term).  Pass 2 (conv_bwd_w_finish_k) sums the chunks in order.
 template <int CI, int CO>
 __global__ void __launch_bounds__(VB)
 conv_bwd_w_k(const float* __restrict__ in, Dims di, const float* __restrict__ dout, Dims dov,
-             int nb, float* __restrict__ dW, float* __restrict__ dbias) {
-  const int co = blockIdx.x / CI, ci = blockIdx.x % CI;
+             int nb, long long chunk, float* __restrict__ part) {
+  const int pair = blockIdx.x, co = pair / CI, ci = pair % CI;
   const long long vi = di.vol(), vo = dov.vol();
+  const long long c0 = (long long)blockIdx.y * chunk, c1 = min(c0 + chunk, nb * vo);
   float acc[27];
 #pragma unroll
   for (int t = 0; t < 27; ++t) acc[t] = 0.0f;
   float accb = 0.0f;
-  for (long long g = threadIdx.x; g < nb * vo; g += VB) {
+  for (long long g = c0 + threadIdx.x; g < c1; g += VB) {
     const long long bi = g / vo, o = g % vo;
     const int ox = (int)(o % dov.x), oy = (int)((o / dov.x) % dov.y), oz = (int)(o / ((long long)dov.x * dov.y));
     const float d = dout[bi * CO * vo + co * vo + o];
@@ -190,9 +194,38 @@ conv_bwd_w_k(const float* __restrict__ in, Dims di, const float* __restrict__ do
   if (threadIdx.x < 28) {
     float v = 0.0f;
     for (int w = 0; w < VB / 64; ++w) v += sh[threadIdx.x][w];
-    if (threadIdx.x < 27) dW[(threadIdx.x * CI + ci) * CO + co] = v;
-    else if (ci == 0) dbias[co] = v;
+    part[((long long)blockIdx.y * CI * CO + pair) * 28 + threadIdx.x] = v;
   }
+}
+
+template <int CI, int CO>
+__global__ void __launch_bounds__(VB)
+conv_bwd_w_finish_k(const float* __restrict__ part, int nchunk, float* __restrict__ dW,
+                    float* __restrict__ dbias) {
+  const int j = blockIdx.x * VB + threadIdx.x;
+  if (j >= CI * CO * 28) return;
+  const int pair = j / 28, t = j % 28, co = pair / CI, ci = pair % CI;
+  if (t == 27 && ci != 0) return;
+  float s = 0.0f;
+  for (int c = 0; c < nchunk; ++c) s += part[((long long)c * CI * CO + pair) * 28 + t];
+  if (t < 27) dW[(t * CI + ci) * CO + co] = s;
+  else dbias[co] = s;
+}
+
+// point chunks of the two-pass weight gradient: about 2048 workgroups in all
+constexpr int BWD_W_GROUPS = 2048;
+
+template <int CI, int CO>
+void launch_bwd_w(const float* in, Dims di, const float* dout, Dims dov, int nb, float* wpart,
+                  float* dW, float* dbias, hipStream_t st) {
+  const long long npts = nb * dov.vol();
+  const int want = BWD_W_GROUPS / (CI * CO) > 0 ? BWD_W_GROUPS / (CI * CO) : 1;
+  const long long chunk = (npts + want - 1) / want;
+  const int nchunk = (int)((npts + chunk - 1) / chunk);
+  hipLaunchKernelGGL((conv_bwd_w_k<CI, CO>), dim3(CI * CO, nchunk), dim3(VB), 0, st, in, di, dout,
+                     dov, nb, chunk, wpart);
+  hipLaunchKernelGGL((conv_bwd_w_finish_k<CI, CO>), dim3((CI * CO * 28 + VB - 1) / VB), dim3(VB), 0,
+                     st, wpart, nchunk, dW, dbias);
 }
 
 // d = 2 (out - tgt) / n; per-block partial sums of (out - tgt)^2
@@ -286,6 +319,196 @@ make_batch_k(GnetFields f, Dims grid, const int* __restrict__ org, int S, int nb
           (float)((xv - e) * is[3]);
     }
   }
+}
+
+// ---------------------------------------------------------------- training, layer 2 on MFMA
+// Layer 2 carries 55,296 of the 63,936 flops per point in each of the forward, the
+// backward-data and the backward-weight pass.  In BF16 training these three run on
+// MFMA 32x32x16 with BF16 operands (rounded from the FP32 activations, gradients and
+// master weights as they are loaded) and FP32 accumulation; activations, gradients
+// and the parameter update stay FP32.  MFMA operand layout (one 64-lane wave): lane l
+// supplies A[m = l%32][k = 8 (l/32) + i] and B[k = 8 (l/32) + i][n = l%32], i < 8;
+// accumulator entry v of lane l is D[8 (v/4) + 4 (l/32) + v%4][l%32].
+
+// W2 for the A operand of the forward (row co, k = ci; the inference layout) and of
+// the backward-data pass (row ci, k = co):
+//   entry ((t*2 + kc)*64 + lane)*8 + i            = W2[t][16 kc + 8 (lane/32) + i][lane % 32]
+//   entry GNET_PACK2 + ((t*2 + kc)*64 + lane)*8 + i = W2[t][lane % 32][16 kc + 8 (lane/32) + i]
+__global__ void __launch_bounds__(VB)
+pack_w2_train_k(const float* __restrict__ params, __bf16* __restrict__ pk) {
+  const int e = blockIdx.x * VB + threadIdx.x;
+  if (e >= 2 * GNET_PACK2) return;
+  const int which = e / GNET_PACK2, r = e % GNET_PACK2;
+  const int i = r % 8, lane = (r / 8) % 64, tk = r / 512, kc = tk % 2, t = tk / 2;
+  const int a = 16 * kc + 8 * (lane / 32) + i, b = lane % 32;
+  const int ci = which ? b : a, co = which ? a : b;
+  pk[e] = (__bf16)params[GNET_W2 + (t * 32 + ci) * 32 + co];
+}
+
+// forward of layer 2: wave w of the grid computes the 32 output channels of the 32
+// consecutive output points 32 w .. 32 w + 31 of the batch (flattened [b][S2^3]);
+// the B operand of tap t and channel slice kc is read from the channel-major a1
+// [b][32][S1^3].  Bias, ReLU and the outside-the-grid zeroing as in conv_fwd_k.
+__global__ void __launch_bounds__(256)
+conv2_train_fwd_k(const float* __restrict__ a1, int S1, int nb, const bf16x8* __restrict__ pk,
+                  const float* __restrict__ bias, float* __restrict__ a2, Dims grid,
+                  const int* __restrict__ org) {
+  const int S2 = S1 - 2;
+  const long long vi = (long long)S1 * S1 * S1, vo = (long long)S2 * S2 * S2;
+  const int lane = threadIdx.x & 63, n32 = lane & 31, half = lane >> 5;
+  const long long g = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + n32;
+  const bool valid = g < nb * vo;
+  const long long bi = valid ? g / vo : 0, o = valid ? g % vo : 0;
+  const int ox = (int)(o % S2), oy = (int)((o / S2) % S2), oz = (int)(o / ((long long)S2 * S2));
+  const float* src = a1 + (bi * 32 + 8 * half) * vi + ox + (long long)S1 * (oy + (long long)S1 * oz);
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int tr = 0; tr < 9; ++tr) {
+    const long long offr = (long long)S1 * (tr % 3 + (long long)S1 * (tr / 3));
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc) {
+        bf16x8 B;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) B[i] = (__bf16)src[(16 * kc + i) * vi + offr + kx];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pk[((3 * tr + kx) * 2 + kc) * 64 + lane], B,
+                                                       acc, 0, 0, 0);
+      }
+  }
+  if (!valid) return;
+  const bool in_grid = inside(org[3 * bi] + ox + 2, org[3 * bi + 1] + oy + 2,
+                              org[3 * bi + 2] + oz + 2, grid);
+  float* dst = a2 + bi * 32 * vo + o;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int co = 8 * (v / 4) + 4 * half + v % 4;
+    dst[co * vo] = in_grid ? fmaxf(acc[v] + bias[co], 0.0f) : 0.0f;
+  }
+}
+
+// backward-data of layer 2: d1[b][ci][q] = [a1 > 0] sum_{t,co} W2[t][ci][co] d2[b][co][q - o_t]
+// over the taps whose output point q - o_t lies in the S2^3 output; wave w computes
+// the 32 channels of the 32 input points 32 w .. 32 w + 31 (flattened [b][S1^3])
+__global__ void __launch_bounds__(256)
+conv2_train_bwd_data_k(const float* __restrict__ d2, int S1, int nb, const bf16x8* __restrict__ pkT,
+                       const float* __restrict__ a1, float* __restrict__ d1) {
+  const int S2 = S1 - 2;
+  const long long vi = (long long)S1 * S1 * S1, vo = (long long)S2 * S2 * S2;
+  const int lane = threadIdx.x & 63, n32 = lane & 31, half = lane >> 5;
+  const long long g = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + n32;
+  const bool valid = g < nb * vi;
+  const long long bi = valid ? g / vi : 0, q = valid ? g % vi : 0;
+  const int qx = (int)(q % S1), qy = (int)((q / S1) % S1), qz = (int)(q / ((long long)S1 * S1));
+  const float* src = d2 + (bi * 32 + 8 * half) * vo;
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int tr = 0; tr < 9; ++tr) {
+    const int oy = qy - tr % 3, oz = qz - tr / 3;
+    const bool okr = valid && oy >= 0 && oy < S2 && oz >= 0 && oz < S2;
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+      const int ox = qx - kx;
+      const bool ok = okr && ox >= 0 && ox < S2;
+      const long long off = ok ? ox + (long long)S2 * (oy + (long long)S2 * oz) : 0;
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc) {
+        bf16x8 B;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) B[i] = (__bf16)(ok ? src[(16 * kc + i) * vo + off] : 0.0f);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pkT[((3 * tr + kx) * 2 + kc) * 64 + lane], B,
+                                                       acc, 0, 0, 0);
+      }
+    }
+  }
+  if (!valid) return;
+  const float* ab = a1 + bi * 32 * vi + q;
+  float* dst = d1 + bi * 32 * vi + q;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int ci = 8 * (v / 4) + 4 * half + v % 4;
+    dst[ci * vi] = ab[ci * vi] > 0.0f ? acc[v] : 0.0f;
+  }
+}
+
+// backward-weight of layer 2: dW2[t][ci][co] = sum over the batch's output points o
+// of a1[b][ci][o + o_t] d2[b][co][o], one 32 x 32 product per tap with the points as
+// k.  Wave w takes tap row (ky, kz) = (w % 9) % 3, (w % 9) / 3 and its three taps
+// kx = 0..2 (which share the d2 operand) over chunk w / 9 of TRAIN_CHUNK output points
+// of one crop; it stores its partial sums to part[chunk][t][ci][co], and the waves of
+// tap row 0 the chunk's sums of d2 per channel co (the bias gradient) to
+// part[chunk][27 * 1024 + co]; reduce_chunks_k sums the chunks in a fixed order.
+constexpr int TRAIN_CHUNK = 2048;
+constexpr int TRAIN_PART = 27 * 1024 + 32;   // floats per chunk: W2's and b2's gradient
+
+__global__ void __launch_bounds__(256)
+conv2_train_bwd_w_k(const float* __restrict__ a1, const float* __restrict__ d2, int S1, int nb,
+                    int cpc, float* __restrict__ part) {
+  const int S2 = S1 - 2;
+  const long long vi = (long long)S1 * S1 * S1, vo = (long long)S2 * S2 * S2;
+  const int lane = threadIdx.x & 63, n32 = lane & 31, half = lane >> 5;
+  const long long wid = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int tr = (int)(wid % 9);
+  const long long chunk = wid / 9;
+  if (chunk >= (long long)nb * cpc) return;
+  const long long bi = chunk / cpc;
+  const long long c0 = (chunk % cpc) * TRAIN_CHUNK, c1 = min(c0 + TRAIN_CHUNK, vo);
+  const float* ai = a1 + (bi * 32 + n32) * vi + (long long)S1 * (tr % 3 + (long long)S1 * (tr / 3));
+  const float* di = d2 + (bi * 32 + n32) * vo;
+  f32x16 acc[3];
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[kx][v] = 0.0f;
+  float bsum = 0.0f;
+  // a crop holds fewer than 2^31 points (S <= 512): 32-bit point indices, stepped
+  // through the 8 consecutive points of each lane
+  const int e1 = (int)c1;
+  for (int base = (int)c0; base < e1; base += 16) {
+    bf16x8 A[3], B;
+    int o = base + 8 * half;
+    int ox = o % S2, oy = (o / S2) % S2, oz = o / (S2 * S2);
+    int in = ox + S1 * (oy + S1 * oz);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const bool ok = o < e1;
+      const float d = ok ? di[o] : 0.0f;
+      bsum += d;
+      B[i] = (__bf16)d;
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) A[kx][i] = (__bf16)(ok ? ai[in + kx] : 0.0f);
+      ++o;
+      ++in;
+      if (++ox == S2) {   // next row (or plane): the input index skips the halo
+        ox = 0;
+        if (++oy == S2) { oy = 0; ++oz; }
+        in = S1 * (oy + S1 * oz);
+      }
+    }
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) acc[kx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kx], B, acc[kx], 0, 0, 0);
+  }
+  float* pc = part + chunk * TRAIN_PART;
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx) {
+    float* dst = pc + (3 * tr + kx) * 1024 + n32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) dst[(8 * (v / 4) + 4 * half + v % 4) * 32] = acc[kx][v];
+  }
+  bsum += __shfl_xor(bsum, 32, 64);
+  if (tr == 0 && half == 0) pc[27 * 1024 + n32] = bsum;
+}
+
+// out[j] = sum over c < nchunk of part[c * n + j], in chunk order
+__global__ void __launch_bounds__(VB)
+reduce_chunks_k(const float* __restrict__ part, long long nchunk, int n, float* __restrict__ out) {
+  const int j = blockIdx.x * VB + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.0f;
+  for (long long c = 0; c < nchunk; ++c) s += part[c * n + j];
+  out[j] = s;
 }
 
 // ---------------------------------------------------------------- inference
@@ -584,34 +807,61 @@ layer3_gather_k(const __bf16* __restrict__ u, GnetFields f, Dims g, const double
 static Dims cube(int s) { return Dims{s, s, s}; }
 
 void gnet_forward_batch(const float* params, const float* in, int nb, int S, const int* grid3,
-                        const int* org_dev, float* a1, float* a2, float* out, hipStream_t st) {
+                        const int* org_dev, float* a1, float* a2, float* out, void* tpk,
+                        hipStream_t st) {
   const int S1 = S - 2, S2 = S - 4, S3 = S - 6;
   const Dims g{grid3[0], grid3[1], grid3[2]};
   hipLaunchKernelGGL((conv_fwd_k<4, 32>), dim3(nbk((long long)nb * S1 * S1 * S1)), dim3(VB), 0, st,
                      in, cube(S), cube(S1), nb, params + GNET_W1, params + GNET_B1, a1, 1, g,
                      org_dev, 1);
-  hipLaunchKernelGGL((conv_fwd_k<32, 32>), dim3(nbk((long long)nb * S2 * S2 * S2)), dim3(VB), 0, st,
-                     a1, cube(S1), cube(S2), nb, params + GNET_W2, params + GNET_B2, a2, 1, g,
-                     org_dev, 2);
+  if (tpk) {
+    hipLaunchKernelGGL(pack_w2_train_k, dim3((2 * GNET_PACK2 + VB - 1) / VB), dim3(VB), 0, st, params,
+                       (__bf16*)tpk);
+    const long long waves = ((long long)nb * S2 * S2 * S2 + 31) / 32;
+    hipLaunchKernelGGL(conv2_train_fwd_k, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a1, S1,
+                       nb, (const bf16x8*)tpk, params + GNET_B2, a2, g, org_dev);
+  } else {
+    hipLaunchKernelGGL((conv_fwd_k<32, 32>), dim3(nbk((long long)nb * S2 * S2 * S2)), dim3(VB), 0, st,
+                       a1, cube(S1), cube(S2), nb, params + GNET_W2, params + GNET_B2, a2, 1, g,
+                       org_dev, 2);
+  }
   hipLaunchKernelGGL((conv_fwd_k<32, 1>), dim3(nbk((long long)nb * S3 * S3 * S3)), dim3(VB), 0, st,
                      a2, cube(S2), cube(S3), nb, params + GNET_W3, params + GNET_B3, out, 0, g,
                      (const int*)nullptr, 0);
 }
 
+long long gnet_train_part_floats(int nb, int S) {
+  const long long vo = (long long)(S - 4) * (S - 4) * (S - 4);
+  return (long long)nb * ((vo + TRAIN_CHUNK - 1) / TRAIN_CHUNK) * TRAIN_PART;
+}
+
+long long gnet_train_wpart_floats() { return (long long)BWD_W_GROUPS * 28; }
+
 void gnet_backward_batch(const float* params, const float* in, int nb, int S, const float* a1,
                          const float* a2, const float* d3, float* d2, float* d1, float* grad,
-                         hipStream_t st) {
+                         const void* tpk, float* part, float* wpart, hipStream_t st) {
   const int S1 = S - 2, S2 = S - 4, S3 = S - 6;
-  hipLaunchKernelGGL((conv_bwd_w_k<32, 1>), dim3(32), dim3(VB), 0, st, a2, cube(S2), d3, cube(S3),
-                     nb, grad + GNET_W3, grad + GNET_B3);
+  launch_bwd_w<32, 1>(a2, cube(S2), d3, cube(S3), nb, wpart, grad + GNET_W3, grad + GNET_B3, st);
   hipLaunchKernelGGL((conv_bwd_data_k<32, 1>), dim3(nbk((long long)nb * S2 * S2 * S2)), dim3(VB), 0,
                      st, d3, cube(S2), cube(S3), nb, params + GNET_W3, a2, d2);
-  hipLaunchKernelGGL((conv_bwd_w_k<32, 32>), dim3(32 * 32), dim3(VB), 0, st, a1, cube(S1), d2,
-                     cube(S2), nb, grad + GNET_W2, grad + GNET_B2);
-  hipLaunchKernelGGL((conv_bwd_data_k<32, 32>), dim3(nbk((long long)nb * S1 * S1 * S1)), dim3(VB), 0,
-                     st, d2, cube(S1), cube(S2), nb, params + GNET_W2, a1, d1);
-  hipLaunchKernelGGL((conv_bwd_w_k<4, 32>), dim3(32 * 4), dim3(VB), 0, st, in, cube(S), d1,
-                     cube(S1), nb, grad + GNET_W1, grad + GNET_B1);
+  if (tpk) {
+    const long long vo = (long long)S2 * S2 * S2;
+    const int cpc = (int)((vo + TRAIN_CHUNK - 1) / TRAIN_CHUNK);
+    const long long nchunk = (long long)nb * cpc, wv = nchunk * 9;
+    hipLaunchKernelGGL(conv2_train_bwd_w_k, dim3((unsigned)((wv + 3) / 4)), dim3(256), 0, st, a1, d2,
+                       S1, nb, cpc, part);
+    // W2's and b2's gradients are contiguous in the parameter layout
+    hipLaunchKernelGGL(reduce_chunks_k, dim3((TRAIN_PART + VB - 1) / VB), dim3(VB), 0, st, part,
+                       nchunk, TRAIN_PART, grad + GNET_W2);
+    const long long wd = ((long long)nb * S1 * S1 * S1 + 31) / 32;
+    hipLaunchKernelGGL(conv2_train_bwd_data_k, dim3((unsigned)((wd + 3) / 4)), dim3(256), 0, st, d2,
+                       S1, nb, (const bf16x8*)tpk + GNET_PACK2 / 8, a1, d1);
+  } else {
+    launch_bwd_w<32, 32>(a1, cube(S1), d2, cube(S2), nb, wpart, grad + GNET_W2, grad + GNET_B2, st);
+    hipLaunchKernelGGL((conv_bwd_data_k<32, 32>), dim3(nbk((long long)nb * S1 * S1 * S1)), dim3(VB),
+                       0, st, d2, cube(S1), cube(S2), nb, params + GNET_W2, a1, d1);
+  }
+  launch_bwd_w<4, 32>(in, cube(S), d1, cube(S1), nb, wpart, grad + GNET_W1, grad + GNET_B1, st);
 }
 
 void gnet_mse_grad(const float* out, const float* tgt, long long n, float* d, double* part,

@@ -24,6 +24,7 @@ EXPORTS = ["ga_setup_patch", "ga_setup_patch_ex", "ga_destroy_patch", "ga_patch_
            "ga_profile", "ga_profile_query", "ga_solve_stats", "ga_last_error", "ga_stage_solution", "ga_patch_set_pinv",
            "ga_integrator_set_damping", "ga_stage_times", "ga_init_state_forced", "ga_step_forced",
            "ga_gnet_create", "ga_gnet_destroy", "ga_gnet_set_params", "ga_gnet_get_params",
+           "ga_gnet_set_train_prec",
            "ga_gnet_make_batch", "ga_gnet_forward", "ga_gnet_loss_grad", "ga_gnet_adam", "ga_gnet_infer",
            "ga_integrator_set_net", "ga_integrator_history", "ga_integrator_set_history", "ga_batch_create", "ga_batch_destroy", "ga_batch_info",
            "ga_batch_tune", "ga_batch_set_precision", "ga_batch_set_tau", "ga_patch_set_cg", "ga_cg_stats", "ga_patch_tune", "ga_patch_tuned_layers", "ga_patch_set_layers", "ga_patch_set_deterministic",
@@ -92,6 +93,7 @@ def load_library(path=LIB_PATH):
     lib.ga_gnet_destroy.argtypes = [vp]
     lib.ga_gnet_set_params.argtypes = [vp, fp]
     lib.ga_gnet_get_params.argtypes = [vp, fp]
+    lib.ga_gnet_set_train_prec.argtypes = [vp, i]
     lib.ga_gnet_make_batch.argtypes = [vp, vp, ctypes.POINTER(vp), dp, i, i, ip, dp, dp, vp]
     lib.ga_gnet_forward.argtypes = [vp, i, i, ip, ip, dp, dp, vp]
     lib.ga_gnet_loss_grad.argtypes = [vp, i, i, ip, ip, dp, dp, dp, ctypes.POINTER(d), vp]
@@ -461,6 +463,10 @@ def _hist_array(patch, hist):
     if len(hist) != 4:
         raise ValueError("need 4 history vectors (newest first)")
     return (ctypes.c_void_p * 4)(*[_ptr(h, patch.n_free).value for h in hist])
+
+
+def ga_gnet_set_train_prec(net, prec):
+    _check(_lib.ga_gnet_set_train_prec(net.h, int(prec)))
 
 
 def ga_gnet_make_batch(net, patch, hist, x, origins, S, inp, tgt):

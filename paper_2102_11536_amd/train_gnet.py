@@ -7,7 +7,8 @@ guess, which keeps the ring of past stage solutions).  From the fifth step on,
 every step gives one training sample per stage: the four previous stage
 solutions H1..H4 and the new one X; the sample is cut into random crops and the
 stage's net takes one Adam step on them.  All of it runs in the library's own
-kernels (ga_gnet_make_batch, ga_gnet_loss_grad, ga_gnet_adam).
+kernels (ga_gnet_make_batch, ga_gnet_loss_grad, ga_gnet_adam); by default layer 2's
+convolutions run on the BF16 matrix cores, with FP32 master weights (--prec).
 
 The nets start with a zero last layer, i.e. at the plain cubic extrapolation,
 and learn the correction.  Output: an .npz with one float32 parameter vector
@@ -84,6 +85,8 @@ def main(argv=None):
     ap.add_argument("--lr-min", type=float, default=2e-7)
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--eval-steps", type=int, default=24)
+    ap.add_argument("--prec", choices=("bf16", "fp32"), default="bf16",
+                    help="training arithmetic: layer 2 on BF16 matrix cores, or FP32 throughout")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     args = ap.parse_args(argv)
     assert torch.cuda.is_available(), "training runs on the GPU"
@@ -96,6 +99,8 @@ def main(argv=None):
     tau = 0.5 * math.sqrt(ga.ga_stability_limit(args.rho) / lam)
     log(f"[train] n={n} p={p} k={k} n_free={pt.n_free} tau={tau:.4e} trajectories={args.trajectories}")
     nets = [ga.GNet(initial_params(args.seed + j)) for j in range(k)]
+    for net in nets:
+        ga.ga_gnet_set_train_prec(net, ga.GA_BF16 if args.prec == "bf16" else ga.GA_FP32)
     S, nb, T = args.crop, args.batch, args.crop - 6
     if min(pt.mf) < T:
         raise SystemExit("grid smaller than the crop target")
@@ -148,7 +153,7 @@ def main(argv=None):
         evals[name] = evaluate(pt, k, args.rho, tau, args.rtol, mode, nets, args.eval_steps, seed=99_999)
         log(f"[train] held-out trajectory, {name} guess: {evals[name]}")
     meta = dict(n=n, p=p, k=k, rho=args.rho, tau=tau, rtol=args.rtol, trajectories=args.trajectories,
-                steps=args.steps, crop=S, batch=nb, lr=args.lr, seed=args.seed,
+                steps=args.steps, crop=S, batch=nb, lr=args.lr, seed=args.seed, prec=args.prec,
                 final_ratio=[float(np.mean(h[-200:])) if h else None for h in hist_ratio],
                 seconds=time.time() - t0, heldout=evals)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

@@ -155,3 +155,28 @@ def test_adam_matches_torch():
         opt.step()
         p, m, v = cn.adam_step(p, m, v, g, k, 1e-2)
     assert np.allclose(p, t.detach().numpy(), rtol=0, atol=1e-12)
+
+
+def test_bf16_emulation_without_rounding_is_the_oracle():
+    """The crop-by-crop emulation of BF16 training (tests/gnet_emulation.py) with the
+    rounding switched off reproduces the oracle's loss and gradient (whole-grid net,
+    autograd): its crops, masks and explicit backward passes are right; with the
+    rounding on it moves the gradient by a few BF16 units only."""
+    from tests.gnet_emulation import U_BF16, bf16_crop_grad
+    mf = (10, 9, 8)
+    grid = (mf[2], mf[1], mf[0])
+    rng = np.random.default_rng(6)
+    n = int(np.prod(mf))
+    H = [rng.standard_normal(n) * (1.0 + 0.1 * h) for h in range(4)]
+    X = rng.standard_normal(n)
+    S = 10
+    org = [(-3, -3, -3), (mf[0] - 7, mf[1] - 7, mf[2] - 7), (0, 1, -2)]
+    params = gnet_random_params(8)
+    rl, rg = cn.crop_loss(params, H, X, grid, org, S)
+    el, eg = bf16_crop_grad(params, H, X, grid, org, S, rnd=lambda t: t)
+    assert abs(el - rl) <= 1e-13 * rl
+    assert np.linalg.norm(eg - rg) <= 1e-13 * np.linalg.norm(rg)
+    bl, bg = bf16_crop_grad(params, H, X, grid, org, S)
+    e = np.linalg.norm(bg - rg) / np.linalg.norm(rg)
+    assert 0.0 < e <= 4 * U_BF16
+    assert abs(bl - rl) <= 4 * U_BF16 * rl
