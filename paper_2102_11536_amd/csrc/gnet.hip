@@ -25,6 +25,7 @@
 //   The layer-1 activations are stored channels-last [point][32] (64 bytes per
 //   point), the tap planes in 54 bytes per point.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <type_traits>
 
 #include "gnet.h"
@@ -435,80 +436,155 @@ conv2_train_bwd_data_k(const float* __restrict__ d2, int S1, int nb, const bf16x
 
 // backward-weight of layer 2: dW2[t][ci][co] = sum over the batch's output points o
 // of a1[b][ci][o + o_t] d2[b][co][o], one 32 x 32 product per tap with the points as
-// k.  Wave w takes tap row (ky, kz) = (w % 9) % 3, (w % 9) / 3 and its three taps
-// kx = 0..2 (which share the d2 operand) over chunk w / 9 of TRAIN_CHUNK output points
-// of one crop; it stores its partial sums to part[chunk][t][ci][co], and the waves of
-// tap row 0 the chunk's sums of d2 per channel co (the bias gradient) to
-// part[chunk][27 * 1024 + co]; reduce_chunks_k sums the chunks in a fixed order.
-constexpr int TRAIN_CHUNK = 2048;
-constexpr int TRAIN_PART = 27 * 1024 + 32;   // floats per chunk: W2's and b2's gradient
+// k, and the bias gradient sum_o d2[b][co][o].
+constexpr int TRAIN_PART = 27 * 1024 + 32;   // floats per partial: W2's and b2's gradient
 
-__global__ void __launch_bounds__(256)
-conv2_train_bwd_w_k(const float* __restrict__ a1, const float* __restrict__ d2, int S1, int nb,
-                    int cpc, float* __restrict__ part) {
-  const int S2 = S1 - 2;
-  const long long vi = (long long)S1 * S1 * S1, vo = (long long)S2 * S2 * S2;
-  const int lane = threadIdx.x & 63, n32 = lane & 31, half = lane >> 5;
-  const long long wid = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int tr = (int)(wid % 9);
-  const long long chunk = wid / 9;
-  if (chunk >= (long long)nb * cpc) return;
-  const long long bi = chunk / cpc;
-  const long long c0 = (chunk % cpc) * TRAIN_CHUNK, c1 = min(c0 + TRAIN_CHUNK, vo);
-  const float* ai = a1 + (bi * 32 + n32) * vi + (long long)S1 * (tr % 3 + (long long)S1 * (tr / 3));
-  const float* di = d2 + (bi * 32 + n32) * vo;
-  f32x16 acc[3];
+// backward-weight of layer 2 through LDS.  Workgroup (b, zc) of 3 waves sums over
+// the output planes oz in [zc * pz, zc * pz + pz) of crop b, in units of 4 output
+// rows x 32 output points: d2 of the unit ([co][4 rows][32 points]) and the layer-1
+// activations it meets ([ci][6 rows x 3 planes][36 points]) are staged as BF16 in LDS
+// with coalesced loads; wave w owns the 9 taps of tap plane kz = w, and for each
+// (row, 16-point k-step, ky) reads two aligned 16-byte A windows that the three kx
+// taps share (shifted by kx elements with alignbyte).  Partial sums per workgroup go
+// to part[b * nzc + zc] (TRAIN_PART floats: 27 taps x [ci][co], then b2's 32), and
+// reduce_chunks_k sums them in a fixed order.
+constexpr int BW_ROWS = 4;                         // output rows per unit
+constexpr int BW_AROW = 96;                        // bytes per staged a1 row (48 BF16)
+constexpr int BW_ACH = 18 * BW_AROW + 16;          // bytes per a1 channel (18 rows), padded
+constexpr int BW_BCH = BW_ROWS * 64 + 16;          // bytes per d2 channel (4 rows of 32), padded
+constexpr int BW_LDS = 32 * BW_ACH + 32 * BW_BCH;  // 64,512 bytes
+
+__device__ __forceinline__ bf16x8 shift_window(const uint4& lo, const uint4& hi, int kx) {
+  // elements kx .. kx + 7 of the 16-element window lo:hi
+  const unsigned w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  const bool d = kx >= 2;
+  const unsigned bs = (kx & 1) * 2;
+  unsigned u[5], o[4];
 #pragma unroll
-  for (int kx = 0; kx < 3; ++kx)
+  for (int j = 0; j < 5; ++j) u[j] = d ? w[j + 1] : w[j];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[kx][v] = 0.0f;
-  float bsum = 0.0f;
-  // a crop holds fewer than 2^31 points (S <= 512): 32-bit point indices, stepped
-  // through the 8 consecutive points of each lane
-  const int e1 = (int)c1;
-  for (int base = (int)c0; base < e1; base += 16) {
-    bf16x8 A[3], B;
-    int o = base + 8 * half;
-    int ox = o % S2, oy = (o / S2) % S2, oz = o / (S2 * S2);
-    int in = ox + S1 * (oy + S1 * oz);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const bool ok = o < e1;
-      const float d = ok ? di[o] : 0.0f;
-      bsum += d;
-      B[i] = (__bf16)d;
-#pragma unroll
-      for (int kx = 0; kx < 3; ++kx) A[kx][i] = (__bf16)(ok ? ai[in + kx] : 0.0f);
-      ++o;
-      ++in;
-      if (++ox == S2) {   // next row (or plane): the input index skips the halo
-        ox = 0;
-        if (++oy == S2) { oy = 0; ++oz; }
-        in = S1 * (oy + S1 * oz);
-      }
-    }
-#pragma unroll
-    for (int kx = 0; kx < 3; ++kx) acc[kx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kx], B, acc[kx], 0, 0, 0);
-  }
-  float* pc = part + chunk * TRAIN_PART;
-#pragma unroll
-  for (int kx = 0; kx < 3; ++kx) {
-    float* dst = pc + (3 * tr + kx) * 1024 + n32;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) dst[(8 * (v / 4) + 4 * half + v % 4) * 32] = acc[kx][v];
-  }
-  bsum += __shfl_xor(bsum, 32, 64);
-  if (tr == 0 && half == 0) pc[27 * 1024 + n32] = bsum;
+  for (int j = 0; j < 4; ++j) o[j] = __builtin_amdgcn_alignbyte(u[j + 1], u[j], bs);
+  bf16x8 r;
+  __builtin_memcpy(&r, o, 16);
+  return r;
 }
 
-// out[j] = sum over c < nchunk of part[c * n + j], in chunk order
+__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2, 2)))
+conv2_train_bwd_w_lds_k(const float* __restrict__ a1, const float* __restrict__ d2, int S1, int nb,
+                        int pz, int nzc, float* __restrict__ part) {
+  __shared__ __align__(16) unsigned char lds[BW_LDS];
+  unsigned char* const la = lds;                  // a1 tile
+  unsigned char* const lb = lds + 32 * BW_ACH;    // d2 tile
+  const int S2 = S1 - 2;
+  const long long vi = (long long)S1 * S1 * S1, vo = (long long)S2 * S2 * S2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n32 = lane & 31, half = lane >> 5;
+  const int b = blockIdx.x / nzc, zc = blockIdx.x % nzc;
+  const float* a1b = a1 + (long long)b * 32 * vi;
+  const float* d2b = d2 + (long long)b * 32 * vo;
+  f32x16 acc[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[a][v] = 0.0f;
+  float bacc[11];
+#pragma unroll
+  for (int j = 0; j < 11; ++j) bacc[j] = 0.0f;
+  const int oz1 = min(zc * pz + pz, S2);
+  for (int oz = zc * pz; oz < oz1; ++oz)
+    for (int y0 = 0; y0 < S2; y0 += BW_ROWS)
+      for (int x0 = 0; x0 < S2; x0 += 32) {
+        // d2: 2048 pairs (co, row r, x pair p), zero outside the output
+#pragma unroll
+        for (int j = 0; j < 11; ++j) {
+          const int pi = tid + 192 * j;
+          if (pi < 2048) {
+            const int p = pi & 15, r = (pi >> 4) & 3, co = pi >> 6;
+            const int y = y0 + r, x = x0 + 2 * p;
+            float v0 = 0.0f, v1 = 0.0f;
+            if (y < S2) {
+              const float* src = d2b + co * vo + ((long long)oz * S2 + y) * S2 + x;
+              if (x < S2) v0 = src[0];
+              if (x + 1 < S2) v1 = src[1];
+            }
+            bacc[j] += v0 + v1;
+            const __bf16 h[2] = {(__bf16)v0, (__bf16)v1};
+            __builtin_memcpy(lb + co * BW_BCH + r * 64 + 4 * p, h, 4);
+          }
+        }
+        // a1: 10368 pairs (ci, staged row = rr + 6 kz, x pair p), zero outside the crop
+#pragma unroll 6
+        for (int j = 0; j < 54; ++j) {
+          const int pi = tid + 192 * j;
+          const int p = pi % 18, row = (pi / 18) % 18, ci = pi / 324;
+          const int rr = row % 6, kz = row / 6;
+          const int y = y0 + rr, x = x0 + 2 * p;
+          float v0 = 0.0f, v1 = 0.0f;
+          if (y < S1) {
+            const float* src = a1b + ci * vi + ((long long)(oz + kz) * S1 + y) * S1 + x;
+            if (x < S1) v0 = src[0];
+            if (x + 1 < S1) v1 = src[1];
+          }
+          const __bf16 h[2] = {(__bf16)v0, (__bf16)v1};
+          __builtin_memcpy(la + ci * BW_ACH + row * BW_AROW + 4 * p, h, 4);
+        }
+        __syncthreads();
+        // wave w: taps (kx, ky, kz = w); lane supplies A[ci = n32][8 half + i] and
+        // B[8 half + i][co = n32] of the k-step's 16 points
+#pragma unroll
+        for (int r = 0; r < BW_ROWS; ++r)
+#pragma unroll
+          for (int ks = 0; ks < 2; ++ks) {
+            const int xo = 16 * ks + 8 * half;
+            bf16x8 B;
+            {
+              const uint4 raw = *reinterpret_cast<const uint4*>(lb + n32 * BW_BCH + r * 64 + 2 * xo);
+              __builtin_memcpy(&B, &raw, 16);
+            }
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky) {
+              const unsigned char* ap = la + n32 * BW_ACH + (r + ky + 6 * w) * BW_AROW + 2 * xo;
+              const uint4 lo = *reinterpret_cast<const uint4*>(ap);
+              const uint4 hi = *reinterpret_cast<const uint4*>(ap + 16);
+#pragma unroll
+              for (int kx = 0; kx < 3; ++kx)
+                acc[3 * ky + kx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(shift_window(lo, hi, kx), B,
+                                                                            acc[3 * ky + kx], 0, 0, 0);
+            }
+          }
+        __syncthreads();
+      }
+  float* pc = part + (long long)blockIdx.x * TRAIN_PART;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    float* dst = pc + (9 * w + a) * 1024 + n32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) dst[(8 * (v / 4) + 4 * half + v % 4) * 32] = acc[a][v];
+  }
+#pragma unroll
+  for (int j = 0; j < 11; ++j) {
+    const float t = wsum(bacc[j]);
+    const int co = w + 3 * j;
+    if (lane == 0 && co < 32) pc[27 * 1024 + co] = t;
+  }
+}
+
+// out[j] = sum over c < nchunk of part[c * n + j]: a workgroup takes 64 consecutive j,
+// its four waves a quarter of the chunks each (in order), and the four partial sums
+// are added in wave order
 __global__ void __launch_bounds__(VB)
 reduce_chunks_k(const float* __restrict__ part, long long nchunk, int n, float* __restrict__ out) {
-  const int j = blockIdx.x * VB + threadIdx.x;
-  if (j >= n) return;
+  __shared__ float sh[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  const long long q = (nchunk + 3) / 4, c0 = w * q, c1 = min(c0 + q, nchunk);
   float s = 0.0f;
-  for (long long c = 0; c < nchunk; ++c) s += part[c * n + j];
-  out[j] = s;
+  if (j < n) {
+#pragma unroll 8
+    for (long long c = c0; c < c1; ++c) s += part[c * n + j];
+  }
+  sh[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < n) out[j] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
 }
 
 // ---------------------------------------------------------------- inference
@@ -830,9 +906,19 @@ void gnet_forward_batch(const float* params, const float* in, int nb, int S, con
                      (const int*)nullptr, 0);
 }
 
+// output planes per workgroup of the BF16 backward-weight pass: one, unless the batch
+// has more than 1024 planes in all
+static void bwd_w_planes(int nb, int S, int* pz, int* nzc) {
+  const int S2 = S - 4;
+  const long long planes = (long long)nb * S2;
+  *pz = (int)std::max<long long>(1, (planes + 1023) / 1024);
+  *nzc = (S2 + *pz - 1) / *pz;
+}
+
 long long gnet_train_part_floats(int nb, int S) {
-  const long long vo = (long long)(S - 4) * (S - 4) * (S - 4);
-  return (long long)nb * ((vo + TRAIN_CHUNK - 1) / TRAIN_CHUNK) * TRAIN_PART;
+  int pz, nzc;
+  bwd_w_planes(nb, S, &pz, &nzc);
+  return (long long)nb * nzc * TRAIN_PART;
 }
 
 long long gnet_train_wpart_floats() { return (long long)BWD_W_GROUPS * 28; }
@@ -845,14 +931,13 @@ void gnet_backward_batch(const float* params, const float* in, int nb, int S, co
   hipLaunchKernelGGL((conv_bwd_data_k<32, 1>), dim3(nbk((long long)nb * S2 * S2 * S2)), dim3(VB), 0,
                      st, d3, cube(S2), cube(S3), nb, params + GNET_W3, a2, d2);
   if (tpk) {
-    const long long vo = (long long)S2 * S2 * S2;
-    const int cpc = (int)((vo + TRAIN_CHUNK - 1) / TRAIN_CHUNK);
-    const long long nchunk = (long long)nb * cpc, wv = nchunk * 9;
-    hipLaunchKernelGGL(conv2_train_bwd_w_k, dim3((unsigned)((wv + 3) / 4)), dim3(256), 0, st, a1, d2,
-                       S1, nb, cpc, part);
+    int pz, nzc;
+    bwd_w_planes(nb, S, &pz, &nzc);
+    hipLaunchKernelGGL(conv2_train_bwd_w_lds_k, dim3((unsigned)(nb * nzc)), dim3(192), 0, st, a1, d2,
+                       S1, nb, pz, nzc, part);
     // W2's and b2's gradients are contiguous in the parameter layout
-    hipLaunchKernelGGL(reduce_chunks_k, dim3((TRAIN_PART + VB - 1) / VB), dim3(VB), 0, st, part,
-                       nchunk, TRAIN_PART, grad + GNET_W2);
+    hipLaunchKernelGGL(reduce_chunks_k, dim3((TRAIN_PART + 63) / 64), dim3(VB), 0, st, part,
+                       (long long)nb * nzc, TRAIN_PART, grad + GNET_W2);
     const long long wd = ((long long)nb * S1 * S1 * S1 + 31) / 32;
     hipLaunchKernelGGL(conv2_train_bwd_data_k, dim3((unsigned)((wd + 3) / 4)), dim3(256), 0, st, d2,
                        S1, nb, (const bf16x8*)tpk + GNET_PACK2 / 8, a1, d1);
