@@ -155,47 +155,60 @@ __device__ __forceinline__ float wsum(float v) {
 }
 
 // gradient w.r.t. the weights and bias of a valid convolution, in two passes.  Pass 1:
-// workgroup (pair, chunk) sums, for the pair (co, ci) = (blockIdx.x / CI, blockIdx.x %
-// CI), the 27 tap products and the bias term over the chunk-th range of `chunk`
-// output points of the batch, into part[(chunk * CI * CO + pair) * 28 + t] (t = 27:
-// the bias term).  Pass 2 (conv_bwd_w_finish_k) sums the chunks in order.
-template <int CI, int CO>
+// workgroup (group, chunk) takes input channel ci = blockIdx.x % CI and the G output
+// channels co = G (blockIdx.x / CI) + g, which share the 27 input loads of each point,
+// and sums the tap products and the bias term over the chunk-th range of `chunk`
+// output points of the batch into part[(chunk * CI * CO + co * CI + ci) * 28 + t]
+// (t = 27: the bias term).  Pass 2 (conv_bwd_w_finish_k) sums the chunks in order.
+template <int CI, int CO, int G>
 __global__ void __launch_bounds__(VB)
 conv_bwd_w_k(const float* __restrict__ in, Dims di, const float* __restrict__ dout, Dims dov,
              int nb, long long chunk, float* __restrict__ part) {
-  const int pair = blockIdx.x, co = pair / CI, ci = pair % CI;
+  const int ci = blockIdx.x % CI, co0 = G * (blockIdx.x / CI);
   const long long vi = di.vol(), vo = dov.vol();
   const long long c0 = (long long)blockIdx.y * chunk, c1 = min(c0 + chunk, nb * vo);
-  float acc[27];
+  float acc[G][27], accb[G];
 #pragma unroll
-  for (int t = 0; t < 27; ++t) acc[t] = 0.0f;
-  float accb = 0.0f;
-  for (long long g = c0 + threadIdx.x; g < c1; g += VB) {
-    const long long bi = g / vo, o = g % vo;
+  for (int g = 0; g < G; ++g) {
+    accb[g] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc[g][t] = 0.0f;
+  }
+  for (long long p = c0 + threadIdx.x; p < c1; p += VB) {
+    const long long bi = p / vo, o = p % vo;
     const int ox = (int)(o % dov.x), oy = (int)((o / dov.x) % dov.y), oz = (int)(o / ((long long)dov.x * dov.y));
-    const float d = dout[bi * CO * vo + co * vo + o];
-    accb += d;
+    float d[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      d[g] = dout[(bi * CO + co0 + g) * vo + o];
+      accb[g] += d[g];
+    }
     const float* ib = in + (bi * CI + ci) * vi + ox + (long long)di.x * (oy + (long long)di.y * oz);
 #pragma unroll
-    for (int t = 0; t < 27; ++t)
-      acc[t] += d * ib[(t % 3) + (long long)di.x * ((t / 3) % 3 + (long long)di.y * (t / 9))];
+    for (int t = 0; t < 27; ++t) {
+      const float x = ib[(t % 3) + (long long)di.x * ((t / 3) % 3 + (long long)di.y * (t / 9))];
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc[g][t] += d[g] * x;
+    }
   }
-  __shared__ float sh[28][VB / 64];
+  __shared__ float sh[G][28][VB / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < 27; ++t) {
-    const float v = wsum(acc[t]);
-    if (lane == 0) sh[t][wv] = v;
-  }
-  {
-    const float v = wsum(accb);
-    if (lane == 0) sh[27][wv] = v;
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+      const float v = wsum(acc[g][t]);
+      if (lane == 0) sh[g][t][wv] = v;
+    }
+    const float v = wsum(accb[g]);
+    if (lane == 0) sh[g][27][wv] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 28) {
+  for (int e = threadIdx.x; e < G * 28; e += VB) {
+    const int g = e / 28, t = e % 28;
     float v = 0.0f;
-    for (int w = 0; w < VB / 64; ++w) v += sh[threadIdx.x][w];
-    part[((long long)blockIdx.y * CI * CO + pair) * 28 + threadIdx.x] = v;
+    for (int w = 0; w < VB / 64; ++w) v += sh[g][t][w];
+    part[((long long)blockIdx.y * CI * CO + (co0 + g) * CI + ci) * 28 + t] = v;
   }
 }
 
@@ -219,11 +232,13 @@ constexpr int BWD_W_GROUPS = 2048;
 template <int CI, int CO>
 void launch_bwd_w(const float* in, Dims di, const float* dout, Dims dov, int nb, float* wpart,
                   float* dW, float* dbias, hipStream_t st) {
+  constexpr int G = CO % 4 == 0 ? 4 : 1;   // output channels per workgroup
+  constexpr int groups = CI * CO / G;
   const long long npts = nb * dov.vol();
-  const int want = BWD_W_GROUPS / (CI * CO) > 0 ? BWD_W_GROUPS / (CI * CO) : 1;
+  const int want = BWD_W_GROUPS / groups > 0 ? BWD_W_GROUPS / groups : 1;
   const long long chunk = (npts + want - 1) / want;
   const int nchunk = (int)((npts + chunk - 1) / chunk);
-  hipLaunchKernelGGL((conv_bwd_w_k<CI, CO>), dim3(CI * CO, nchunk), dim3(VB), 0, st, in, di, dout,
+  hipLaunchKernelGGL((conv_bwd_w_k<CI, CO, G>), dim3(groups, nchunk), dim3(VB), 0, st, in, di, dout,
                      dov, nb, chunk, wpart);
   hipLaunchKernelGGL((conv_bwd_w_finish_k<CI, CO>), dim3((CI * CO * 28 + VB - 1) / VB), dim3(VB), 0,
                      st, wpart, nchunk, dW, dbias);
@@ -406,22 +421,34 @@ conv2_train_bwd_data_k(const float* __restrict__ d2, int S1, int nb, const bf16x
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-  for (int tr = 0; tr < 9; ++tr) {
-    const int oy = qy - tr % 3, oz = qz - tr / 3;
-    const bool okr = valid && oy >= 0 && oy < S2 && oz >= 0 && oz < S2;
+  // tap t reads d2 at output point q - o_t (all 16 channel values of the lane); a
+  // masked tap reads offset 0 (in bounds) and is zeroed on conversion.  The loads of
+  // tap t + 1 are issued before tap t's conversions and MFMAs.
+  auto load_tap = [&](int t, float (&v)[16]) -> bool {
+    const int ox = qx - t % 3, oy = qy - (t / 3) % 3, oz = qz - t / 9;
+    const bool ok = valid && ox >= 0 && ox < S2 && oy >= 0 && oy < S2 && oz >= 0 && oz < S2;
+    const long long off = ok ? ox + (long long)S2 * (oy + (long long)S2 * oz) : 0;
 #pragma unroll
-    for (int kx = 0; kx < 3; ++kx) {
-      const int ox = qx - kx;
-      const bool ok = okr && ox >= 0 && ox < S2;
-      const long long off = ok ? ox + (long long)S2 * (oy + (long long)S2 * oz) : 0;
+    for (int c = 0; c < 16; ++c) v[c] = src[(c / 8 * 16 + c % 8) * vo + off];
+    return ok;
+  };
+  float cur[16], nxt[16];
+  bool okc = load_tap(0, cur);
 #pragma unroll
-      for (int kc = 0; kc < 2; ++kc) {
-        bf16x8 B;
+  for (int t = 0; t < 27; ++t) {
+    bool okn = false;
+    if (t + 1 < 27) okn = load_tap(t + 1, nxt);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) B[i] = (__bf16)(ok ? src[(16 * kc + i) * vo + off] : 0.0f);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pkT[((3 * tr + kx) * 2 + kc) * 64 + lane], B,
-                                                       acc, 0, 0, 0);
-      }
+    for (int kc = 0; kc < 2; ++kc) {
+      bf16x8 B;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) B[i] = (__bf16)(okc ? cur[8 * kc + i] : 0.0f);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pkT[(t * 2 + kc) * 64 + lane], B, acc, 0, 0, 0);
+    }
+    if (t + 1 < 27) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
+      okc = okn;
     }
   }
   if (!valid) return;
@@ -921,7 +948,8 @@ long long gnet_train_part_floats(int nb, int S) {
   return (long long)nb * nzc * TRAIN_PART;
 }
 
-long long gnet_train_wpart_floats() { return (long long)BWD_W_GROUPS * 28; }
+// at most BWD_W_GROUPS / (CI CO / G) chunks of CI CO partials of 28 floats, G <= 4
+long long gnet_train_wpart_floats() { return (long long)BWD_W_GROUPS * 4 * 28; }
 
 void gnet_backward_batch(const float* params, const float* in, int nb, int S, const float* a1,
                          const float* a2, const float* d3, float* d2, float* d1, float* grad,
