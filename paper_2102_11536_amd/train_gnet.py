@@ -16,6 +16,9 @@ per stage (``stage0``, ``stage1``, ...) and the run's settings (``meta``, JSON).
 
     python -m paper_2102_11536_amd.train_gnet --n 128 --p 3 --k 2 \
         --trajectories 500 --steps 16 --out paper_2102_11536_amd/weights/gnet_p3_n128_k2.npz
+
+``--time-gradient N`` only times the loss gradient of one training batch in BF16 and in
+FP32 training.
 """
 import argparse
 import json
@@ -70,6 +73,33 @@ def evaluate(pt, k, rho, tau, rtol, mode, nets, nsteps, seed):
             "mean_iters": float(its.mean())}
 
 
+def time_gradient(m, S, nb, reps, seed):
+    """Mean time of ga_gnet_loss_grad on nb random crops of S^3 on an m^3 grid (inputs
+    and targets standard normal, random parameters), in BF16 and in FP32 training."""
+    dev = "cuda:0"
+    rng = np.random.default_rng(seed)
+    T = S - 6
+    grid = (m, m, m)
+    org = [tuple(int(rng.integers(-3, m - T - 3 + 1)) for _ in range(3)) for _ in range(nb)]
+    inp = torch.as_tensor(rng.standard_normal(nb * 4 * S ** 3), dtype=torch.float32, device=dev)
+    tgt = torch.as_tensor(rng.standard_normal(nb * T ** 3), dtype=torch.float32, device=dev)
+    grad = torch.zeros(ga.GA_GNET_NPARAM, dtype=torch.float32, device=dev)
+    out = dict(grid=m, crop=S, batch=nb, reps=reps)
+    for name, prec in (("bf16", ga.GA_BF16), ("fp32", ga.GA_FP32)):
+        net = ga.GNet(workloads.gnet_random_params(seed))
+        ga.ga_gnet_set_train_prec(net, prec)
+        for _ in range(2):
+            ga.ga_gnet_loss_grad(net, grid, org, S, inp, tgt, grad, want_loss=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ga.ga_gnet_loss_grad(net, grid, org, S, inp, tgt, grad, want_loss=False)
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+        log(f"[train] gradient {name}: {out[f'{name}_ms']:.3f} ms")
+    print(json.dumps(out), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--n", type=int, default=128)
@@ -88,12 +118,18 @@ def main(argv=None):
     ap.add_argument("--prec", choices=("bf16", "fp32"), default="bf16",
                     help="training arithmetic: layer 2 on BF16 matrix cores, or FP32 throughout")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--time-gradient", type=int, default=0, metavar="N",
+                    help="only time N loss gradients of one batch of random crops on the grid of "
+                         "free coefficients, in BF16 and in FP32, print one JSON line and exit")
     args = ap.parse_args(argv)
     assert torch.cuda.is_available(), "training runs on the GPU"
     dev = "cuda:0"
     torch.cuda.set_device(0)
     ga.load_library()
     n, p, k = args.n, args.p, args.k
+    if args.time_gradient > 0:
+        time_gradient(n + p - 2, args.crop, args.batch, args.time_gradient, args.seed)
+        return
     pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
     lam = ga.ga_lambda_max(pt, 25)
     tau = 0.5 * math.sqrt(ga.ga_stability_limit(args.rho) / lam)
