@@ -698,9 +698,11 @@ __device__ __forceinline__ void stage_act_brick(const uint4* __restrict__ src, D
     const int e = tid + k * 256, n = e >> 2, c = e & 3;
     const int hx = n % HX, hy = (n / HX) % HY, hz = n / (HX * HY);
     const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
-    v[k] = make_uint4(0u, 0u, 0u, 0u);
-    if (e < HP * 4 && inside(x, y, z, g))
-      v[k] = src[(x + (long long)g.x * (y + (long long)g.y * z)) * 4 + c];
+    // points outside the grid load chunk c of point 0 (in bounds) without a branch; the
+    // select zeroes them
+    const bool in = e < HP * 4 && inside(x, y, z, g);
+    const uint4 raw = src[(in ? x + (long long)g.x * (y + (long long)g.y * z) : 0) * 4 + c];
+    v[k] = in ? raw : make_uint4(0u, 0u, 0u, 0u);
   }
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
@@ -734,8 +736,13 @@ conv1_mfma_k(GnetFields f, Dims g, const double* __restrict__ sq, const bf16x8* 
     const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
     const bool in = n < HP && inside(x, y, z, g);
     const long long p = in ? x + (long long)g.x * (y + (long long)g.y * z) : 0;
+    // points outside the grid load point 0 (in bounds) without a branch; the select
+    // zeroes them
 #pragma unroll
-    for (int c = 0; c < 4; ++c) hv[k][c] = in ? f.h[c][p] : 0.0;
+    for (int c = 0; c < 4; ++c) {
+      const double h = f.h[c][p];
+      hv[k][c] = in ? h : 0.0;
+    }
   }
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
@@ -891,13 +898,20 @@ layer3_gather_k(const __bf16* __restrict__ u, GnetFields f, Dims g, const double
     const int ox = (int)(io - row * gx), oy = (int)(row % gy), oz = (int)(row / gy);
     const bool in[3][3] = {{ox > 0, true, ox + 1 < g.x}, {oy > 0, true, oy + 1 < g.y},
                            {oz > 0, true, oz + 1 < g.z}};
-    float acc = bias[0];
+    // a tap outside the grid reads the point itself (in bounds) and is zeroed by the
+    // select, so all 27 loads are issued without a branch
+    float tap[27];
 #pragma unroll
     for (int t = 0; t < 27; ++t) {
       const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
-      if (!(in[0][dx] && in[1][dy] && in[2][dz])) continue;
-      acc += (float)u[t * v + o + (dx - 1) + (dy - 1) * sy + (dz - 1) * sz];
+      const bool ok = in[0][dx] && in[1][dy] && in[2][dz];
+      const long long off = ok ? (dx - 1) + (dy - 1) * sy + (dz - 1) * sz : 0;
+      const float w = (float)u[t * v + o + off];
+      tap[t] = ok ? w : 0.0f;
     }
+    float acc = bias[0];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc += tap[t];
     const double e = 4.0 * f.h[0][o] - 6.0 * f.h[1][o] + 4.0 * f.h[2][o] - f.h[3][o];
     X[o] = e + s3 * (double)acc;
   }
