@@ -134,8 +134,12 @@ def test_forward_matches_oracle(n, p, prec):
 # the exact oracle: each rounded product is off by up to 2u = 2^-7; the W1 block,
 # a sum with strong cancellation fed by the rounded backward-data pass, moves most
 # (measured 3e-2), so the bars are 4u for the whole gradient and 16u per block.
+# The third case's crops hold 17 planes of 17^2 layer-2 outputs (row blocks of 4 with a
+# ragged fifth); the fourth has 147 crops of 7 planes (1029 in all), so a workgroup of
+# the BF16 backward-weight pass sums two planes and the last one of a crop alone.
 @pytest.mark.parametrize("prec", [ga.GA_FP32, ga.GA_BF16])
-@pytest.mark.parametrize("n,p,S,nb", [(n, p, 10, 3) for n, p in PATCHES] + [((20, 18, 17), 2, 21, 2)])
+@pytest.mark.parametrize("n,p,S,nb", [(n, p, 10, 3) for n, p in PATCHES]
+                         + [((20, 18, 17), 2, 21, 2), (PATCHES[0][0], PATCHES[0][1], 11, 147)])
 def test_loss_grad_matches_oracle(n, p, S, nb, prec):
     _say("loss_grad", n, p, S, nb, prec)
     pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
