@@ -194,7 +194,9 @@ def test_adam_matches_oracle():
     assert np.max(np.abs(got - p)) <= 2e-6
 
 
-INFER = [((9, 8, 7), 3), ((20, 13, 9), 3), ((16, 6, 7), 2)]
+# free grids 10x9x8, 21x14x10, 16x6x7 and 10x11x6: the last 16x8x4 tile along y holds 1,
+# 3, 3 and 2 groups of two rows, and along z 4, 2, 3 and 2 planes
+INFER = [((9, 8, 7), 3), ((20, 13, 9), 3), ((16, 6, 7), 2), ((10, 11, 6), 2)]
 
 
 @pytest.mark.parametrize("n,p", INFER)
