@@ -9,10 +9,13 @@
 // Scaling every channel by its own RMS keeps inputs and target of order one,
 // although the differences are orders of magnitude below the fields.
 //
-// Training (FP32, on crops):  forward / backward-data / backward-weight / MSE / Adam.
-//   Crops are channel-major [b][c][S^3]; the convolutions are "valid" and the
-//   activations of layers 1 and 2 at positions outside the grid are forced to zero,
-//   which makes a crop reproduce the whole-grid net on its interior.
+// Training (on crops):  forward / backward-data / backward-weight / MSE / Adam, with
+//   FP32 master weights, activations and gradients.  Crops are channel-major
+//   [b][c][S^3]; the convolutions are "valid" and the activations of layers 1 and 2 at
+//   positions outside the grid are forced to zero, which makes a crop reproduce the
+//   whole-grid net on its interior.  Layer 2's three passes run either in FP32 on the
+//   vector units or on MFMA 32x32x16 with BF16 operands and FP32 accumulation; layers
+//   1 and 3 run in FP32.
 // Inference (whole grid; BF16 inputs, weights and activations; FP32 accumulation),
 // three kernels over the same tiles, each staging its input brick in LDS:
 //   layer 1 forms the four channels from the FP64 history into the brick and runs
