@@ -686,6 +686,14 @@ def main():
         ga.ga_profile(False)
         side[pname] = (m_ms / max(m_cnt, 1) * 1e-3, p_ms / max(p_cnt, 1) * 1e-3)
     del xs, ys
+    # one loss gradient of the nets' training batch (its crop and batch size) on this
+    # grid, BF16 and FP32 training, outside the timed region
+    if nets and isinstance(learned_note, dict):
+        from paper_2102_11536_amd.train_gnet import time_gradient
+        tg = time_gradient(pt.mf[0], meta["crop"], meta["batch"], 10, 0)
+        learned_note["training_gradient_ms"] = {"bf16": tg["bf16_ms"], "fp32": tg["fp32_ms"],
+                                                "crop": tg["crop"], "batch": tg["batch"]}
+        log(f"[bench] training gradient: BF16 {tg['bf16_ms']:.3f} ms, FP32 {tg['fp32_ms']:.3f} ms")
     # algorithmic bytes per launch: the stiffness apply on k right-hand sides reads the
     # 6 factors of G per Gauss point and each input vector once and writes each output
     # once; the mass apply the same with the one factor W; the preconditioner's three

@@ -75,7 +75,8 @@ def evaluate(pt, k, rho, tau, rtol, mode, nets, nsteps, seed):
 
 def time_gradient(m, S, nb, reps, seed):
     """Mean time of ga_gnet_loss_grad on nb random crops of S^3 on an m^3 grid (inputs
-    and targets standard normal, random parameters), in BF16 and in FP32 training."""
+    and targets standard normal, random parameters), in BF16 and in FP32 training:
+    {"bf16_ms": .., "fp32_ms": .., ...}."""
     dev = "cuda:0"
     rng = np.random.default_rng(seed)
     T = S - 6
@@ -96,8 +97,7 @@ def time_gradient(m, S, nb, reps, seed):
             ga.ga_gnet_loss_grad(net, grid, org, S, inp, tgt, grad, want_loss=False)
         torch.cuda.synchronize()
         out[f"{name}_ms"] = 1e3 * (time.perf_counter() - t0) / reps
-        log(f"[train] gradient {name}: {out[f'{name}_ms']:.3f} ms")
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main(argv=None):
@@ -128,7 +128,9 @@ def main(argv=None):
     ga.load_library()
     n, p, k = args.n, args.p, args.k
     if args.time_gradient > 0:
-        time_gradient(n + p - 2, args.crop, args.batch, args.time_gradient, args.seed)
+        out = time_gradient(n + p - 2, args.crop, args.batch, args.time_gradient, args.seed)
+        log(f"[train] gradient: BF16 {out['bf16_ms']:.3f} ms, FP32 {out['fp32_ms']:.3f} ms")
+        print(json.dumps(out), flush=True)
         return
     pt = ga.ga_setup_patch(3, n, p, workloads.deformed_cube_ctrl(n, p))
     lam = ga.ga_lambda_max(pt, 25)
