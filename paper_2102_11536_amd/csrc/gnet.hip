@@ -530,32 +530,44 @@ conv2_train_bwd_w_lds_k(const float* __restrict__ a1, const float* __restrict__ 
           if (pi < 2048) {
             const int p = pi & 15, r = (pi >> 4) & 3, co = pi >> 6;
             const int y = y0 + r, x = x0 + 2 * p;
-            float v0 = 0.0f, v1 = 0.0f;
-            if (y < S2) {
-              const float* src = d2b + co * vo + ((long long)oz * S2 + y) * S2 + x;
-              if (x < S2) v0 = src[0];
-              if (x + 1 < S2) v1 = src[1];
-            }
+            // entries outside the output load offset 0 (in bounds) without a branch and are
+            // zeroed by the select, so the loads of all pairs are in flight together
+            const bool ok0 = y < S2 && x < S2, ok1 = y < S2 && x + 1 < S2;
+            const float* src = d2b + co * vo;
+            const long long e = ((long long)oz * S2 + y) * S2 + x;
+            const float l0 = src[ok0 ? e : 0], l1 = src[ok1 ? e + 1 : 0];
+            const float v0 = ok0 ? l0 : 0.0f, v1 = ok1 ? l1 : 0.0f;
             bacc[j] += v0 + v1;
             const __bf16 h[2] = {(__bf16)v0, (__bf16)v1};
             __builtin_memcpy(lb + co * BW_BCH + r * 64 + 4 * p, h, 4);
           }
         }
-        // a1: 10368 pairs (ci, staged row = rr + 6 kz, x pair p), zero outside the crop
-#pragma unroll 6
-        for (int j = 0; j < 54; ++j) {
-          const int pi = tid + 192 * j;
-          const int p = pi % 18, row = (pi / 18) % 18, ci = pi / 324;
-          const int rr = row % 6, kz = row / 6;
-          const int y = y0 + rr, x = x0 + 2 * p;
-          float v0 = 0.0f, v1 = 0.0f;
-          if (y < S1) {
-            const float* src = a1b + ci * vi + ((long long)(oz + kz) * S1 + y) * S1 + x;
-            if (x < S1) v0 = src[0];
-            if (x + 1 < S1) v1 = src[1];
+        // a1: 10368 pairs (ci, staged row = rr + 6 kz, x pair p), zero outside the crop;
+        // 9 batches of 6 pairs per thread, each batch's 12 loads issued before its stores
+#pragma unroll 1
+        for (int j0 = 0; j0 < 54; j0 += 6) {
+          float l0[6], l1[6];
+          bool k0[6], k1[6];
+#pragma unroll
+          for (int jj = 0; jj < 6; ++jj) {
+            const int pi = tid + 192 * (j0 + jj);
+            const int p = pi % 18, row = (pi / 18) % 18, ci = pi / 324;
+            const int rr = row % 6, kz = row / 6;
+            const int y = y0 + rr, x = x0 + 2 * p;
+            k0[jj] = y < S1 && x < S1;
+            k1[jj] = y < S1 && x + 1 < S1;
+            const float* src = a1b + ci * vi;
+            const long long e = ((long long)(oz + kz) * S1 + y) * S1 + x;
+            l0[jj] = src[k0[jj] ? e : 0];
+            l1[jj] = src[k1[jj] ? e + 1 : 0];
           }
-          const __bf16 h[2] = {(__bf16)v0, (__bf16)v1};
-          __builtin_memcpy(la + ci * BW_ACH + row * BW_AROW + 4 * p, h, 4);
+#pragma unroll
+          for (int jj = 0; jj < 6; ++jj) {
+            const int pi = tid + 192 * (j0 + jj);
+            const int p = pi % 18, row = (pi / 18) % 18, ci = pi / 324;
+            const __bf16 h[2] = {(__bf16)(k0[jj] ? l0[jj] : 0.0f), (__bf16)(k1[jj] ? l1[jj] : 0.0f)};
+            __builtin_memcpy(la + ci * BW_ACH + row * BW_AROW + 4 * p, h, 4);
+          }
         }
         __syncthreads();
         // wave w: taps (kx, ky, kz = w); lane supplies A[ci = n32][8 half + i] and
