@@ -287,7 +287,24 @@ __global__ void adam_k(float* __restrict__ p, float* __restrict__ m, float* __re
 __global__ void __launch_bounds__(VB)
 diff_norms_k(GnetFields f, long long n, double* __restrict__ part) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (long long i = (long long)blockIdx.x * VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+  // four points per trip with their 16 loads in flight together, added in point order
+  const long long stride = (long long)gridDim.x * VB;
+  long long i = (long long)blockIdx.x * VB + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double h[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) h[u][c] = f.h[c][i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double d[4];
+      differences(h[u][0], h[u][1], h[u][2], h[u][3], d);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += d[c] * d[c];
+    }
+  }
+  for (; i < n; i += stride) {
     double d[4];
     differences(f.h[0][i], f.h[1][i], f.h[2][i], f.h[3][i], d);
 #pragma unroll

@@ -95,8 +95,21 @@ dotm_k(const TA* __restrict__ a, const TB* __restrict__ b, size_t n, double* __r
   const TA* ar = a + off;
   const TB* br = b + off;
   double s = 0.0;
-  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB)
-    s += (double)ar[i] * (double)br[i];
+  // four points per trip with their loads in flight together, added in point order
+  const size_t stride = (size_t)gridDim.x * VB;
+  size_t i = (size_t)blockIdx.x * VB + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    TA x[4];
+    TB y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = ar[i + u * stride];
+      y[u] = br[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += (double)x[u] * (double)y[u];
+  }
+  for (; i < n; i += stride) s += (double)ar[i] * (double)br[i];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = s;
 }
@@ -110,7 +123,25 @@ dot2_k(const float* __restrict__ r, const float* __restrict__ z, const float* __
   size_t off;
   span(seg, rr, n, off, n);
   double s1 = 0.0, s2 = 0.0;
-  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB) {
+  // four points per trip with their loads in flight together, added in point order
+  const size_t stride = (size_t)gridDim.x * VB;
+  size_t i = (size_t)blockIdx.x * VB + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    float rv[4], zv[4], qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      rv[u] = r[off + i + u * stride];
+      zv[u] = z[off + i + u * stride];
+      qv[u] = q[off + i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double zd = zv[u];
+      s1 += (double)rv[u] * zd;
+      s2 += zd * (double)qv[u];
+    }
+  }
+  for (; i < n; i += stride) {
     const double zv = z[off + i];
     s1 += (double)r[off + i] * zv;
     s2 += zv * (double)q[off + i];

@@ -146,8 +146,21 @@ dot_partial_k(const double* __restrict__ a, const double* __restrict__ b, size_t
   const double* ar = a + (size_t)r * n;
   const double* br = b + (size_t)r * n;
   double s = 0.0;
-  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB)
-    s += ar[i] * br[i];
+  // four points per trip with their loads in flight together; the additions keep the
+  // point order of one point per trip, so the sum is bitwise the same
+  const size_t stride = (size_t)gridDim.x * VB;
+  size_t i = (size_t)blockIdx.x * VB + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = ar[i + u * stride];
+      y[u] = br[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += x[u] * y[u];
+  }
+  for (; i < n; i += stride) s += ar[i] * br[i];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = s;
 }
