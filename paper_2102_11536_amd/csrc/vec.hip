@@ -404,8 +404,20 @@ dot_partial_seg_k(const double* __restrict__ a, const double* __restrict__ b,
   const int r = blockIdx.y;
   const size_t off = (size_t)seg[2 * r], n = (size_t)seg[2 * r + 1];
   double s = 0.0;
-  for (size_t i = (size_t)blockIdx.x * VB + threadIdx.x; i < n; i += (size_t)gridDim.x * VB)
-    s += a[off + i] * b[off + i];
+  // four points per trip with their loads in flight together, added in point order
+  const size_t stride = (size_t)gridDim.x * VB;
+  size_t i = (size_t)blockIdx.x * VB + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = a[off + i + u * stride];
+      y[u] = b[off + i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += x[u] * y[u];
+  }
+  for (; i < n; i += stride) s += a[off + i] * b[off + i];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = s;
 }
